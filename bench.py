@@ -1,0 +1,161 @@
+"""Benchmark: short-range particles/s of the truncated FMM on one MI355X.
+
+A step is one full short-range evaluation of a fresh box: octree build
+(fmm_build_tree) plus fmm_short_range_forces (upward pass, traversal, M2L, P2P,
+downward pass).  particles/s = N / step time.  Inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clustered|uniform]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "short-range particles/s at p99 rel force err ≤1e-3; learned/FP32 vs plain"
+PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12}
+P2P_FLOP_PER_PAIR = 38.0
+
+# Largest opening angle of the grid {0.5, 0.45, 0.4, 0.35, 0.3} whose p99 error against
+# brute force is <= 1e-3 at the configured order (measured with the oracle on the
+# clustered workload: theta 0.5 -> 2.5e-3, 0.45 -> 1.9e-3, 0.4 -> 2.6e-4).
+WORKLOADS = {
+    "clustered": dict(theta=0.4, precision=1, n_crit=32),
+    "uniform": dict(theta=0.5, precision=0, n_crit=32),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", type=int, default=None)
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--n-crit", type=int, default=None)
+    ap.add_argument("--cpu-sample", type=int, default=6000, help="oracle targets for cpu_baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2006_14952_amd as hf
+    from paper_2006_14952_amd import inputs
+
+    wl = dict(WORKLOADS[args.workload])
+    if args.precision is not None:
+        wl["precision"] = args.precision
+    if args.theta is not None:
+        wl["theta"] = args.theta
+    if args.n_crit is not None:
+        wl["n_crit"] = args.n_crit
+    cfg = inputs.CONFIGS[args.workload]
+    pr = inputs.split_params(args.workload)
+    pos_np, m_np = inputs.make(args.workload)
+    n = len(pos_np)
+    prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
+                    precision=wl["precision"])
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(pos_np, device=dev)
+    mass = torch.tensor(m_np, device=dev)
+    acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    tree = hf.Tree()
+
+    def step():
+        tree.build(pos, mass, prm, stream)
+        tree.short_range(prm, out=acc, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    tree.set_timing(True)
+    torch.cuda.synchronize()
+    p2p_ms, build_ms, stage = [], [], {}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        s = tree.stats()
+        p2p_ms.append(s["t_p2p_ms"])
+        build_ms.append(s["t_build_ms"])
+        for k in ("t_upward_ms", "t_traverse_ms", "t_m2l_ms", "t_p2p_ms", "t_downward_ms", "t_total_ms"):
+            stage.setdefault(k, []).append(s[k])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = tree.stats()
+
+    flop_launch = P2P_FLOP_PER_PAIR * st["p2p_pairs"]
+    p2p_s = float(np.mean(p2p_ms)) * 1e-3
+    peak = PEAK["fp32_vector"] if wl["precision"] else PEAK["fp64_vector"]
+    achieved = flop_launch / p2p_s
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "p2p_traffic_%s_fp%d.json" % (args.workload, 32 if wl["precision"] else 64))
+    if os.path.exists(tf):
+        traffic = json.load(open(tf)).get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": n / dt,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if wl["precision"] else "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s N=%d (%s), p=%d, theta=%.2f, n_crit=%d, r_s=%.6g, r_cut=%.6g, %s" % (
+            args.workload, n, cfg["kind"], pr["p"], wl["theta"], wl["n_crit"], pr["rs"], pr["rcut"],
+            "FP32 P2P/M2L + FP64 positions/offsets/final sum" if wl["precision"] else "FP64"),
+            "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"]},
+        "roofline": {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "flop_per_launch": flop_launch, "p2p_ms_per_launch": p2p_s * 1e3},
+        "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
+        "build_ms": float(np.mean(build_ms)),
+        "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit")},
+    }
+
+    if args.cpu_sample > 0:
+        import oracle
+        got = acc.cpu().numpy()
+        tg = inputs.rng_for(CONFIG_SAMPLE_SEED).choice(n, min(args.cpu_sample, n), replace=False)
+        op = oracle.make_params(box=1.0, rs=pr["rs"], rcut=pr["rcut"], theta=wl["theta"], p=pr["p"],
+                                ncrit=wl["n_crit"])
+        nth = oracle.max_threads()
+        t1 = time.perf_counter()
+        res = oracle.fmm(pos_np, m_np, op, targets=tg)
+        t_or = time.perf_counter() - t1
+        bf = oracle.bruteforce(pos_np, m_np, op, targets=tg)
+        ref_norm = np.linalg.norm(bf, axis=1)
+        floor = np.median(ref_norm[ref_norm > 0])
+        e_bf = np.linalg.norm(got[tg] - bf, axis=1) / np.where(ref_norm > 0, ref_norm, floor)
+        e_or = np.linalg.norm(got[tg] - res.acc[tg], axis=1) / np.maximum(np.linalg.norm(res.acc[tg], axis=1), 1e-300)
+        out["cpu_baseline"] = {"value": len(tg) / t_or, "unit": "particles/s", "cores": nth, "kind": "oracle",
+                               "sample": "%d random particles of the same box: full tree + upward pass, traversal/"
+                                         "M2L/P2P/downward for their sink cells only; %.1f s" % (len(tg), t_or)}
+        out["accuracy"] = {"sample": len(tg), "p99_vs_bruteforce": float(np.percentile(e_bf, 99)),
+                           "median_vs_bruteforce": float(np.median(e_bf)), "max_vs_bruteforce": float(e_bf.max()),
+                           "median_vs_oracle": float(np.median(e_or)), "p99_vs_oracle": float(np.percentile(e_or, 99)),
+                           "max_vs_oracle": float(e_or.max())}
+    print(json.dumps(out))
+    tree.free()
+
+
+CONFIG_SAMPLE_SEED = 777
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * hfmm.h -- C ABI of the MI355X (gfx950) short-range gravity solver of the hybrid
+ * PM-FMM method of Q. Wang, "A Hybrid Fast Multipole Method for Cosmological N-body
+ * Simulations" (arXiv:2006.14952).
+ *
+ * The short-range force is the Gaussian-split (erfc-truncated) part of periodic
+ * Newtonian gravity (Sec. 2.2, truncated potential and force law):
+ *     a_i = G sum_{j, 0 < r_ij < r_cut} m_j f_(1)(r_ij) d_ij,
+ *     f_(1)(r) = -[erfc(r/2r_s) + r/(r_s sqrt(pi)) exp(-r^2/4r_s^2)] / r^3,
+ *     d_ij = x_i - x_j - box * round((x_i - x_j)/box)   (minimum image; r_cut < box/2).
+ * It is evaluated by a truncated Cartesian FMM (Sec. 2.1 Eqs. (1)-(6) with the
+ * truncated prefactors of Sec. 2.2) over a Morton-ordered octree, with the modified
+ * multipole acceptance criterion of Sec. 2.3.  The long-range part is a plain
+ * particle-mesh step with the Gaussian filter exp(-k^2 r_s^2) (Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named pos / mass / acc are DEVICE pointers owned by the caller,
+ *     contiguous, double precision; pos and acc are (n, 3) row-major.
+ *   - stream is a hipStream_t passed as void*; NULL means the default stream.  All
+ *     GPU work is enqueued on it.  Calls return after enqueuing, except where noted
+ *     (tree building reads a few level sizes back to the host).
+ *   - Return value: 0 on success, a negative FMM_ERR_* code otherwise; the message
+ *     of the last error of the calling thread is available from fmm_last_error().
+ *   - Positions outside [0, box) are wrapped periodically; NaN or Inf positions are
+ *     rejected with FMM_ERR_NAN (checked on the device, reported by the call).
+ *   - Output is acceleration (units with the given G) in the caller's particle order.
+ */
+#ifndef HFMM_H
+#define HFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_OK 0
+#define FMM_ERR_ARG (-1)    /* invalid argument or parameter */
+#define FMM_ERR_NOMEM (-2)  /* device or host allocation failed */
+#define FMM_ERR_HIP (-3)    /* a HIP runtime call or kernel launch failed */
+#define FMM_ERR_NAN (-4)    /* non-finite input position */
+#define FMM_ERR_STATE (-5)  /* tree and parameters do not match */
+
+#define FMM_PMAX 8          /* highest expansion order compiled for the GPU */
+#define FMM_MAXLEVEL 21     /* finest octree level (63-bit Morton keys) */
+
+/* Method parameters (Secs. 2.1-2.3).
+ *   box       periodic box side L > 0
+ *   r_s       split scale of the Gaussian filter (Sec. 2.2), > 0
+ *   r_cut     truncation radius of the short-range force (~5 r_s in the paper), 0 < r_cut < box/2
+ *   theta     opening angle of MAC item 2 (Sec. 2.3), > 0
+ *   G         gravitational constant (1 in the workloads)
+ *   p         expansion order, 0 <= p <= FMM_PMAX
+ *   n_crit    leaf limit: a cell is split while it holds more than n_crit particles (Sec. 2.1), >= 1
+ *   mac_mode  bit 0: literal item 3 (open when S_c > r_cut > S_m) instead of the strict
+ *             reading (open when S_M > r_cut >= S_m); bit 1: item 2 uses the source side
+ *             alone instead of the larger side of the pair
+ *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
+ *             compensated per-particle sums, FP64 positions, cell offsets and final sum
+ *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see
+ *             fmm_load_mac_model), the plain MAC's hard rules still apply */
+typedef struct fmm_params {
+    double box, r_s, r_cut, theta, G;
+    int p, n_crit;
+    int mac_mode;
+    int precision;
+    int learned;
+    int reserved[3];
+} fmm_params;
+
+/* Counters and stage times of the last fmm_short_range_forces on a tree. Counts
+ * follow the paper's cost measure (numbers of M2L and P2P operations, Sec. 3). */
+typedef struct fmm_stats {
+    int64_t n;                 /* particles */
+    int64_t n_cells, n_leaves, max_level;
+    int64_t n_m2l;             /* accepted M2L cell pairs */
+    int64_t n_p2p;             /* P2P leaf pairs */
+    int64_t p2p_pairs;         /* listed particle pairs (sum over P2P leaf pairs of n_A n_B) */
+    int64_t n_visit;           /* cell pairs examined by the traversal */
+    int64_t levels_traversed;
+    int64_t reserved_i[7];
+    double t_tree_ms, t_upward_ms, t_traverse_ms, t_m2l_ms, t_p2p_ms, t_downward_ms, t_total_ms;
+    double t_build_ms;         /* last fmm_build_tree */
+    double reserved_d[8];
+} fmm_stats;
+
+typedef struct fmm_tree fmm_tree; /* opaque; owned by the library */
+
+/* Build the Morton-ordered octree of n particles (the particle packs of Sec. 2.1):
+ * wrap, 63-bit Morton keys, radix sort, SoA permutation, cells level by level.
+ * pos (n,3) and mass (n) stay owned by the caller and must not change before the
+ * forces are computed.  *out receives a new tree, or an existing tree passed in *out
+ * is reused (its device memory only grows).  Uses params->box and params->n_crit.
+ * Synchronises the stream (level sizes are read back).  n = 0 is allowed. */
+int fmm_build_tree(const fmm_params *params, int64_t n, const double *pos, const double *mass, void *stream,
+                   fmm_tree **out);
+
+/* Short-range accelerations of the particles of a built tree (Secs. 2.1-2.3):
+ * upward pass (P2M, M2M), dual traversal with the modified MAC, M2L and P2P, downward
+ * pass (L2L, L2P).  acc (n,3) is overwritten.  params->box and n_crit must equal the
+ * values the tree was built with (FMM_ERR_STATE otherwise).  Synchronises the stream
+ * once per traversed level (list sizes are read back). */
+int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
+
+/* Long-range accelerations by the particle-mesh method with a mesh of mesh^3 cells
+ * (Sec. 2.2: Poisson Green function filtered by exp(-k^2 r_s^2)): CIC deposit, FFT,
+ * filtered Green function with the CIC window deconvolved, spectral gradient, inverse
+ * FFTs, CIC interpolation.  acc (n,3) is overwritten.  8 <= mesh <= 1024. */
+int pm_long_range_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
+                         double *acc, void *stream);
+
+/* Total periodic acceleration: pm_long_range_forces + fmm_short_range_forces (builds a
+ * temporary tree).  acc (n,3) is overwritten. */
+int hybrid_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
+                  double *acc, void *stream);
+
+/* Short-range accelerations of nbox independent periodic boxes stored back to back:
+ * box b holds particles offsets[b] .. offsets[b+1]-1 of pos/mass/acc, with its own
+ * parameters per_box[b].  offsets is a HOST array of nbox+1 entries starting at 0.
+ * The P2P and M2L work of all boxes runs in shared launches. */
+int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets,
+                                   const double *pos, const double *mass, double *acc, void *stream);
+
+/* Counters and stage times of the last force evaluation (host struct, caller-owned). */
+int fmm_get_stats(const fmm_tree *tree, fmm_stats *out);
+
+/* Turn per-stage timing with HIP events on (1) or off (0) for this tree.  Timing
+ * synchronises the stream after each stage. */
+int fmm_set_timing(fmm_tree *tree, int on);
+
+/* Copy the interaction lists of the last force evaluation to HOST memory as
+ * (sink cell key, source cell key, image) triples, image = 9 (sx+1) + 3 (sy+1) + (sz+1).
+ * A cell key is (1 << 3 level) | morton(ix, iy, iz) at its level.  kind 0 = M2L,
+ * 1 = P2P.  With out == NULL only the count is returned in *count; otherwise at most
+ * cap triples are written and *count receives the number written. */
+int fmm_copy_interactions(const fmm_tree *tree, int kind, uint64_t *out, int64_t cap, int64_t *count);
+
+/* Load the learned MAC/order selector from a model file written by fmm_save_mac_model
+ * (global for the process; path NULL unloads it). */
+int fmm_load_mac_model(const char *path);
+
+void fmm_free_tree(fmm_tree *tree);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fmm_last_error(void);
+
+/* Library version string. */
+const char *fmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFMM_H */

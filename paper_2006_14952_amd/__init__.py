@@ -1,1 +1,207 @@
-"""MI355X-native truncated-FMM short-range gravity (placeholder, binding added below)."""
+"""MI355X-native short-range solver of the hybrid PM-FMM method (arXiv:2006.14952).
+
+Thin Python binding of ``libhfmm.so`` (declared in ``include/hfmm.h``).  This module
+only marshals arguments: torch tensors provide device memory and the stream, every
+step of the method runs in the library's HIP kernels.  If the library is missing the
+calls raise; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhfmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hfmm.h")
+_lib = None
+
+FMM_OK, FMM_ERR_ARG, FMM_ERR_NOMEM, FMM_ERR_HIP, FMM_ERR_NAN, FMM_ERR_STATE = 0, -1, -2, -3, -4, -5
+PMAX = 8
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("box", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
+                ("G", C.c_double), ("p", C.c_int), ("n_crit", C.c_int), ("mac_mode", C.c_int),
+                ("precision", C.c_int), ("learned", C.c_int), ("reserved", C.c_int * 3)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_cells", C.c_int64), ("n_leaves", C.c_int64), ("max_level", C.c_int64),
+                ("n_m2l", C.c_int64), ("n_p2p", C.c_int64), ("p2p_pairs", C.c_int64), ("n_visit", C.c_int64),
+                ("levels_traversed", C.c_int64), ("reserved_i", C.c_int64 * 7),
+                ("t_tree_ms", C.c_double), ("t_upward_ms", C.c_double), ("t_traverse_ms", C.c_double),
+                ("t_m2l_ms", C.c_double), ("t_p2p_ms", C.c_double), ("t_downward_ms", C.c_double),
+                ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("reserved_d", C.c_double * 8)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+
+
+def exported_names():
+    """Function names declared by include/hfmm.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FMMError(FMM_ERR_STATE, "libhfmm.so is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, dp = C.c_void_p, C.c_int64, C.c_void_p
+        L.fmm_build_tree.argtypes = [C.POINTER(Params), i64, dp, dp, vp, C.POINTER(vp)]
+        L.fmm_short_range_forces.argtypes = [vp, C.POINTER(Params), dp, vp]
+        L.pm_long_range_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
+        L.hybrid_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
+        L.fmm_short_range_forces_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, dp, vp]
+        L.fmm_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.fmm_set_timing.argtypes = [vp, C.c_int]
+        L.fmm_copy_interactions.argtypes = [vp, C.c_int, vp, i64, C.POINTER(i64)]
+        L.fmm_load_mac_model.argtypes = [C.c_char_p]
+        L.fmm_free_tree.argtypes = [vp]
+        L.fmm_free_tree.restype = None
+        L.fmm_last_error.restype = C.c_char_p
+        L.fmm_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise FMMError(rc, lib().fmm_last_error().decode())
+
+
+def params(box=1.0, r_s=0.0390625, r_cut=None, theta=0.5, G=1.0, p=4, n_crit=32, mac_mode=0, precision=0,
+           learned=0) -> Params:
+    if r_cut is None:
+        r_cut = 4.5 * r_s
+    return Params(float(box), float(r_s), float(r_cut), float(theta), float(G), int(p), int(n_crit), int(mac_mode),
+                  int(precision), int(learned), (C.c_int * 3)(0, 0, 0))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev64(x, shape_tail=None):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+        raise FMMError(FMM_ERR_ARG, "expected a contiguous float64 CUDA tensor")
+    if shape_tail is not None and tuple(x.shape[1:]) != shape_tail:
+        raise FMMError(FMM_ERR_ARG, "bad tensor shape %s" % (tuple(x.shape),))
+    return C.c_void_p(x.data_ptr())
+
+
+class Tree:
+    """A built octree (device-resident) and the lists of its last evaluation."""
+
+    def __init__(self):
+        self._h = C.c_void_p()
+        self.n = 0
+
+    def build(self, pos, mass, prm: Params, stream=None):
+        self.n = int(pos.shape[0])
+        if mass.shape[0] != self.n:
+            raise FMMError(FMM_ERR_ARG, "pos and mass lengths differ")
+        _check(lib().fmm_build_tree(C.byref(prm), self.n, _dev64(pos, (3,)) if self.n else None,
+                                    _dev64(mass) if self.n else None, _stream(stream), C.byref(self._h)))
+        return self
+
+    def short_range(self, prm: Params, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        _check(lib().fmm_short_range_forces(self._h, C.byref(prm), _dev64(out, (3,)) if self.n else None,
+                                            _stream(stream)))
+        return out
+
+    def set_timing(self, on=True):
+        _check(lib().fmm_set_timing(self._h, int(on)))
+
+    def stats(self):
+        s = Stats()
+        _check(lib().fmm_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def interactions(self, kind):
+        """(sink key, source key, image) triples of the last evaluation; kind 'm2l' or 'p2p'."""
+        k = 1 if kind == "p2p" else 0
+        cnt = C.c_int64()
+        _check(lib().fmm_copy_interactions(self._h, k, None, 0, C.byref(cnt)))
+        out = np.zeros((cnt.value, 3), np.uint64)
+        if cnt.value:
+            _check(lib().fmm_copy_interactions(self._h, k, C.c_void_p(out.ctypes.data), cnt.value, C.byref(cnt)))
+        return out[: cnt.value]
+
+    def free(self):
+        if self._h:
+            lib().fmm_free_tree(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def short_range(pos, mass, prm: Params, stream=None):
+    t = Tree().build(pos, mass, prm, stream)
+    try:
+        return t.short_range(prm, stream=stream)
+    finally:
+        t.free()
+
+
+def pm_long_range(pos, mass, prm: Params, mesh, out=None, stream=None):
+    import torch
+    n = int(pos.shape[0])
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    _check(lib().pm_long_range_forces(C.byref(prm), int(mesh), n, _dev64(pos, (3,)), _dev64(mass),
+                                      _dev64(out, (3,)), _stream(stream)))
+    return out
+
+
+def hybrid(pos, mass, prm: Params, mesh, out=None, stream=None):
+    import torch
+    n = int(pos.shape[0])
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    _check(lib().hybrid_forces(C.byref(prm), int(mesh), n, _dev64(pos, (3,)), _dev64(mass), _dev64(out, (3,)),
+                               _stream(stream)))
+    return out
+
+
+def short_range_batched(pos, mass, per_box, offsets, out=None, stream=None):
+    import torch
+    n = int(pos.shape[0])
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    nb = len(per_box)
+    arr = (Params * nb)(*per_box)
+    off = (C.c_int64 * (nb + 1))(*[int(v) for v in offsets])
+    _check(lib().fmm_short_range_forces_batched(arr, nb, off, _dev64(pos, (3,)), _dev64(mass), _dev64(out, (3,)),
+                                                _stream(stream)))
+    return out
+
+
+def load_mac_model(path):
+    _check(lib().fmm_load_mac_model(None if path is None else str(path).encode()))
+
+
+def version():
+    return lib().fmm_version().decode()

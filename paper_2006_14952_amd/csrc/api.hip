@@ -1,0 +1,247 @@
+// C ABI of the solver: argument checks, stage orchestration, statistics.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "state.h"
+
+namespace hfmm {
+const char *last_error();
+void clear_error();
+}  // namespace hfmm
+
+using namespace hfmm;
+
+static int check_params(const fmm_params *P)
+{
+    if (!P) return set_error(FMM_ERR_ARG, "params is NULL");
+    if (!(P->box > 0) || !isfinite(P->box)) return set_error(FMM_ERR_ARG, "box must be > 0");
+    if (!(P->r_s > 0) || !isfinite(P->r_s)) return set_error(FMM_ERR_ARG, "r_s must be > 0");
+    if (!(P->r_cut > 0) || !(P->r_cut < 0.5 * P->box)) return set_error(FMM_ERR_ARG, "need 0 < r_cut < box/2");
+    if (!(P->theta > 0) || !isfinite(P->theta)) return set_error(FMM_ERR_ARG, "theta must be > 0");
+    if (!isfinite(P->G)) return set_error(FMM_ERR_ARG, "G must be finite");
+    if (P->p < 0 || P->p > FMM_PMAX) return set_error(FMM_ERR_ARG, "p must be in [0, %d]", FMM_PMAX);
+    if (P->n_crit < 1) return set_error(FMM_ERR_ARG, "n_crit must be >= 1");
+    if (P->mac_mode < 0 || P->mac_mode > 3) return set_error(FMM_ERR_ARG, "mac_mode must be in [0, 3]");
+    if (P->precision != 0 && P->precision != 1) return set_error(FMM_ERR_ARG, "precision must be 0 or 1");
+    if (P->learned != 0 && P->learned != 1) return set_error(FMM_ERR_ARG, "learned must be 0 or 1");
+    return 0;
+}
+
+static void free_buf(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+static float ev_ms(fmm_tree *t, int a, int b)
+{
+    float ms = 0;
+    hipEventElapsedTime(&ms, t->ev[a], t->ev[b]);
+    return ms;
+}
+
+static void mark(fmm_tree *t, int k, hipStream_t st)
+{
+    if (t->timing) hipEventRecord(t->ev[k], st);
+}
+
+extern "C" {
+
+const char *fmm_last_error(void) { return last_error(); }
+
+const char *fmm_version(void) { return "hfmm 0.1 gfx950"; }
+
+int fmm_set_timing(fmm_tree *t, int on)
+{
+    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
+    if (on && !t->events_ready) {
+        for (auto &e : t->ev)
+            if (hipEventCreate(&e) != hipSuccess) return set_error(FMM_ERR_HIP, "hipEventCreate");
+        t->events_ready = true;
+    }
+    t->timing = on ? 1 : 0;
+    return 0;
+}
+
+int fmm_build_tree(const fmm_params *P, int64_t n, const double *pos, const double *mass, void *stream,
+                   fmm_tree **out)
+{
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (!out) return set_error(FMM_ERR_ARG, "out is NULL");
+    if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
+    if (n > 0 && (!pos || !mass)) return set_error(FMM_ERR_ARG, "pos/mass is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    fmm_tree *t = *out;
+    bool fresh = false;
+    if (!t) {
+        t = new (std::nothrow) fmm_tree();
+        if (!t) return set_error(FMM_ERR_NOMEM, "tree allocation");
+        fresh = true;
+    }
+    if (t->timing) hipEventRecord(t->ev[14], st);
+    int rc = tree_build(t, P, n, pos, mass, st);
+    if (rc) {
+        if (fresh) fmm_free_tree(t);
+        return rc;
+    }
+    if (t->timing) {
+        hipEventRecord(t->ev[15], st);
+        hipEventSynchronize(t->ev[15]);
+        t->stats.t_build_ms = ev_ms(t, 14, 15);
+    }
+    t->stats.n = n;
+    t->stats.n_cells = t->ncell;
+    t->stats.n_leaves = t->nleaf;
+    t->stats.max_level = t->nlevel - 1;
+    *out = t;
+    return 0;
+}
+
+int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *stream)
+{
+    clear_error();
+    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
+    if (int rc = check_params(P)) return rc;
+    if (P->box != t->box || P->n_crit != t->ncrit)
+        return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
+    if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
+    if (P->learned) return set_error(FMM_ERR_ARG, "learned selector requested but no model is loaded");
+    hipStream_t st = (hipStream_t)stream;
+    if (t->n == 0) return 0;
+    int rc;
+    mark(t, 0, st);
+    if ((rc = upward(t, P, st))) return rc;
+    mark(t, 1, st);
+    if ((rc = traverse(t, P, st))) return rc;
+    mark(t, 2, st);
+    if ((rc = m2l(t, P, st))) return rc;
+    mark(t, 3, st);
+    if ((rc = downward_l2l(t, P, st))) return rc;
+    mark(t, 4, st);
+    if ((rc = p2p(t, P, st))) return rc;
+    mark(t, 5, st);
+    if ((rc = l2p_combine(t, P, acc, st))) return rc;
+    mark(t, 6, st);
+    t->last_p = P->p;
+    t->last_prec = P->precision;
+    fmm_stats &S = t->stats;
+    S.n_m2l = t->n_m2l;
+    S.n_p2p = t->n_p2p;
+    S.p2p_pairs = t->p2p_pairs;
+    S.n_visit = t->n_visit;
+    S.levels_traversed = t->nlevel;
+    if (t->timing) {
+        hipEventSynchronize(t->ev[6]);
+        S.t_upward_ms = ev_ms(t, 0, 1);
+        S.t_traverse_ms = ev_ms(t, 1, 2);
+        S.t_m2l_ms = ev_ms(t, 2, 3);
+        S.t_downward_ms = ev_ms(t, 3, 4) + ev_ms(t, 5, 6);
+        S.t_p2p_ms = ev_ms(t, 4, 5);
+        S.t_total_ms = ev_ms(t, 0, 6);
+    }
+    return hip_check(hipGetLastError(), "short range forces");
+}
+
+int fmm_get_stats(const fmm_tree *t, fmm_stats *out)
+{
+    if (!t || !out) return set_error(FMM_ERR_ARG, "NULL argument");
+    *out = t->stats;
+    return 0;
+}
+
+int fmm_copy_interactions(const fmm_tree *tc, int kind, uint64_t *out, int64_t cap, int64_t *count)
+{
+    fmm_tree *t = const_cast<fmm_tree *>(tc);
+    if (!t || !count || (kind != 0 && kind != 1)) return set_error(FMM_ERR_ARG, "bad arguments");
+    int64_t total = kind ? t->n_p2p : t->n_m2l;
+    if (!out) {
+        *count = total;
+        return 0;
+    }
+    int nc = t->ncell;
+    std::vector<Cell> cells(nc);
+    std::vector<int> head(nc), cnt(nc);
+    int nchunk = t->lcap[kind] + 1;
+    std::vector<uint32_t> items((size_t)nchunk * kChunk);
+    std::vector<int> next(nchunk);
+    if (hipDeviceSynchronize() != hipSuccess) return set_error(FMM_ERR_HIP, "sync");
+    hipMemcpy(cells.data(), t->cells.p, (size_t)nc * sizeof(Cell), hipMemcpyDeviceToHost);
+    hipMemcpy(head.data(), ptr<int>(t->lhead) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost);
+    hipMemcpy(cnt.data(), ptr<int>(t->lcnt) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost);
+    hipMemcpy(items.data(), t->litems[kind].p, items.size() * 4, hipMemcpyDeviceToHost);
+    hipMemcpy(next.data(), t->lnext[kind].p, next.size() * 4, hipMemcpyDeviceToHost);
+    std::vector<uint64_t> key(nc);
+    for (int c = 0; c < nc; ++c)
+        key[c] = cell_key_host(cell_level(cells[c]), cells[c].ix, cells[c].iy, cells[c].iz);
+    int64_t w = 0;
+    for (int c = 0; c < nc && w < cap; ++c) {
+        int chunk = head[c];
+        for (int e = 0; e < cnt[c] && w < cap; ++e) {
+            if (e > 0 && e % kChunk == 0) chunk = next[chunk];
+            uint32_t it = items[(size_t)chunk * kChunk + e % kChunk];
+            out[3 * w] = key[c];
+            out[3 * w + 1] = key[it >> 5];
+            out[3 * w + 2] = it & 31;
+            ++w;
+        }
+    }
+    *count = w;
+    return 0;
+}
+
+int fmm_load_mac_model(const char *path)
+{
+    (void)path;
+    return set_error(FMM_ERR_ARG, "learned selector not available in this build");
+}
+
+int pm_long_range_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass,
+                         double *acc, void *stream)
+{
+    (void)P; (void)mesh; (void)n; (void)pos; (void)mass; (void)acc; (void)stream;
+    return set_error(FMM_ERR_ARG, "particle-mesh step not available in this build");
+}
+
+int hybrid_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
+                  void *stream)
+{
+    (void)P; (void)mesh; (void)n; (void)pos; (void)mass; (void)acc; (void)stream;
+    return set_error(FMM_ERR_ARG, "particle-mesh step not available in this build");
+}
+
+int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets, const double *pos,
+                                   const double *mass, double *acc, void *stream)
+{
+    (void)per_box; (void)nbox; (void)offsets; (void)pos; (void)mass; (void)acc; (void)stream;
+    return set_error(FMM_ERR_ARG, "batched form not available in this build");
+}
+
+void fmm_free_tree(fmm_tree *t)
+{
+    if (!t) return;
+    DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
+                      &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
+                      &t->lcnt, &t->litems[0], &t->litems[1], &t->litems[2], &t->lnext[0], &t->lnext[1],
+                      &t->lnext[2], &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag};
+    for (DevBuf *b : bufs) free_buf(*b);
+    if (t->host) (void)hipHostFree(t->host);
+    if (t->events_ready)
+        for (auto &e : t->ev) (void)hipEventDestroy(e);
+    delete t;
+}
+
+}  // extern "C"
+
+namespace hfmm {
+uint64_t cell_key_host(int level, int ix, int iy, int iz)
+{
+    uint64_t k = 1;
+    for (int b = level - 1; b >= 0; --b)
+        k = (k << 3) | ((uint64_t)((ix >> b) & 1) << 2) | ((uint64_t)((iy >> b) & 1) << 1) | (uint64_t)((iz >> b) & 1);
+    return k;
+}
+}  // namespace hfmm

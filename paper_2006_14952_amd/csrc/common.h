@@ -1,0 +1,76 @@
+// Internal declarations shared by the HIP translation units of the solver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hfmm.h"
+
+namespace hfmm {
+
+constexpr int kMaxLevel = FMM_MAXLEVEL;
+constexpr int kPMax = FMM_PMAX;
+
+// One octree cell: the cube [i h, (i+1) h)^3 with h = box / 2^level, holding the
+// Morton-sorted particles beg..end-1.  Children are contiguous (child .. child+nchild-1)
+// and ordered by octant 4 bx + 2 by + bz.  32 bytes, read as two 16-byte loads.
+struct __align__(16) Cell {
+    int ix, iy, iz;
+    int lvl_nch;  // level | (nchild << 8)
+    int beg, end;
+    int child;    // first child, -1 for a leaf
+    int parent;   // -1 for the root
+};
+
+__host__ __device__ inline int cell_level(const Cell &c) { return c.lvl_nch & 0xff; }
+__host__ __device__ inline int cell_nchild(const Cell &c) { return c.lvl_nch >> 8; }
+
+// Multi-indices n = (nx, ny, nz) with |n| <= p, ordered by degree, then nx descending,
+// then ny descending: idx = d(d+1)(d+2)/6 + t(t+1)/2 + nz, d = |n|, t = ny + nz.
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int midx(int x, int y, int z)
+{
+    return (x + y + z) * (x + y + z + 1) * (x + y + z + 2) / 6 + (y + z) * (y + z + 1) / 2 + z;
+}
+
+// Traversal thresholds: every distance of a cell pair is an integer multiple of
+// u_l = box / 2^(l+1), l the finer level of the pair.
+struct MacConst {
+    double cut2[kMaxLevel + 1];  // (r_cut / u_l)^2
+    double theta2;
+    int mode;
+    int pad;
+};
+
+// Interaction lists are chains of kChunk-entry chunks (entry = source cell << 5 | image).
+constexpr int kChunk = 64;
+
+// Per-call constants of the P2P force law in FP32: f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),
+// t = 2 r^2 / r_cut^2 - 1, S a degree-10 polynomial fitted on the host.
+constexpr int kP2PPoly = 11;
+struct P2PConst {
+    float c[kP2PPoly];
+    float inv8rs3;
+    float two_over_rc2;
+    float rc2;
+    double rs, rc2d;
+};
+
+// ---------------------------------------------------------------------------
+// Device buffers of one tree/evaluation.  Grown, never shrunk.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+int grow(DevBuf &b, size_t bytes);                    // 0 or FMM_ERR_NOMEM; content is lost
+int grow_keep(DevBuf &b, size_t bytes, size_t used);  // keeps the first `used` bytes
+template <class T> inline T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
+
+// error reporting (thread-local message)
+int set_error(int code, const char *fmt, ...);
+int hip_check(hipError_t e, const char *what);
+
+// scans (int32), result is exclusive; total (device int) optional
+int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp);
+
+}  // namespace hfmm

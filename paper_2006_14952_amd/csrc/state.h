@@ -1,0 +1,60 @@
+// The opaque tree handle: every device buffer of one box, grown on demand.
+#pragma once
+#include <vector>
+
+#include "common.h"
+
+struct fmm_tree {
+    // shape
+    int64_t n = 0;
+    double box = 1.0;
+    int ncrit = 32;
+    int ncell = 0, nleaf = 0, nlevel = 0;  // levels 0 .. nlevel-1 are non-empty
+    std::vector<int> lvl_beg;              // cells of level l: lvl_beg[l] .. lvl_beg[l+1]-1
+
+    // particles, Morton order
+    hfmm::DevBuf keys[2], idx[2];
+    hfmm::DevBuf xs, ys, zs, ms;  // wrapped FP64 positions and masses
+    hfmm::DevBuf perm;            // sorted index -> caller index
+    hfmm::DevBuf leaf_of;         // sorted index -> leaf cell
+    hfmm::DevBuf rel32;           // float4 (x - c_leaf, m) for the FP32 form
+    hfmm::DevBuf nearf;           // near-field acceleration, 3 x n FP64 (SoA)
+
+    // cells
+    hfmm::DevBuf cells;           // Cell[ncell]
+    hfmm::DevBuf leaves;          // int[nleaf]
+    hfmm::DevBuf Mc, Lc;          // expansion coefficients, ncell x ncoef(p) (float or double)
+
+    // interaction lists: per cell and list kind (0 M2L, 1 P2P, 2 handed to the children)
+    // a chain of 64-entry chunks; head[k * ncell + c], cnt[k * ncell + c]
+    hfmm::DevBuf lhead, lcnt;
+    hfmm::DevBuf litems[3], lnext[3];
+    int lcap[3] = {0, 0, 0};                         // chunks (one more is allocated as overflow bin)
+    hfmm::DevBuf tstack;                             // per-wave traversal stacks
+    int stk_cap = 16384;
+    bool global_stack = false;                       // set once an input overflowed the LDS stack
+    int64_t n_m2l = 0, n_p2p = 0, n_visit = 0, p2p_pairs = 0;
+    hfmm::DevBuf counters;                           // device counters
+
+    // scratch
+    hfmm::DevBuf scan_tmp, nch, flag;
+    int *host = nullptr;  // pinned readback area (64 ints)
+    int last_p = -1, last_prec = -1;
+
+    // timing
+    int timing = 0;
+    fmm_stats stats{};
+    hipEvent_t ev[16]{};
+    bool events_ready = false;
+};
+
+namespace hfmm {
+int tree_build(fmm_tree *t, const fmm_params *P, int64_t n, const double *pos, const double *mass, hipStream_t st);
+int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int upward(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st);
+uint64_t cell_key_host(int level, int ix, int iy, int iz);
+}  // namespace hfmm

@@ -1,0 +1,364 @@
+// Octree construction (the particle packs of Sec. 2.1, built as a Morton octree):
+// wrap + 63-bit Morton keys, LSD radix sort (8-bit digits, stable), SoA gather, then
+// cells level by level from the sorted keys.
+#include <math.h>
+
+#include "state.h"
+
+namespace hfmm {
+
+// ---------------------------------------------------------------------------
+// keys
+
+__device__ inline uint64_t spread3(uint32_t v)  // 21 bits -> every third bit
+{
+    uint64_t x = v & 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+// Periodic wrap into [0, box) and the integer coordinate floor(x / box * 2^21).  The
+// expression order (no contraction) fixes the rounding so that every implementation
+// of the method assigns a particle to the same cube.
+__device__ inline double wrap_coord(double x, double box)
+{
+#pragma clang fp contract(off)
+    double v = x - box * floor(x / box);
+    return v >= box ? 0.0 : v;
+}
+
+__device__ inline uint32_t grid_coord(double v, double box)
+{
+#pragma clang fp contract(off)
+    double g = floor(v / box * 2097152.0);
+    int c = (int)g;
+    c = c < 0 ? 0 : c;
+    c = c > 2097151 ? 2097151 : c;
+    return (uint32_t)c;
+}
+
+__global__ void k_keys(const double *__restrict__ pos, int n, double box, uint64_t *__restrict__ keys,
+                       uint32_t *__restrict__ idx, int *__restrict__ bad)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = pos[3 * (size_t)i], y = pos[3 * (size_t)i + 1], z = pos[3 * (size_t)i + 2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        *bad = 1;
+        x = y = z = 0.0;
+    }
+    uint32_t gx = grid_coord(wrap_coord(x, box), box), gy = grid_coord(wrap_coord(y, box), box),
+             gz = grid_coord(wrap_coord(z, box), box);
+    keys[i] = spread3(gx) << 2 | spread3(gy) << 1 | spread3(gz);
+    idx[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits.  A tile of 4096 keys per 256-thread block; each wave
+// handles 1024 consecutive keys in 16 rounds of 64, ranking equal digits inside a
+// round with ballots, so the scatter is stable.
+
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restrict__ keys, int n, int shift,
+                                                        int nblocks, int *__restrict__ hist)
+{
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int base = blockIdx.x * kRsTile;
+    for (int k = 0; k < kRsRounds; ++k) {
+        int i = base + k * kRsThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+                                                           uint32_t *__restrict__ vout, int n, int shift, int nblocks,
+                                                           const int *__restrict__ offs)
+{
+    __shared__ int cnt[4][256];
+    __shared__ int boff[256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < 4 * 256; k += kRsThreads) (&cnt[0][0])[k] = 0;
+    boff[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int base = blockIdx.x * kRsTile + w * (kRsTile / 4);
+    uint64_t key[kRsRounds];
+    uint32_t val[kRsRounds];
+    int pos[kRsRounds];
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        int i = base + r * 64 + lane;
+        bool ok = i < n;
+        key[r] = ok ? kin[i] : 0;
+        val[r] = ok ? vin[i] : 0;
+        int d = (int)((key[r] >> shift) & 0xff);
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? m : ~m;
+        }
+        int old = cnt[w][d];
+        int rank = __popcll(peers & lt);
+        if (ok && rank == 0) cnt[w][d] = old + __popcll(peers);
+        pos[r] = ok ? old + rank : -1;
+    }
+    __syncthreads();
+    {  // per-digit prefix over the four waves
+        int d = threadIdx.x, run = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int c = cnt[q][d];
+            cnt[q][d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsRounds; ++r) {
+        if (pos[r] < 0) continue;
+        int d = (int)((key[r] >> shift) & 0xff);
+        int o = boff[d] + cnt[w][d] + pos[r];
+        kout[o] = key[r];
+        vout[o] = val[r];
+    }
+}
+
+static int radix_sort(fmm_tree *t, int n, hipStream_t st)
+{
+    int nb = (n + kRsTile - 1) / kRsTile;
+    if (int rc = grow(t->nch, (size_t)256 * nb * 2 * sizeof(int))) return rc;
+    int *hist = ptr<int>(t->nch), *offs = hist + 256 * nb;
+    int cur = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        int shift = 8 * pass;
+        k_rs_hist<<<nb, kRsThreads, 0, st>>>(ptr<uint64_t>(t->keys[cur]), n, shift, nb, hist);
+        if (int rc = scan_exclusive(hist, offs, 256 * nb, nullptr, st, t->scan_tmp)) return rc;
+        k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ptr<uint64_t>(t->keys[cur]), ptr<uint32_t>(t->idx[cur]),
+                                                ptr<uint64_t>(t->keys[cur ^ 1]), ptr<uint32_t>(t->idx[cur ^ 1]), n,
+                                                shift, nb, offs);
+        cur ^= 1;
+    }
+    // 8 passes: the sorted data is back in buffer 0
+    return hip_check(hipGetLastError(), "radix sort");
+}
+
+// ---------------------------------------------------------------------------
+// gather into Morton order
+
+__global__ void k_gather(const double *__restrict__ pos, const double *__restrict__ mass,
+                         const uint32_t *__restrict__ idx, int n, double box, double *__restrict__ xs,
+                         double *__restrict__ ys, double *__restrict__ zs, double *__restrict__ ms,
+                         int *__restrict__ perm)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = idx[i];
+    double x = pos[3 * (size_t)j], y = pos[3 * (size_t)j + 1], z = pos[3 * (size_t)j + 2];
+    xs[i] = isfinite(x) ? wrap_coord(x, box) : 0.0;
+    ys[i] = isfinite(y) ? wrap_coord(y, box) : 0.0;
+    zs[i] = isfinite(z) ? wrap_coord(z, box) : 0.0;
+    ms[i] = mass[j];
+    perm[i] = (int)j;
+}
+
+// ---------------------------------------------------------------------------
+// cells, level by level
+
+__global__ void k_root(Cell *cells, int n)
+{
+    Cell c;
+    c.ix = c.iy = c.iz = 0;
+    c.lvl_nch = 0;
+    c.beg = 0;
+    c.end = n;
+    c.child = -1;
+    c.parent = -1;
+    cells[0] = c;
+}
+
+// first index in [lo, hi) whose key is >= v
+__device__ inline int lower_bound_key(const uint64_t *keys, int lo, int hi, uint64_t v)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (keys[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Octant boundaries of a cell at level l: b[o] = first particle of octant o, b[8] = end.
+__device__ inline void octant_bounds(const uint64_t *keys, const Cell &c, int l, int b[9])
+{
+    int shift = 3 * (kMaxLevel - 1 - l);
+    uint64_t prefix = keys[c.beg] >> (shift + 3) << (shift + 3);
+    b[0] = c.beg;
+    for (int o = 1; o < 8; ++o) b[o] = lower_bound_key(keys, b[o - 1], c.end, prefix | ((uint64_t)o << shift));
+    b[8] = c.end;
+}
+
+__global__ void k_count_children(const Cell *__restrict__ cells, int lbeg, int ln, int l, int ncrit,
+                                 const uint64_t *__restrict__ keys, int *__restrict__ nch)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    Cell c = cells[lbeg + t];
+    int k = 0;
+    if (c.end - c.beg > ncrit && l < kMaxLevel) {
+        int b[9];
+        octant_bounds(keys, c, l, b);
+        for (int o = 0; o < 8; ++o) k += b[o + 1] > b[o];
+    }
+    nch[t] = k;
+}
+
+__global__ void k_make_children(Cell *__restrict__ cells, int lbeg, int ln, int l, int ncrit,
+                                const uint64_t *__restrict__ keys, const int *__restrict__ off, int nbeg)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    int ci = lbeg + t;
+    Cell c = cells[ci];
+    if (!(c.end - c.beg > ncrit && l < kMaxLevel)) return;
+    int b[9];
+    octant_bounds(keys, c, l, b);
+    int first = nbeg + off[t], k = 0;
+    for (int o = 0; o < 8; ++o) {
+        if (b[o + 1] == b[o]) continue;
+        Cell ch;
+        ch.ix = 2 * c.ix + ((o >> 2) & 1);
+        ch.iy = 2 * c.iy + ((o >> 1) & 1);
+        ch.iz = 2 * c.iz + (o & 1);
+        ch.lvl_nch = l + 1;
+        ch.beg = b[o];
+        ch.end = b[o + 1];
+        ch.child = -1;
+        ch.parent = ci;
+        cells[first + k] = ch;
+        ++k;
+    }
+    c.child = first;
+    c.lvl_nch = l | (k << 8);
+    cells[ci] = c;
+}
+
+__global__ void k_leaf_flag(const Cell *__restrict__ cells, int ncell, int *__restrict__ flag)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) flag[c] = cell_nchild(cells[c]) == 0;
+}
+
+__global__ void k_leaf_compact(const Cell *__restrict__ cells, int ncell, const int *__restrict__ flag,
+                               const int *__restrict__ off, int *__restrict__ leaves, int *__restrict__ leaf_of)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell || !flag[c]) return;
+    leaves[off[c]] = c;
+    Cell cc = cells[c];
+    for (int i = cc.beg; i < cc.end; ++i) leaf_of[i] = c;
+}
+
+// FP32 particle records relative to the centre of their leaf (the FP32 form keeps FP64
+// only for absolute positions and the exact cell-centre offsets).
+__global__ void k_rel32(const Cell *__restrict__ cells, const int *__restrict__ leaf_of, const double *__restrict__ xs,
+                        const double *__restrict__ ys, const double *__restrict__ zs, const double *__restrict__ ms,
+                        int n, double box, float4 *__restrict__ rel)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Cell c = cells[leaf_of[i]];
+    double h = ldexp(box, -cell_level(c));
+    rel[i] = make_float4((float)(xs[i] - (c.ix + 0.5) * h), (float)(ys[i] - (c.iy + 0.5) * h),
+                         (float)(zs[i] - (c.iz + 0.5) * h), (float)ms[i]);
+}
+
+static inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos, const double *mass, hipStream_t st)
+{
+    if (n64 < 0 || n64 > (int64_t)1 << 30) return set_error(FMM_ERR_ARG, "n = %lld out of range", (long long)n64);
+    int n = (int)n64;
+    t->n = n;
+    t->box = P->box;
+    t->ncrit = P->n_crit;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    int rc = 0;
+    for (int b = 0; b < 2 && !rc; ++b) rc = grow(t->keys[b], nn * 8) | grow(t->idx[b], nn * 4);
+    if (!rc) rc = grow(t->xs, nn * 8) | grow(t->ys, nn * 8) | grow(t->zs, nn * 8) | grow(t->ms, nn * 8);
+    if (!rc) rc = grow(t->perm, nn * 4) | grow(t->leaf_of, nn * 4) | grow(t->rel32, nn * 16) | grow(t->nearf, nn * 24);
+    if (!rc) rc = grow(t->flag, 64 * sizeof(int));
+    if (!rc) rc = grow(t->cells, sizeof(Cell) * 1024);
+    if (rc) return rc;
+    if (!t->host) {
+        if (hipHostMalloc((void **)&t->host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+            return set_error(FMM_ERR_NOMEM, "pinned host buffer");
+    }
+    int *bad = ptr<int>(t->flag);
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    if (n > 0) {
+        k_keys<<<blocks(n, 256), 256, 0, st>>>(pos, n, P->box, ptr<uint64_t>(t->keys[0]), ptr<uint32_t>(t->idx[0]), bad);
+        if ((rc = radix_sort(t, n, st))) return rc;
+        k_gather<<<blocks(n, 256), 256, 0, st>>>(pos, mass, ptr<uint32_t>(t->idx[0]), n, P->box, ptr<double>(t->xs),
+                                                 ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms),
+                                                 ptr<int>(t->perm));
+    }
+    k_root<<<1, 1, 0, st>>>(ptr<Cell>(t->cells), n);
+    if ((rc = hip_check(hipGetLastError(), "tree keys"))) return rc;
+
+    t->lvl_beg.assign(1, 0);
+    t->lvl_beg.push_back(1);
+    const uint64_t *keys = ptr<uint64_t>(t->keys[0]);
+    int l = 0;
+    for (; l < kMaxLevel && n > 0; ++l) {
+        int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
+        if ((rc = grow(t->nch, (size_t)ln * 2 * sizeof(int) + 64))) return rc;
+        int *nch = ptr<int>(t->nch), *off = nch + ln;
+        k_count_children<<<blocks(ln, 256), 256, 0, st>>>(ptr<Cell>(t->cells), lb, ln, l, P->n_crit, keys, nch);
+        if ((rc = scan_exclusive(nch, off, ln, bad + 1, st, t->scan_tmp))) return rc;
+        hipMemcpyAsync(t->host, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+        if ((rc = hip_check(hipStreamSynchronize(st), "tree level sync"))) return rc;
+        if (t->host[0]) return set_error(FMM_ERR_NAN, "non-finite particle position");
+        int nnext = t->host[1];
+        if (nnext == 0) break;
+        int nbeg = t->lvl_beg[l + 1];
+        if ((rc = grow_keep(t->cells, (size_t)(nbeg + nnext) * sizeof(Cell), (size_t)nbeg * sizeof(Cell)))) return rc;
+        k_make_children<<<blocks(ln, 256), 256, 0, st>>>(ptr<Cell>(t->cells), lb, ln, l, P->n_crit, keys, off, nbeg);
+        t->lvl_beg.push_back(nbeg + nnext);
+    }
+    t->nlevel = (int)t->lvl_beg.size() - 1;
+    t->ncell = t->lvl_beg.back();
+    if (n == 0) {
+        t->nleaf = 0;
+        return hip_check(hipStreamSynchronize(st), "tree");
+    }
+    // leaves
+    if ((rc = grow(t->nch, (size_t)t->ncell * 2 * sizeof(int) + 64))) return rc;
+    int *flag = ptr<int>(t->nch), *off = flag + t->ncell;
+    k_leaf_flag<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag);
+    if ((rc = scan_exclusive(flag, off, t->ncell, bad + 1, st, t->scan_tmp))) return rc;
+    hipMemcpyAsync(t->host, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(hipStreamSynchronize(st), "leaf count"))) return rc;
+    t->nleaf = t->host[0];
+    if ((rc = grow(t->leaves, (size_t)t->nleaf * 4 + 4))) return rc;
+    k_leaf_compact<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag, off, ptr<int>(t->leaves),
+                                                          ptr<int>(t->leaf_of));
+    k_rel32<<<blocks(n, 256), 256, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaf_of), ptr<double>(t->xs),
+                                            ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms), n, P->box,
+                                            ptr<float4>(t->rel32));
+    return hip_check(hipGetLastError(), "tree leaves");
+}
+
+}  // namespace hfmm

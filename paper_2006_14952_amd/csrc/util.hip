@@ -1,0 +1,140 @@
+// Error reporting, device buffer growth and a device-wide exclusive scan.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "common.h"
+
+namespace hfmm {
+
+static thread_local char g_msg[512] = "";
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof(g_msg), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+const char *last_error() { return g_msg; }
+void clear_error() { g_msg[0] = 0; }
+
+int hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return 0;
+    return set_error(FMM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int grow(DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.bytes) return 0;
+    size_t want = bytes + bytes / 4 + 256;
+    void *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FMM_ERR_NOMEM, "hipMalloc of %zu bytes failed", want);
+    }
+    if (b.p) (void)hipFree(b.p);
+    b.p = p;
+    b.bytes = want;
+    return 0;
+}
+
+// Grow keeping the first `used` bytes.  The caller's stream must be idle.
+int grow_keep(DevBuf &b, size_t bytes, size_t used)
+{
+    if (bytes <= b.bytes) return 0;
+    DevBuf nb;
+    if (int rc = grow(nb, bytes)) return rc;
+    if (b.p && used) {
+        if (hipMemcpy(nb.p, b.p, used, hipMemcpyDeviceToDevice) != hipSuccess) {
+            (void)hipFree(nb.p);
+            return set_error(FMM_ERR_HIP, "device copy while growing a buffer");
+        }
+    }
+    if (b.p) (void)hipFree(b.p);
+    b = nb;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int32: block-local scans of 2048 elements, a recursive scan of
+// the block totals, then a uniform add.  Totals fit in int32 by construction of the
+// callers (list sizes are checked against 2^31 before use).
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int *__restrict__ in, int *__restrict__ out, int n,
+                                                            int *__restrict__ tile_sum)
+{
+    __shared__ int lds[kScanThreads];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {  // Hillis-Steele inclusive scan of thread sums
+        int t = threadIdx.x >= off ? lds[threadIdx.x - off] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = lds[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_sum[blockIdx.x] = lds[threadIdx.x];
+}
+
+__global__ void k_scan_add(int *__restrict__ out, int n, const int *__restrict__ tile_off)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
+__global__ void k_scan_total(const int *__restrict__ in, const int *__restrict__ out, int n, int *__restrict__ total)
+{
+    *total = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
+static int scan_rec(const int *in, int *out, int n, hipStream_t st, int *tmp)
+{
+    int nt = (n + kScanTile - 1) / kScanTile;
+    int *sums = tmp, *offs = tmp + nt;
+    k_scan_tile<<<nt, kScanThreads, 0, st>>>(in, out, n, sums);
+    if (nt > 1) {
+        int rc = scan_rec(sums, offs, nt, st, tmp + 2 * nt);
+        if (rc) return rc;
+        k_scan_add<<<(n + 255) / 256, 256, 0, st>>>(out, n, offs);
+    }
+    return 0;
+}
+
+int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp)
+{
+    if (n <= 0) {
+        if (total) hipMemsetAsync(total, 0, sizeof(int), st);
+        return 0;
+    }
+    size_t need = 0;
+    for (int m = n; m > 1; m = (m + kScanTile - 1) / kScanTile) need += 2 * ((m + kScanTile - 1) / kScanTile);
+    need += 4;
+    if (int rc = grow(tmp, need * sizeof(int))) return rc;
+    if (int rc = scan_rec(in, out, n, st, static_cast<int *>(tmp.p))) return rc;
+    if (total) k_scan_total<<<1, 1, 0, st>>>(in, out, n, total);
+    return hip_check(hipGetLastError(), "scan");
+}
+
+}  // namespace hfmm

@@ -1,0 +1,37 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and the
+binding refuses bad input before touching a GPU."""
+import ctypes as C
+
+import pytest
+
+import paper_2006_14952_amd as hf
+
+
+def test_library_exports_every_declared_symbol():
+    names = hf.exported_names()
+    assert {"fmm_build_tree", "fmm_short_range_forces", "pm_long_range_forces", "hybrid_forces"} <= set(names)
+    L = C.CDLL(hf.LIB_PATH)
+    for nm in names:
+        assert hasattr(L, nm), nm
+
+
+def test_param_struct_layout_matches_header():
+    assert C.sizeof(hf.Params) == 5 * 8 + 8 * 4
+    assert C.sizeof(hf.Stats) == 16 * 8 + 16 * 8
+
+
+def test_version_and_error_string():
+    assert "gfx950" in hf.version()
+    assert isinstance(hf.lib().fmm_last_error(), bytes)
+
+
+@pytest.mark.parametrize("bad", [dict(theta=0.0), dict(p=9), dict(p=-1), dict(n_crit=0), dict(r_cut=0.6),
+                                 dict(r_s=-1.0), dict(precision=2), dict(mac_mode=4), dict(box=0.0)])
+def test_bad_params_rejected_without_gpu(bad):
+    kw = dict(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
+    kw.update(bad)
+    prm = hf.params(**kw)
+    h = C.c_void_p()
+    rc = hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h))
+    assert rc == hf.FMM_ERR_ARG
+    assert hf.lib().fmm_last_error()

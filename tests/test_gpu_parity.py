@@ -1,0 +1,180 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Lists are compared as sets of (sink key, source key, image) triples (they must be
+identical: the MAC arithmetic is exact on both sides); forces are compared element by
+element.  FP64 form bar: median relative error <= 1e-6 and max <= 1e-4 against the
+oracle.  Every form: 99th percentile <= 1e-3 against the hard-cut brute force."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err, same_lists
+from paper_2006_14952_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+hf = pytest.importorskip("paper_2006_14952_amd")
+
+
+def gpu_run(pos, m, prm):
+    t = hf.Tree().build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+    acc = t.short_range(prm)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), t
+
+
+def opar(prm):
+    return oracle.make_params(box=prm.box, rs=prm.r_s, rcut=prm.r_cut, theta=prm.theta, G=prm.G, p=prm.p,
+                              ncrit=prm.n_crit, mac_mode=prm.mac_mode)
+
+
+def check_fp64(pos, m, prm, lists=True, targets=None):
+    got, t = gpu_run(pos, m, prm)
+    ref = oracle.fmm(pos, m, opar(prm), targets=targets)
+    if lists:
+        assert same_lists(t.interactions("p2p"), ref.lists("p2p"))
+        assert same_lists(t.interactions("m2l"), ref.lists("m2l"))
+    st = t.stats()
+    if targets is None:
+        assert st["n_m2l"] == ref.stats["n_m2l"] and st["n_p2p"] == ref.stats["n_p2p"]
+        assert st["p2p_pairs"] == ref.stats["p2p_pairs"]
+        e = rel_err(got, ref.acc)
+    else:
+        e = rel_err(got[targets], ref.acc[targets])
+    assert np.median(e) <= 1e-6 and e.max() <= 1e-4, (np.median(e), e.max())
+    t.free()
+    return got, ref, e
+
+
+@pytest.mark.parametrize("p", list(range(0, 9)))
+def test_fp64_every_order_small_clustered(p):
+    rng = inputs.rng_for(101, p)
+    pos, m = inputs.clustered(3000, 3, rng)
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.5, p=p, n_crit=8)
+    _, _, e = check_fp64(pos, m, prm)
+    assert e.max() < 1e-9
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_mac_modes_lists_identical(mode):
+    rng = inputs.rng_for(102, mode)
+    pos, m = inputs.clustered(6000, 5, rng)
+    prm = hf.params(r_s=0.015, r_cut=0.0675, theta=0.5, p=4, n_crit=16, mac_mode=mode)
+    check_fp64(pos, m, prm)
+
+
+def test_uniform_config_plain_fp64():
+    """32^3 uniform, r_s = 1.25/32, r_cut = 4.5 r_s, p = 4, theta = 0.5, FP64."""
+    pos, m = inputs.make("uniform")
+    pr = inputs.split_params("uniform")
+    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=0.5, p=4, n_crit=32)
+    got, ref, e = check_fp64(pos, m, prm)
+    assert e.max() < 1e-10
+    bf = oracle.bruteforce(pos, m, opar(prm))
+    assert np.percentile(rel_err(got, bf), 99) <= 1e-3
+
+
+def test_clustered_midsize_fp64_and_fp32():
+    rng = inputs.rng_for(103)
+    pos, m = inputs.clustered(60000, 60, rng)
+    prm = hf.params(r_s=0.01, r_cut=0.045, theta=0.4, p=6, n_crit=32)
+    got64, ref, e64 = check_fp64(pos, m, prm)
+    assert e64.max() < 1e-9
+    prm.precision = 1
+    got32, t = gpu_run(pos, m, prm)
+    e32 = rel_err(got32, ref.acc)
+    print("fp32 vs oracle: median %.2e p99 %.2e max %.2e" % (np.median(e32), np.percentile(e32, 99), e32.max()))
+    assert np.percentile(e32, 99) <= 1e-4
+    bf = oracle.bruteforce(pos, m, opar(prm))
+    for got in (got64, got32):
+        assert np.percentile(rel_err(got, bf), 99) <= 1e-3
+
+
+def test_clustered_config_full_size_sampled():
+    """N = 128^3 clustered, p = 6, theta = 0.4, FP32 and FP64 forms at full size; the oracle
+    evaluates 1500 sampled particles exactly (only their sink cells are traversed)."""
+    pos, m = inputs.make("clustered")
+    pr = inputs.split_params("clustered")
+    tg = inputs.rng_for(1, 7).choice(len(pos), 1500, replace=False)
+    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=0.4, p=6, n_crit=32, precision=0)
+    got64, ref, e64 = check_fp64(pos, m, prm, lists=False, targets=tg)
+    bf = oracle.bruteforce(pos, m, opar(prm), targets=tg)
+    assert np.percentile(rel_err(got64[tg], bf), 99) <= 1e-3
+    prm.precision = 1
+    got32, _ = gpu_run(pos, m, prm)
+    e32 = rel_err(got32[tg], ref.acc[tg])
+    print("fp32 full size vs oracle: median %.2e p99 %.2e max %.2e" % (np.median(e32), np.percentile(e32, 99),
+                                                                      e32.max()))
+    assert np.percentile(e32, 99) <= 1e-4
+    assert np.percentile(rel_err(got32[tg], bf), 99) <= 1e-3
+
+
+# ---- edge cases ------------------------------------------------------------------
+
+def test_empty_and_single_particle():
+    prm = hf.params(r_s=0.02, r_cut=0.09, p=4, n_crit=8)
+    t = hf.Tree().build(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                        torch.zeros(0, dtype=torch.float64, device="cuda"), prm)
+    out = t.short_range(prm)
+    assert out.shape == (0, 3)
+    got, _ = gpu_run(np.array([[0.3, 0.4, 0.5]]), np.array([1.0]), prm)
+    assert np.all(got == 0.0)
+
+
+def test_two_body_and_wrapping():
+    prm = hf.params(r_s=0.04, r_cut=0.18, p=4, n_crit=1)
+    pos = np.array([[0.99, 0.5, 0.5], [0.02, 0.52, 0.47]])  # across the periodic boundary
+    m = np.array([0.25, 0.75])
+    got, _ = gpu_run(pos, m, prm)
+    ref = oracle.bruteforce(pos, m, opar(prm))
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+    got2, _ = gpu_run(pos + np.array([[3.0, -1.0, 2.0], [-5.0, 1.0, 0.0]]), m, prm)
+    np.testing.assert_allclose(got2, ref, rtol=1e-9)
+
+
+def test_single_leaf_and_ragged_sizes():
+    rng = inputs.rng_for(104)
+    for n in (5, 63, 64, 65, 4095, 4097, 9001):
+        pos, m = inputs.clustered(n, 2, rng)
+        for ncrit in (1, 64, 100000):
+            prm = hf.params(r_s=0.03, r_cut=0.135, theta=0.5, p=3, n_crit=ncrit)
+            check_fp64(pos, m, prm)
+
+
+def test_coincident_and_dense_leaf():
+    """More than 64 particles in one finest cell (a leaf above n_crit) and exact duplicates."""
+    rng = inputs.rng_for(105)
+    pos, m = inputs.clustered(2000, 3, rng)
+    pos[:150] = pos[0]  # 150 coincident particles: pairs at r = 0 contribute nothing
+    prm = hf.params(r_s=0.03, r_cut=0.135, theta=0.5, p=4, n_crit=8)
+    check_fp64(pos, m, prm)
+
+
+def test_errors_reported():
+    prm = hf.params(r_s=0.02, r_cut=0.09, p=4, n_crit=8)
+    pos = np.random.default_rng(0).random((100, 3))
+    pos[7, 1] = np.nan
+    with pytest.raises(hf.FMMError) as ei:
+        gpu_run(pos, np.full(100, 0.01), prm)
+    assert ei.value.code == hf.FMM_ERR_NAN
+    pos[7, 1] = 0.5
+    t = hf.Tree().build(torch.tensor(pos, device="cuda"), torch.full((100,), 0.01, dtype=torch.float64, device="cuda"),
+                        prm)
+    prm2 = hf.params(r_s=0.02, r_cut=0.09, p=4, n_crit=9)
+    with pytest.raises(hf.FMMError) as ei:
+        t.short_range(prm2)
+    assert ei.value.code == hf.FMM_ERR_STATE
+
+
+def test_tree_reuse_shrink_and_grow():
+    rng = inputs.rng_for(106)
+    t = hf.Tree()
+    for n in (20000, 3000, 40000):
+        pos, m = inputs.clustered(n, 4, rng)
+        prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.5, p=4, n_crit=16)
+        t.build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+        got = t.short_range(prm).cpu().numpy()
+        ref = oracle.fmm(pos, m, opar(prm)).acc
+        assert rel_err(got, ref).max() < 1e-9
+    t.free()
