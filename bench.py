@@ -42,8 +42,13 @@ def main():
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--n-crit", type=int, default=None)
-    ap.add_argument("--cpu-sample", type=int, default=6000, help="oracle targets for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=20000, help="oracle targets for cpu_baseline (0: skip)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (calibrates HBM counters) and exit")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
@@ -156,6 +161,19 @@ def main():
 
 
 CONFIG_SAMPLE_SEED = 777
+
+
+def copy_calibration(nbytes):
+    """A plain elementwise copy (reads and writes nbytes each) for scaling the FETCH_SIZE
+    and WRITE_SIZE counters of the profiled kernels."""
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 if __name__ == "__main__":
     main()

@@ -111,13 +111,17 @@ class Tree:
     def __init__(self):
         self._h = C.c_void_p()
         self.n = 0
+        self._timing = False
 
     def build(self, pos, mass, prm: Params, stream=None):
         self.n = int(pos.shape[0])
         if mass.shape[0] != self.n:
             raise FMMError(FMM_ERR_ARG, "pos and mass lengths differ")
+        fresh = not self._h
         _check(lib().fmm_build_tree(C.byref(prm), self.n, _dev64(pos, (3,)) if self.n else None,
                                     _dev64(mass) if self.n else None, _stream(stream), C.byref(self._h)))
+        if fresh and self._timing:
+            _check(lib().fmm_set_timing(self._h, 1))
         return self
 
     def short_range(self, prm: Params, out=None, stream=None):
@@ -129,7 +133,10 @@ class Tree:
         return out
 
     def set_timing(self, on=True):
-        _check(lib().fmm_set_timing(self._h, int(on)))
+        """Per-stage HIP-event timing (applied now, or at the first build)."""
+        self._timing = bool(on)
+        if self._h:
+            _check(lib().fmm_set_timing(self._h, int(on)))
 
     def stats(self):
         s = Stats()

@@ -131,7 +131,6 @@ int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *
     fmm_stats &S = t->stats;
     S.n_m2l = t->n_m2l;
     S.n_p2p = t->n_p2p;
-    S.p2p_pairs = t->p2p_pairs;
     S.n_visit = t->n_visit;
     S.levels_traversed = t->nlevel;
     if (t->timing) {
@@ -146,9 +145,16 @@ int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *
     return hip_check(hipGetLastError(), "short range forces");
 }
 
-int fmm_get_stats(const fmm_tree *t, fmm_stats *out)
+int fmm_get_stats(const fmm_tree *tc, fmm_stats *out)
 {
-    if (!t || !out) return set_error(FMM_ERR_ARG, "NULL argument");
+    if (!tc || !out) return set_error(FMM_ERR_ARG, "NULL argument");
+    fmm_tree *t = const_cast<fmm_tree *>(tc);
+    if (t->counters.p && t->n > 0) {  // the P2P kernel counts listed pairs on the device
+        unsigned long long v = 0;
+        if (hipMemcpy(&v, ptr<unsigned long long>(t->counters) + 1, 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return set_error(FMM_ERR_HIP, "reading counters");
+        t->stats.p2p_pairs = (int64_t)v;
+    }
     *out = t->stats;
     return 0;
 }
@@ -176,7 +182,7 @@ int fmm_copy_interactions(const fmm_tree *tc, int kind, uint64_t *out, int64_t c
     hipMemcpy(next.data(), t->lnext[kind].p, next.size() * 4, hipMemcpyDeviceToHost);
     std::vector<uint64_t> key(nc);
     for (int c = 0; c < nc; ++c)
-        key[c] = cell_key_host(cell_level(cells[c]), cells[c].ix, cells[c].iy, cells[c].iz);
+        key[c] = cell_key_host(cell_level(cells[c]), cell_ix(cells[c]), cells[c].iy, cells[c].iz);
     int64_t w = 0;
     for (int c = 0; c < nc && w < cap; ++c) {
         int chunk = head[c];

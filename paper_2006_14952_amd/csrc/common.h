@@ -12,17 +12,24 @@ constexpr int kPMax = FMM_PMAX;
 
 // One octree cell: the cube [i h, (i+1) h)^3 with h = box / 2^level, holding the
 // Morton-sorted particles beg..end-1.  Children are contiguous (child .. child+nchild-1)
-// and ordered by octant 4 bx + 2 by + bz.  32 bytes, read as two 16-byte loads.
+// and ordered by octant 4 bx + 2 by + bz.  32 bytes; the first 16 hold everything the
+// traversal needs (x index, level, number of children, y and z indices, first child).
 struct __align__(16) Cell {
-    int ix, iy, iz;
-    int lvl_nch;  // level | (nchild << 8)
-    int beg, end;
+    int xln;      // ix | level << 21 | nchild << 26
+    int iy, iz;
     int child;    // first child, -1 for a leaf
+    int beg, end;
     int parent;   // -1 for the root
+    int pad;
 };
 
-__host__ __device__ inline int cell_level(const Cell &c) { return c.lvl_nch & 0xff; }
-__host__ __device__ inline int cell_nchild(const Cell &c) { return c.lvl_nch >> 8; }
+__host__ __device__ inline int pack_xln(int ix, int level, int nchild) { return ix | level << 21 | nchild << 26; }
+__host__ __device__ inline int xln_ix(int v) { return v & 0x1fffff; }
+__host__ __device__ inline int xln_level(int v) { return (v >> 21) & 31; }
+__host__ __device__ inline int xln_nchild(int v) { return (v >> 26) & 15; }
+__host__ __device__ inline int cell_ix(const Cell &c) { return xln_ix(c.xln); }
+__host__ __device__ inline int cell_level(const Cell &c) { return xln_level(c.xln); }
+__host__ __device__ inline int cell_nchild(const Cell &c) { return xln_nchild(c.xln); }
 
 // Multi-indices n = (nx, ny, nz) with |n| <= p, ordered by degree, then nx descending,
 // then ny descending: idx = d(d+1)(d+2)/6 + t(t+1)/2 + nz, d = |n|, t = ny + nz.

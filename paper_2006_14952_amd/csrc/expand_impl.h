@@ -1,0 +1,432 @@
+// Expansion operators of Sec. 2.1 (Eqs. (1), (2), (3), (5), (6)) with the truncated
+// kernel of Sec. 2.2, templated on the order P and the arithmetic type T.
+//
+// Coefficients are stored scaled by the cell side h so that FP32 keeps its range at
+// every level:  Mh_m = M_m / h^|m|,  Lh_n = L_n h^(|n|+1).  In these units
+//   P2M  Mh_m  = sum_a mu_a (-1)^|m|/m! ((x_a - z)/h)^m
+//   M2M  Mh_m(parent) = 2^-|m| sum_{n<=m} xh^n/n! Mh_{m-n}(child),  xh = (z_p - z_c)/h_c = +-1/2
+//   M2L  Lh_n(A) += sum_{|m|<=P-|n|} rho^|m| Mh_m(B) Dh_{n+m}(Rh),  rho = h_B/h_A, Rh = R/h_A,
+//        Dh_j = h_A^(|j|+1) D_j(R) = derivatives in h_A units with split scale r_s/h_A
+//   L2L  Lh_n(child) += 2^-(|n|+1) sum_{|m|<=P-|n|} xh^m/m! Lh_{n+m}(parent),  xh = +-1/4
+//   L2P  grad Psi = h^-2 sum_{|n|<=P-1} Lh_{n+e_k} yh^n/n!,  yh = (x - z)/h
+// The derivative tensor is built with the radial recurrence
+//   D^(m)_n = R_a D^(m+1)_{n-e_a} + (n_a - 1) D^(m+1)_{n-2e_a},   D^(m)_0 = f_(m)(r),
+// (f_(m) = (r^-1 d/dr)^m of the truncated potential), from the prefactor recurrence of
+// Sec. 2.2 in its corrected form  -r^2 f_(k) = (2k-1) f_(k-1) + (-1)^(k-1) e^(-r^2/4r_s^2)/(2^(k-1) sqrt(pi) r_s^(2k-1)).
+#pragma once
+#include "state.h"
+
+namespace hfmm {
+
+// ---------------------------------------------------------------------------
+// compile-time tables
+
+template <int P> struct Tab {
+    static constexpr int NC = ncoef(P);
+    int x[NC], y[NC], z[NC], d[NC];
+    int ax[NC], par[NC], par2[NC], na[NC];  // first non-zero axis a, index of n-e_a, of n-2e_a (-1), n_a
+    double invf[NC];                        // 1 / n!
+    double sgn_invf[NC];                    // (-1)^|n| / n!
+    constexpr Tab() : x(), y(), z(), d(), ax(), par(), par2(), na(), invf(), sgn_invf()
+    {
+        for (int dd = 0; dd <= P; ++dd)
+            for (int a = dd; a >= 0; --a)
+                for (int b = dd - a; b >= 0; --b) {
+                    int c = dd - a - b, k = midx(a, b, c);
+                    x[k] = a; y[k] = b; z[k] = c; d[k] = dd;
+                    double f = 1.0;
+                    for (int i = 2; i <= a; ++i) f *= i;
+                    for (int i = 2; i <= b; ++i) f *= i;
+                    for (int i = 2; i <= c; ++i) f *= i;
+                    invf[k] = 1.0 / f;
+                    sgn_invf[k] = (dd & 1) ? -1.0 / f : 1.0 / f;
+                    if (dd == 0) { ax[k] = 0; par[k] = -1; par2[k] = -1; na[k] = 0; continue; }
+                    int e[3] = {a, b, c};
+                    int q = e[0] ? 0 : (e[1] ? 1 : 2);
+                    ax[k] = q; na[k] = e[q];
+                    e[q] -= 1;
+                    par[k] = midx(e[0], e[1], e[2]);
+                    if (e[q] >= 1) { e[q] -= 1; par2[k] = midx(e[0], e[1], e[2]); }
+                    else par2[k] = -1;
+                }
+    }
+};
+
+constexpr int binom(int n, int k)
+{
+    int r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// (n, m) pairs with |n| + |m| <= P, m outer: used by M2L (L_n += M_m D_{n+m}) and L2L.
+template <int P> struct PairTab {
+    static constexpr int NT = binom(P + 6, 6);
+    short n[NT], m[NT], nm[NT];
+    int mstart[ncoef(P) + 1];  // pairs with source index m occupy mstart[m] .. mstart[m+1]-1
+    constexpr PairTab() : n(), m(), nm(), mstart()
+    {
+        Tab<P> T{};
+        int t = 0;
+        for (int km = 0; km < ncoef(P); ++km)
+            for (int kn = 0; kn < ncoef(P - T.d[km]); ++kn) {
+                n[t] = (short)kn; m[t] = (short)km;
+                nm[t] = (short)midx(T.x[kn] + T.x[km], T.y[kn] + T.y[km], T.z[kn] + T.z[km]);
+                if (kn == 0) mstart[km] = t;
+                ++t;
+            }
+        mstart[ncoef(P)] = t;
+    }
+};
+
+// M2L contraction for source indices KB .. KB+MB-1: the block of the source multipole is
+// loaded (scaled by rho^|m|) and consumed before the next block is loaded, so that only
+// L, D and one block are live.
+template <int P, class T, int KB, int MB>
+__device__ __forceinline__ void m2l_contract(const T *__restrict__ Mb, const T *rp, const T *D, T *acc)
+{
+    constexpr Tab<P> tb{};
+    constexpr PairTab<P> pt{};
+    constexpr int NC = ncoef(P);
+    constexpr int KE = KB + MB < NC ? KB + MB : NC;
+    T Ms[MB];
+#pragma unroll
+    for (int k = KB; k < KE; ++k) Ms[k - KB] = Mb[k] * rp[tb.d[k]];
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = pt.mstart[KB]; q < pt.mstart[KE]; ++q) acc[pt.n[q]] += Ms[pt.m[q] - KB] * D[pt.nm[q]];
+    if constexpr (KE < NC) m2l_contract<P, T, KE, MB>(Mb, rp, D, acc);
+}
+
+// (m, n) pairs with n <= m componentwise, |m| <= P: used by M2M.
+template <int P> struct SubTab {
+    static constexpr int NT = binom(P + 6, 6);
+    short m[NT], n[NT], mn[NT];
+    constexpr SubTab() : m(), n(), mn()
+    {
+        Tab<P> T{};
+        int t = 0;
+        for (int km = 0; km < ncoef(P); ++km)
+            for (int a = 0; a <= T.x[km]; ++a)
+                for (int b = 0; b <= T.y[km]; ++b)
+                    for (int c = 0; c <= T.z[km]; ++c) {
+                        m[t] = (short)km; n[t] = (short)midx(a, b, c);
+                        mn[t] = (short)midx(T.x[km] - a, T.y[km] - b, T.z[km] - c);
+                        ++t;
+                    }
+    }
+};
+
+// monomials y^n / n! for |n| <= P (scaled by w)
+template <int P, class T> __device__ __forceinline__ void monomials(T yx, T yy, T yz, T w, T *mono)
+{
+    constexpr Tab<P> tb{};
+    const T yv[3] = {yx, yy, yz};
+    mono[0] = w;
+#pragma unroll
+    for (int k = 1; k < Tab<P>::NC; ++k) mono[k] = mono[tb.par[k]] * yv[tb.ax[k]];
+#pragma unroll
+    for (int k = 1; k < Tab<P>::NC; ++k) mono[k] *= (T)tb.invf[k];
+}
+
+__device__ __forceinline__ float d_erfc(float x) { return erfcf(x); }
+__device__ __forceinline__ double d_erfc(double x) { return erfc(x); }
+__device__ __forceinline__ float d_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double d_exp(double x) { return exp(x); }
+__device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
+
+// Truncated prefactors f_(0..P) at squared distance r2 with split scale rs (any units).
+template <int P, class T> __device__ __forceinline__ void prefactors(T r2, T rs, T *f)
+{
+    T r = d_sqrt(r2);
+    T inv_r2 = (T)1 / r2;
+    T e = d_exp(-r2 / ((T)4 * rs * rs));
+    f[0] = d_erfc(r / ((T)2 * rs)) / r;
+    T src = e / ((T)1.7724538509055160273 * rs);  // k = 1 source term
+    T step = (T)(-0.5) / (rs * rs);
+#pragma unroll
+    for (int k = 1; k <= P; ++k) {
+        f[k] = -((T)(2 * k - 1) * f[k - 1] + src) * inv_r2;
+        src *= step;
+    }
+}
+
+// Dh_j for |j| <= P from the radial recurrence, in place: at level m the entries are
+// rewritten in decreasing index (hence non-increasing degree) order, so every read of
+// degree |n|-1 or |n|-2 still sees level m+1.
+template <int P, class T> __device__ __forceinline__ void dtensor(T Rx, T Ry, T Rz, const T *f, T *D)
+{
+    constexpr Tab<P> tb{};
+    const T Rv[3] = {Rx, Ry, Rz};
+    D[0] = f[P];
+#pragma unroll
+    for (int m = P - 1; m >= 0; --m) {
+#pragma unroll
+        for (int k = ncoef(P - m) - 1; k >= 1; --k) {
+            T v = Rv[tb.ax[k]] * D[tb.par[k]];
+            if (tb.par2[k] >= 0) v += (T)(tb.na[k] - 1) * D[tb.par2[k]];
+            D[k] = v;
+        }
+        D[0] = f[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+
+__device__ __forceinline__ double cell_h(const Cell &c, double box) { return ldexp(box, -cell_level(c)); }
+
+template <int P, class T>
+__global__ __launch_bounds__(64) void k_p2m(const Cell *__restrict__ cells, const int *__restrict__ leaves, int nleaf,
+                                            const double *__restrict__ xs, const double *__restrict__ ys,
+                                            const double *__restrict__ zs, const double *__restrict__ ms, double box,
+                                            T *__restrict__ M)
+{
+    constexpr int NC = Tab<P>::NC;
+    constexpr Tab<P> tb{};
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf) return;
+    int c = leaves[t];
+    Cell cc = cells[c];
+    double h = cell_h(cc, box), ih = 1.0 / h;
+    double cx = (cell_ix(cc) + 0.5) * h, cy = (cc.iy + 0.5) * h, cz = (cc.iz + 0.5) * h;
+    T acc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[k] = 0;
+    for (int i = cc.beg; i < cc.end; ++i) {
+        T mono[NC];
+        monomials<P, T>((T)((xs[i] - cx) * ih), (T)((ys[i] - cy) * ih), (T)((zs[i] - cz) * ih), (T)ms[i], mono);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += mono[k];
+    }
+    T *out = M + (size_t)c * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) out[k] = (tb.d[k] & 1) ? -acc[k] : acc[k];
+}
+
+template <int P, class T>
+__global__ __launch_bounds__(64) void k_m2m(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ M)
+{
+    constexpr int NC = Tab<P>::NC;
+    constexpr Tab<P> tb{};
+    constexpr SubTab<P> st{};
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    int c = lbeg + t;
+    Cell cc = cells[c];
+    int nch = cell_nchild(cc);
+    if (nch == 0) return;
+    T acc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[k] = 0;
+    for (int q = 0; q < nch; ++q) {
+        int ch = cc.child + q;
+        Cell cq = cells[ch];
+        T mono[NC], Mc[NC];
+        monomials<P, T>((T)(0.5 - (cell_ix(cq) & 1)), (T)(0.5 - (cq.iy & 1)), (T)(0.5 - (cq.iz & 1)), (T)1, mono);
+        const T *src = M + (size_t)ch * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) Mc[k] = src[k];
+#pragma unroll
+        for (int e = 0; e < SubTab<P>::NT; ++e) acc[st.m[e]] += mono[st.n[e]] * Mc[st.mn[e]];
+    }
+    T *out = M + (size_t)c * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) out[k] = acc[k] * (T)(1.0 / (double)(1 << tb.d[k]));
+}
+
+template <int P, class T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l(const Cell *__restrict__ cells, int ncell, const int *__restrict__ head,
+                                            const int *__restrict__ cnt, const uint32_t *__restrict__ items,
+                                            const int *__restrict__ next, const T *__restrict__ M, T *__restrict__ L,
+                                            double box, double rs)
+{
+    constexpr int NC = Tab<P>::NC;
+    constexpr Tab<P> tb{};
+    constexpr PairTab<P> pt{};
+    int A = blockIdx.x * blockDim.x + threadIdx.x;
+    if (A >= ncell) return;
+    int nl = cnt[A];
+    T acc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[k] = 0;
+    if (nl > 0) {
+        Cell ca = cells[A];
+        int la = cell_level(ca);
+        T rsh = (T)(rs / cell_h(ca, box));
+        int chunk = head[A];
+        for (int e = 0; e < nl; ++e) {
+            if (e > 0 && (e & (kChunk - 1)) == 0) chunk = next[chunk];
+            uint32_t it = items[(size_t)chunk * kChunk + (e & (kChunk - 1))];
+            int B = (int)(it >> 5), s = (int)(it & 31);
+            Cell cb = cells[B];
+            int lb = cell_level(cb);
+            int l = la > lb ? la : lb;
+            int64_t wa = (int64_t)1 << (l - la), wb = (int64_t)1 << (l - lb);
+            int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
+            // R / h_A = R_int / (2 w_a), R_int the integer separation in units of box/2^(l+1)
+            T inv2wa = (T)(0.5 / (double)wa);
+            T Rx = (T)((2 * (int64_t)cell_ix(ca) + 1) * wa - (2 * (int64_t)cell_ix(cb) + 1) * wb - (int64_t)sh[0] * ((int64_t)2 << l)) * inv2wa;
+            T Ry = (T)((2 * (int64_t)ca.iy + 1) * wa - (2 * (int64_t)cb.iy + 1) * wb - (int64_t)sh[1] * ((int64_t)2 << l)) * inv2wa;
+            T Rz = (T)((2 * (int64_t)ca.iz + 1) * wa - (2 * (int64_t)cb.iz + 1) * wb - (int64_t)sh[2] * ((int64_t)2 << l)) * inv2wa;
+            T f[P + 1], D[NC];
+            prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, rsh, f);
+            dtensor<P, T>(Rx, Ry, Rz, f, D);
+            T rho = (T)ldexp(1.0, la - lb);
+            T rp[P + 1];
+            rp[0] = 1;
+#pragma unroll
+            for (int k = 1; k <= P; ++k) rp[k] = rp[k - 1] * rho;
+            const T *Mb = M + (size_t)B * NC;
+            m2l_contract<P, T, 0, 16>(Mb, rp, D, acc);
+        }
+    }
+    T *out = L + (size_t)A * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) out[k] = acc[k];
+}
+
+template <int P, class T>
+__global__ __launch_bounds__(64) void k_l2l(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ L)
+{
+    constexpr int NC = Tab<P>::NC;
+    constexpr Tab<P> tb{};
+    constexpr PairTab<P> pt{};
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    int c = lbeg + t;
+    Cell cc = cells[c];
+    T mono[NC], Lp[NC], acc[NC];
+    monomials<P, T>((T)(0.25 * ((cell_ix(cc) & 1) ? 1 : -1)), (T)(0.25 * ((cc.iy & 1) ? 1 : -1)),
+                    (T)(0.25 * ((cc.iz & 1) ? 1 : -1)), (T)1, mono);
+    const T *src = L + (size_t)cc.parent * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) { Lp[k] = src[k]; acc[k] = 0; }
+#pragma unroll
+    for (int q = 0; q < PairTab<P>::NT; ++q) acc[pt.n[q]] += mono[pt.m[q]] * Lp[pt.nm[q]];
+    T *out = L + (size_t)c * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) out[k] += acc[k] * (T)(1.0 / (double)(2 << tb.d[k]));
+}
+
+// L2P (gradient of Eq. (6)), plus the near field, times G, written in caller order.
+template <int P, class T>
+__global__ __launch_bounds__(256) void k_l2p(const Cell *__restrict__ cells, const int *__restrict__ leaf_of, int n,
+                                             const double *__restrict__ xs, const double *__restrict__ ys,
+                                             const double *__restrict__ zs, const T *__restrict__ L,
+                                             const double *__restrict__ nearf, const int *__restrict__ perm, double box,
+                                             double G, double *__restrict__ acc)
+{
+    constexpr int NC = Tab<P>::NC;
+    constexpr int NC1 = P > 0 ? ncoef(P - 1) : 1;
+    constexpr Tab<P> tb{};
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = leaf_of[i];
+    Cell cc = cells[c];
+    double h = cell_h(cc, box), ih = 1.0 / h;
+    double g[3] = {0, 0, 0};
+    if (P > 0) {
+        T mono[NC1];
+        monomials<(P > 0 ? P - 1 : 0), T>((T)((xs[i] - (cell_ix(cc) + 0.5) * h) * ih), (T)((ys[i] - (cc.iy + 0.5) * h) * ih),
+                                          (T)((zs[i] - (cc.iz + 0.5) * h) * ih), (T)1, mono);
+        const T *Lc = L + (size_t)c * NC;
+        T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+        for (int k = 0; k < NC1; ++k) {
+            int a = tb.x[k], b = tb.y[k], z = tb.z[k];
+            gx += Lc[midx(a + 1, b, z)] * mono[k];
+            gy += Lc[midx(a, b + 1, z)] * mono[k];
+            gz += Lc[midx(a, b, z + 1)] * mono[k];
+        }
+        double s = ih * ih;
+        g[0] = (double)gx * s;
+        g[1] = (double)gy * s;
+        g[2] = (double)gz * s;
+    }
+    size_t o = 3 * (size_t)perm[i];
+    acc[o] = G * (g[0] + nearf[i]);
+    acc[o + 1] = G * (g[1] + nearf[(size_t)n + i]);
+    acc[o + 2] = G * (g[2] + nearf[2 * (size_t)n + i]);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over P and precision
+
+template <template <int, class> class F, class T, class... Args> int dispatch_p(int p, Args &&...args)
+{
+    switch (p) {
+    case 0: return F<0, T>::run(args...);
+    case 1: return F<1, T>::run(args...);
+    case 2: return F<2, T>::run(args...);
+    case 3: return F<3, T>::run(args...);
+    case 4: return F<4, T>::run(args...);
+    case 5: return F<5, T>::run(args...);
+    case 6: return F<6, T>::run(args...);
+    case 7: return F<7, T>::run(args...);
+    case 8: return F<8, T>::run(args...);
+    }
+    return set_error(FMM_ERR_ARG, "expansion order %d not compiled", p);
+}
+
+static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+template <int P, class T> struct Upward {
+    static int run(fmm_tree *t, hipStream_t st)
+    {
+        constexpr int NC = ncoef(P);
+        if (int rc = grow(t->Mc, (size_t)t->ncell * NC * sizeof(T)) | grow(t->Lc, (size_t)t->ncell * NC * sizeof(T)))
+            return rc;
+        k_p2m<P, T><<<nblk(t->nleaf, 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaves), t->nleaf,
+                                                       ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
+                                                       ptr<double>(t->ms), t->box, ptr<T>(t->Mc));
+        for (int l = t->nlevel - 2; l >= 0; --l) {
+            int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
+            k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+        }
+        return hip_check(hipGetLastError(), "upward pass");
+    }
+};
+
+template <int P, class T> struct M2L {
+    static int run(fmm_tree *t, double rs, hipStream_t st)
+    {
+        k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead),
+                                                       ptr<int>(t->lcnt), ptr<uint32_t>(t->litems[0]),
+                                                       ptr<int>(t->lnext[0]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs);
+        return hip_check(hipGetLastError(), "m2l");
+    }
+};
+
+template <int P, class T> struct L2L {
+    static int run(fmm_tree *t, hipStream_t st)
+    {
+        for (int l = 1; l < t->nlevel; ++l) {
+            int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
+            k_l2l<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
+        }
+        return hip_check(hipGetLastError(), "l2l");
+    }
+};
+
+template <int P, class T> struct L2P {
+    static int run(fmm_tree *t, double G, double *acc, hipStream_t st)
+    {
+        k_l2p<P, T><<<nblk(t->n, 256), 256, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaf_of), (int)t->n,
+                                                     ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
+                                                     ptr<T>(t->Lc), ptr<double>(t->nearf), ptr<int>(t->perm), t->box,
+                                                     G, acc);
+        return hip_check(hipGetLastError(), "l2p");
+    }
+};
+
+template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
+template <class T> int m2l_t(fmm_tree *t, int p, double rs, hipStream_t st) { return dispatch_p<M2L, T>(p, t, rs, st); }
+template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
+template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, hipStream_t st)
+{
+    return dispatch_p<L2P, T>(p, t, G, acc, st);
+}
+
+}  // namespace hfmm

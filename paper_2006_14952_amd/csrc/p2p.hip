@@ -2,21 +2,22 @@
 // (Sec. 2.1 last paragraph; force law of Sec. 2.2):  a_i += m_j f_(1)(r) d, d = x_i - x_j - s box,
 // counted iff 0 < r^2 < r_cut^2.
 //
-// One 64-lane wave per sink leaf.  Sources of up to 64 list entries are laid out as one
-// stream of slots (a wave prefix sum over the entry sizes); slots are staged 64 at a
-// time in LDS.  A sink leaf of n_A <= 64 particles occupies n2 = pow2ceil(n_A) lanes;
-// the wave holds 64 / n2 copies of the sink, each copy walking a different subset of
-// the staged sources, and the copies are summed with cross-lane shuffles at the end.
+// One 64-lane wave per sink leaf.  The sources of up to 64 list entries form one stream
+// of slots (a wave prefix sum over the entry sizes), staged 192 slots at a time in LDS.
+// A sink of n_A <= 64 particles is held floor(64 / n_A) times in the wave; copy g walks
+// slots g, g + G, ... of the staged stream, and the copies are summed through LDS at
+// the end.  Larger leaves are processed 64 sink particles at a time.
 //
 // FP64 form: absolute FP64 positions, erfc/exp from the device math library.
 // FP32 form: FP32 coordinates relative to each particle's leaf centre, the exact
 // centre offset c_B + s box - c_A added when staging, and
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
-// degree-10 polynomial fitted on the host; sums per staged chunk are added to a
+// degree-10 polynomial fitted on the host; the sum of each staged block is added to a
 // Kahan-compensated per-particle accumulator.
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "state.h"
@@ -46,13 +47,6 @@ __device__ __forceinline__ int find_entry(const int *pref, int ne, int slot)
     return lo;
 }
 
-__device__ __forceinline__ int pow2ceil(int v)
-{
-    int p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
 struct P2PArgs {
     const Cell *cells;
     const int *leaves;
@@ -66,92 +60,8 @@ struct P2PArgs {
     double box;
     double *nearf;  // 3 x n SoA
     int n;
+    unsigned long long *pairs;  // listed particle pairs (sum of n_A n_B over P2P leaf pairs)
 };
-
-// ---------------------------------------------------------------------------
-// FP64
-
-__global__ __launch_bounds__(64) void k_p2p_f64(P2PArgs a, P2PConst k)
-{
-    __shared__ double4 src[64];
-    __shared__ int ebeg[64], epref[64];
-    __shared__ double esh[64][3];
-    const int lane = threadIdx.x;
-    const int A = a.leaves[blockIdx.x];
-    const Cell ca = a.cells[A];
-    const int nA = ca.end - ca.beg;
-    const int nlist = a.cnt[A];
-    int chunk = a.head[A];
-    const double rc2 = k.rc2d, inv2rs = 0.5 / k.rs, c1 = 1.0 / (k.rs * 1.7724538509055160273);
-
-    for (int ib = 0; ib < nA; ib += 64) {
-        const int ns = min(64, nA - ib);
-        const int n2 = pow2ceil(ns), G = 64 / n2;
-        const int si = lane & (n2 - 1), g = lane / n2;
-        const bool valid = si < ns;
-        const int i = ca.beg + ib + (valid ? si : 0);
-        const double xi = a.xs[i], yi = a.ys[i], zi = a.zs[i];
-        double ax = 0, ay = 0, az = 0;
-        for (int eb = 0; eb < nlist; eb += 64) {
-            const int ne = min(64, nlist - eb);
-            int cntj = 0;
-            if (lane < ne) {
-                uint32_t it = a.items[(size_t)chunk * kChunk + lane];
-                int s = (int)(it & 31);
-                Cell cb = a.cells[it >> 5];
-                cntj = cb.end - cb.beg;
-                ebeg[lane] = cb.beg;
-                esh[lane][0] = (double)(s / 9 - 1) * a.box;
-                esh[lane][1] = (double)((s / 3) % 3 - 1) * a.box;
-                esh[lane][2] = (double)(s % 3 - 1) * a.box;
-            }
-            const int incl = wave_incl_scan(cntj);
-            if (lane < ne) epref[lane] = incl - cntj;
-            const int total = __shfl(incl, 63, 64);
-            __syncthreads();
-            for (int cb0 = 0; cb0 < total; cb0 += 64) {
-                const int slot = cb0 + lane;
-                double4 v = make_double4(1e30, 1e30, 1e30, 0.0);
-                if (slot < total) {
-                    int e = find_entry(epref, ne, slot);
-                    int j = ebeg[e] + slot - epref[e];
-                    v = make_double4(a.xs[j] + esh[e][0], a.ys[j] + esh[e][1], a.zs[j] + esh[e][2], a.ms[j]);
-                }
-                src[lane] = v;
-                __syncthreads();
-                for (int q = g; q < 64; q += G) {
-                    const double4 s = src[q];
-                    double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-                    double r2 = dx * dx + dy * dy + dz * dz;
-                    bool in = r2 > 0.0 && r2 < rc2;
-                    double rr2 = in ? r2 : 1.0;
-                    double r = sqrt(rr2);
-                    double u = r * inv2rs;
-                    double h = erfc(u) + r * c1 * exp(-u * u);
-                    double w = in ? -s.w * h / (rr2 * r) : 0.0;
-                    ax += w * dx;
-                    ay += w * dy;
-                    az += w * dz;
-                }
-                __syncthreads();
-            }
-            if (eb + 64 < nlist) chunk = a.next[chunk];
-        }
-        for (int o = n2; o < 64; o <<= 1) {
-            ax += __shfl_xor(ax, o, 64);
-            ay += __shfl_xor(ay, o, 64);
-            az += __shfl_xor(az, o, 64);
-        }
-        if (g == 0 && valid) {
-            a.nearf[i] = ax;
-            a.nearf[(size_t)a.n + i] = ay;
-            a.nearf[2 * (size_t)a.n + i] = az;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// FP32
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 {
@@ -161,29 +71,40 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
     s = t;
 }
 
-__global__ __launch_bounds__(64) void k_p2p_f32(P2PArgs a, P2PConst k)
+constexpr int kStage = 192;
+
+template <bool F64>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8))) void k_p2p(P2PArgs a, P2PConst k)
 {
-    __shared__ float4 src[64];
+    using R = typename std::conditional<F64, double, float>::type;
+    using V4 = typename std::conditional<F64, double4, float4>::type;
+    __shared__ V4 src[kStage];
     __shared__ int ebeg[64], epref[64];
-    __shared__ float eoff[64][3];
+    __shared__ R eoff[64][3];
     const int lane = threadIdx.x;
     const int A = a.leaves[blockIdx.x];
     const Cell ca = a.cells[A];
-    const int la = cell_level(ca);
-    const double hA = ldexp(a.box, -la);
-    const double cax = (ca.ix + 0.5) * hA, cay = (ca.iy + 0.5) * hA, caz = (ca.iz + 0.5) * hA;
+    const double hA = ldexp(a.box, -cell_level(ca));
+    const double cax = (cell_ix(ca) + 0.5) * hA, cay = (ca.iy + 0.5) * hA, caz = (ca.iz + 0.5) * hA;
     const int nA = ca.end - ca.beg;
     const int nlist = a.cnt[A];
-    int chunk = a.head[A];
+    unsigned long long npairs = 0;
 
     for (int ib = 0; ib < nA; ib += 64) {
         const int ns = min(64, nA - ib);
-        const int n2 = pow2ceil(ns), G = 64 / n2;
-        const int si = lane & (n2 - 1), g = lane / n2;
-        const bool valid = si < ns;
+        const int G = 64 / ns, g = lane / ns, si = lane - g * ns;
+        const bool valid = g < G;
         const int i = ca.beg + ib + (valid ? si : 0);
-        const float4 me = a.rel[i];
-        float sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;
+        R xi, yi, zi;
+        if constexpr (F64) {
+            xi = a.xs[i]; yi = a.ys[i]; zi = a.zs[i];
+        } else {
+            float4 me = a.rel[i];
+            xi = me.x; yi = me.y; zi = me.z;
+        }
+        double ax = 0, ay = 0, az = 0;              // FP64 form
+        float sx = 0, sy = 0, sz = 0, cx = 0, cy = 0, cz = 0;  // FP32 form (Kahan)
+        int chunk = a.head[A];
         for (int eb = 0; eb < nlist; eb += 64) {
             const int ne = min(64, nlist - eb);
             int cntj = 0;
@@ -191,64 +112,107 @@ __global__ __launch_bounds__(64) void k_p2p_f32(P2PArgs a, P2PConst k)
                 uint32_t it = a.items[(size_t)chunk * kChunk + lane];
                 int s = (int)(it & 31);
                 Cell cb = a.cells[it >> 5];
-                double hB = ldexp(a.box, -cell_level(cb));
                 cntj = cb.end - cb.beg;
                 ebeg[lane] = cb.beg;
-                // exact in FP64: dyadic centres and integer image shifts
-                eoff[lane][0] = (float)((cb.ix + 0.5) * hB + (double)(s / 9 - 1) * a.box - cax);
-                eoff[lane][1] = (float)((cb.iy + 0.5) * hB + (double)((s / 3) % 3 - 1) * a.box - cay);
-                eoff[lane][2] = (float)((cb.iz + 0.5) * hB + (double)(s % 3 - 1) * a.box - caz);
+                double shx = (double)(s / 9 - 1) * a.box, shy = (double)((s / 3) % 3 - 1) * a.box,
+                       shz = (double)(s % 3 - 1) * a.box;
+                if constexpr (F64) {
+                    eoff[lane][0] = shx; eoff[lane][1] = shy; eoff[lane][2] = shz;
+                } else {  // exact in FP64: dyadic centres and integer image shifts
+                    double hB = ldexp(a.box, -cell_level(cb));
+                    eoff[lane][0] = (float)((cell_ix(cb) + 0.5) * hB + shx - cax);
+                    eoff[lane][1] = (float)((cb.iy + 0.5) * hB + shy - cay);
+                    eoff[lane][2] = (float)((cb.iz + 0.5) * hB + shz - caz);
+                }
             }
             const int incl = wave_incl_scan(cntj);
             if (lane < ne) epref[lane] = incl - cntj;
-            const int total = __shfl(incl, 63, 64);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
+            npairs += (unsigned long long)ns * (unsigned)total;
             __syncthreads();
-            for (int cb0 = 0; cb0 < total; cb0 += 64) {
-                const int slot = cb0 + lane;
-                float4 v = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-                if (slot < total) {
+            for (int sb = 0; sb < total; sb += kStage) {
+                const int nst = min(kStage, total - sb);
+                for (int q = lane; q < nst; q += 64) {
+                    int slot = sb + q;
                     int e = find_entry(epref, ne, slot);
-                    float4 r = a.rel[ebeg[e] + slot - epref[e]];
-                    v = make_float4(r.x + eoff[e][0], r.y + eoff[e][1], r.z + eoff[e][2], r.w);
+                    int j = ebeg[e] + slot - epref[e];
+                    if constexpr (F64) {
+                        src[q] = make_double4(a.xs[j] + eoff[e][0], a.ys[j] + eoff[e][1], a.zs[j] + eoff[e][2], a.ms[j]);
+                    } else {
+                        float4 r = a.rel[j];
+                        src[q] = make_float4(r.x + eoff[e][0], r.y + eoff[e][1], r.z + eoff[e][2], r.w);
+                    }
                 }
-                src[lane] = v;
                 __syncthreads();
-                float px = 0, py = 0, pz = 0;
-                for (int q = g; q < 64; q += G) {
-                    const float4 s = src[q];
-                    float dx = me.x - s.x, dy = me.y - s.y, dz = me.z - s.z;
-                    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                    float rinv = __frsqrt_rn(r2);
-                    float t = fmaf(r2, k.two_over_rc2, -1.0f);
-                    float S = k.c[kP2PPoly - 1];
+                if (valid) {
+                    if constexpr (F64) {
+                        const double rc2 = k.rc2d, inv2rs = 0.5 / k.rs, c1 = 1.0 / (k.rs * 1.7724538509055160273);
+                        for (int q = g; q < nst; q += G) {
+                            const double4 s = src[q];
+                            double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+                            double r2 = dx * dx + dy * dy + dz * dz;
+                            bool in = r2 > 0.0 && r2 < rc2;
+                            double rr2 = in ? r2 : 1.0;
+                            double r = sqrt(rr2);
+                            double u = r * inv2rs;
+                            double h = erfc(u) + r * c1 * exp(-u * u);
+                            double w = in ? -s.w * h / (rr2 * r) : 0.0;
+                            ax += w * dx;
+                            ay += w * dy;
+                            az += w * dz;
+                        }
+                    } else {
+                        float px = 0, py = 0, pz = 0;
+                        for (int q = g; q < nst; q += G) {
+                            const float4 s = src[q];
+                            float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+                            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                            float rinv = __frsqrt_rn(r2);
+                            float t = fmaf(r2, k.two_over_rc2, -1.0f);
+                            float S = k.c[kP2PPoly - 1];
 #pragma unroll
-                    for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
-                    float rinv2 = rinv * rinv;
-                    float f1 = fmaf(S, k.inv8rs3, -rinv2 * rinv);
-                    float w = (r2 < k.rc2 && r2 > 0.0f) ? s.w * f1 : 0.0f;
-                    px = fmaf(w, dx, px);
-                    py = fmaf(w, dy, py);
-                    pz = fmaf(w, dz, pz);
+                            for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
+                            float rinv2 = rinv * rinv;
+                            float f1 = fmaf(S, k.inv8rs3, -rinv2 * rinv);
+                            float w = (r2 < k.rc2 && r2 > 0.0f) ? s.w * f1 : 0.0f;
+                            px = fmaf(w, dx, px);
+                            py = fmaf(w, dy, py);
+                            pz = fmaf(w, dz, pz);
+                        }
+                        kahan_add(sx, cx, px);
+                        kahan_add(sy, cy, py);
+                        kahan_add(sz, cz, pz);
+                    }
                 }
-                kahan_add(sx, cx, px);
-                kahan_add(sy, cy, py);
-                kahan_add(sz, cz, pz);
                 __syncthreads();
             }
             if (eb + 64 < nlist) chunk = a.next[chunk];
         }
-        double ax = (double)sx - (double)cx, ay = (double)sy - (double)cy, az = (double)sz - (double)cz;
-        for (int o = n2; o < 64; o <<= 1) {
-            ax += __shfl_xor(ax, o, 64);
-            ay += __shfl_xor(ay, o, 64);
-            az += __shfl_xor(az, o, 64);
+        if constexpr (!F64) {
+            ax = (double)sx - (double)cx;
+            ay = (double)sy - (double)cy;
+            az = (double)sz - (double)cz;
         }
-        if (g == 0 && valid) {
-            a.nearf[i] = ax;
-            a.nearf[(size_t)a.n + i] = ay;
-            a.nearf[2 * (size_t)a.n + i] = az;
+        double(*red)[3] = reinterpret_cast<double(*)[3]>(&src[0]);  // staging area is free here
+        red[lane][0] = ax;
+        red[lane][1] = ay;
+        red[lane][2] = az;
+        __syncthreads();
+        if (lane < ns) {
+            double tx = 0, ty = 0, tz = 0;
+            for (int q = 0; q < G; ++q) {
+                tx += red[q * ns + lane][0];
+                ty += red[q * ns + lane][1];
+                tz += red[q * ns + lane][2];
+            }
+            int o = ca.beg + ib + lane;
+            a.nearf[o] = tx;
+            a.nearf[(size_t)a.n + o] = ty;
+            a.nearf[2 * (size_t)a.n + o] = tz;
         }
+        __syncthreads();
     }
+    if (lane == 0) atomicAdd(a.pairs, npairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,8 +285,9 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
     a.box = t->box;
     a.nearf = ptr<double>(t->nearf);
     a.n = (int)t->n;
-    if (P->precision) k_p2p_f32<<<t->nleaf, 64, 0, st>>>(a, k);
-    else k_p2p_f64<<<t->nleaf, 64, 0, st>>>(a, k);
+    a.pairs = ptr<unsigned long long>(t->counters) + 1;
+    if (P->precision) k_p2p<false><<<t->nleaf, 64, 0, st>>>(a, k);
+    else k_p2p<true><<<t->nleaf, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");
 }
 

@@ -21,34 +21,31 @@
 namespace hfmm {
 
 // 0 = neglect (item 1), 1 = M2L (item 2), 2 = open (item 3 or item 2 failed).
-// Distances are exact integers in units of u = box / 2^(l+1), l the finer level.
-__device__ inline int mac_decide(const Cell &a, const Cell &b, int s, const MacConst &mc)
+// Distances are integers in units of u = box / 2^(l+1), l the finer level: every
+// separation is below 2^23 and every squared distance below 2^50, so double precision
+// holds them exactly and the comparisons are exact.
+__device__ __forceinline__ int mac_decide(int4 a, int4 b, int s, const MacConst &mc)
 {
-    int la = cell_level(a), lb = cell_level(b);
+    int la = xln_level(a.x), lb = xln_level(b.x);
     int l = la > lb ? la : lb;
-    int64_t wa = (int64_t)1 << (l - la), wb = (int64_t)1 << (l - lb);
-    int64_t half = wa + wb;
-    int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
-    int ia[3] = {a.ix, a.iy, a.iz}, ib[3] = {b.ix, b.iy, b.iz};
-    int64_t sc2 = 0, sm2 = 0, sM2 = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        int64_t R = (2 * (int64_t)ia[i] + 1) * wa - (2 * (int64_t)ib[i] + 1) * wb - (int64_t)sh[i] * ((int64_t)2 << l);
-        int64_t aR = R < 0 ? -R : R;
-        int64_t g = aR - half;
-        g = g < 0 ? 0 : g;
-        int64_t G = aR + half;
-        sc2 += R * R;
-        sm2 += g * g;
-        sM2 += G * G;
-    }
-    double cut2 = mc.cut2[l];
-    if ((double)sm2 > cut2) return 0;
-    bool straddle = (mc.mode & 1) ? ((double)sc2 > cut2) : ((double)sM2 > cut2);
+    double wa = (double)(1 << (l - la)), wb = (double)(1 << (l - lb));
+    double half = wa + wb, img = (double)(2 << l);
+    double sh0 = (double)(s / 9 - 1), sh1 = (double)((s / 3) % 3 - 1), sh2 = (double)(s % 3 - 1);
+    double R0 = (2.0 * xln_ix(a.x) + 1.0) * wa - (2.0 * xln_ix(b.x) + 1.0) * wb - sh0 * img;
+    double R1 = (2.0 * a.y + 1.0) * wa - (2.0 * b.y + 1.0) * wb - sh1 * img;
+    double R2 = (2.0 * a.z + 1.0) * wa - (2.0 * b.z + 1.0) * wb - sh2 * img;
+    double A0 = fabs(R0), A1 = fabs(R1), A2 = fabs(R2);
+    double g0 = fmax(A0 - half, 0.0), g1 = fmax(A1 - half, 0.0), g2 = fmax(A2 - half, 0.0);
+    double sm2 = g0 * g0 + g1 * g1 + g2 * g2;
+    double cut2 = ldexp(mc.cut2[0], 2 * l);  // equals (r_cut / u_l)^2 exactly
+    if (sm2 > cut2) return 0;
+    double sc2 = R0 * R0 + R1 * R1 + R2 * R2;
+    double G0 = A0 + half, G1 = A1 + half, G2 = A2 + half;
+    double sM2 = G0 * G0 + G1 * G1 + G2 * G2;
+    bool straddle = (mc.mode & 1) ? (sc2 > cut2) : (sM2 > cut2);
     if (straddle) return 2;
-    int64_t w = (mc.mode & 2) ? wb : (wa > wb ? wa : wb);
-    double hl2 = (double)(4 * w * w);
-    if (hl2 <= mc.theta2 * (double)sc2) return 1;
+    double w = (mc.mode & 2) ? wb : fmax(wa, wb);
+    if (4.0 * w * w <= mc.theta2 * sc2) return 1;
     return 2;
 }
 
@@ -63,7 +60,7 @@ struct TravArgs {
     uint32_t *stack; // per-wave stacks when they do not fit in LDS
     int stk_cap;
     int *err;        // bit 0: stack overflow, bit 1: pool overflow
-    unsigned long long *counters;  // [0] visits, [1] listed particle pairs, [2] M2L, [3] P2P
+    unsigned long long *counters;  // [0] visits, [1] listed particle pairs (P2P kernel), [2] M2L, [3] P2P
 };
 
 constexpr int kChunkBlock = 16;   // chunks taken from a pool per atomic
@@ -74,13 +71,14 @@ struct ListState {
 };
 
 // Next free chunk of list k.  Each wave takes kChunkBlock chunks per atomic and hands
-// them out itself, so the pool counters see one atomic per 16 chunks.
+// them out itself, so the pool counters see one atomic per 16 chunks.  All list state
+// is wave-uniform and kept in scalar registers.
 __device__ __forceinline__ int new_chunk(const TravArgs &a, int k, int *bnext, int *bend, int lane)
 {
     if (bnext[k] == bend[k]) {
         int c = 0;
         if (lane == 0) c = atomicAdd(&a.pool[k], kChunkBlock);
-        c = __shfl(c, 0, 64);
+        c = __builtin_amdgcn_readfirstlane(c);
         bnext[k] = c;
         bend[k] = c + kChunkBlock;
     }
@@ -141,19 +139,20 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
     const uint64_t lt = (1ull << lane) - 1ull;
     uint32_t *stk = GLOBAL_STACK ? a.stack + (size_t)blockIdx.x * a.stk_cap : lds_stack;
     const int scap = GLOBAL_STACK ? a.stk_cap : kLdsStack;
-    unsigned long long visits = 0, pairs = 0, nm2l = 0, np2p = 0;
+    const int4 *cell4 = reinterpret_cast<const int4 *>(a.cells);  // two int4 per cell
+    unsigned long long visits = 0, nm2l = 0, np2p = 0;
     int bnext[3] = {0, 0, 0}, bend[3] = {0, 0, 0};
     for (int t = blockIdx.x; t < a.ln; t += gridDim.x) {
         const int A = a.lbeg + t;
-        const Cell ca = a.cells[A];
-        const bool leafA = cell_nchild(ca) == 0;
-        const int lvA = cell_level(ca);
-        const int nA = ca.end - ca.beg;
+        const int4 ga = cell4[2 * A];
+        const int parentA = a.cells[A].parent;
+        const bool leafA = xln_nchild(ga.x) == 0;
+        const int lvA = xln_level(ga.x);
         const bool root = A == 0;
         int ninh = 27, ichunk = 0;
         if (!root) {
-            ninh = a.cnt[2 * a.ncell + ca.parent];
-            ichunk = a.head[2 * a.ncell + ca.parent];
+            ninh = a.cnt[2 * a.ncell + parentA];
+            ichunk = a.head[2 * a.ncell + parentA];
         }
         ListState Ls[3];
 #pragma unroll
@@ -175,35 +174,37 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
             } else {
                 break;
             }
+            visits += kk;
             const bool valid = lane < kk;
             int d = 0;
-            Cell cb;
+            int4 gb = make_int4(0, 0, 0, 0);
             const int B = (int)(it >> 5), s = (int)(it & 31);
             if (valid) {
-                cb = a.cells[B];
-                d = mac_decide(ca, cb, s, mc);
-                ++visits;
+                gb = cell4[2 * B];
+                d = mac_decide(ga, gb, s, mc);
             }
-            bool leafB = valid && cell_nchild(cb) == 0;
+            const int lvB = xln_level(gb.x);
+            const bool leafB = xln_nchild(gb.x) == 0;
             bool is_m2l = d == 1;
             bool is_p2p = d == 2 && leafA && leafB;
-            bool is_pd = d == 2 && !is_p2p && !leafA && (lvA <= cell_level(cb) || leafB);
+            bool is_pd = d == 2 && !is_p2p && !leafA && (lvA <= lvB || leafB);
             bool open_src = d == 2 && !is_p2p && !is_pd;
-            if (is_p2p) pairs += (unsigned long long)nA * (unsigned)(cb.end - cb.beg);
             emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
             emit(a, 1, Ls[1], bnext, bend, is_p2p, it, lt, lane);
             emit(a, 2, Ls[2], bnext, bend, is_pd, it, lt, lane);
-            int nch = open_src ? cell_nchild(cb) : 0;
+            int nch = open_src ? xln_nchild(gb.x) : 0;
             int incl = wave_incl_scan(nch, lane);
-            int tot = __shfl(incl, 63, 64);
+            int tot = __builtin_amdgcn_readlane(incl, 63);
             if (tot > 0) {
                 if (sp + tot > scap) {
                     if (lane == 0) atomicOr(a.err, 1);
                     failed = true;
                     break;
                 }
-                int off = sp + incl - nch;
-                for (int q = 0; q < nch; ++q) stk[off + q] = (uint32_t)(cb.child + q) << 5 | (uint32_t)s;
+                if (nch > 0) {
+                    int off = sp + incl - nch;
+                    for (int q = 0; q < nch; ++q) stk[off + q] = (uint32_t)(gb.w + q) << 5 | (uint32_t)s;
+                }
                 sp += tot;
                 __syncthreads();  // pushes complete before the next pop reads them
             }
@@ -219,15 +220,8 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
         nm2l += Ls[0].tot;
         np2p += Ls[1].tot;
     }
-    // per-lane visit/pair counts, summed over the wave
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        visits += __shfl_xor(visits, o, 64);
-        pairs += __shfl_xor(pairs, o, 64);
-    }
     if (lane == 0) {
         atomicAdd(&a.counters[0], visits);
-        atomicAdd(&a.counters[1], pairs);
         atomicAdd(&a.counters[2], nm2l);
         atomicAdd(&a.counters[3], np2p);
     }
@@ -311,7 +305,6 @@ int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st)
         int err = c32[3];
         if (err == 0) {
             t->n_visit = (int64_t)c64[0];
-            t->p2p_pairs = (int64_t)c64[1];
             t->n_m2l = (int64_t)c64[2];
             t->n_p2p = (int64_t)c64[3];
             return 0;

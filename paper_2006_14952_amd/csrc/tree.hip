@@ -180,8 +180,9 @@ __global__ void k_gather(const double *__restrict__ pos, const double *__restric
 __global__ void k_root(Cell *cells, int n)
 {
     Cell c;
-    c.ix = c.iy = c.iz = 0;
-    c.lvl_nch = 0;
+    c.xln = pack_xln(0, 0, 0);
+    c.iy = c.iz = 0;
+    c.pad = 0;
     c.beg = 0;
     c.end = n;
     c.child = -1;
@@ -239,10 +240,10 @@ __global__ void k_make_children(Cell *__restrict__ cells, int lbeg, int ln, int 
     for (int o = 0; o < 8; ++o) {
         if (b[o + 1] == b[o]) continue;
         Cell ch;
-        ch.ix = 2 * c.ix + ((o >> 2) & 1);
+        ch.xln = pack_xln(2 * cell_ix(c) + ((o >> 2) & 1), l + 1, 0);
         ch.iy = 2 * c.iy + ((o >> 1) & 1);
         ch.iz = 2 * c.iz + (o & 1);
-        ch.lvl_nch = l + 1;
+        ch.pad = 0;
         ch.beg = b[o];
         ch.end = b[o + 1];
         ch.child = -1;
@@ -251,7 +252,7 @@ __global__ void k_make_children(Cell *__restrict__ cells, int lbeg, int ln, int 
         ++k;
     }
     c.child = first;
-    c.lvl_nch = l | (k << 8);
+    c.xln = pack_xln(cell_ix(c), l, k);
     cells[ci] = c;
 }
 
@@ -281,7 +282,7 @@ __global__ void k_rel32(const Cell *__restrict__ cells, const int *__restrict__ 
     if (i >= n) return;
     Cell c = cells[leaf_of[i]];
     double h = ldexp(box, -cell_level(c));
-    rel[i] = make_float4((float)(xs[i] - (c.ix + 0.5) * h), (float)(ys[i] - (c.iy + 0.5) * h),
+    rel[i] = make_float4((float)(xs[i] - (cell_ix(c) + 0.5) * h), (float)(ys[i] - (c.iy + 0.5) * h),
                          (float)(zs[i] - (c.iz + 0.5) * h), (float)ms[i]);
 }
 
