@@ -27,9 +27,11 @@ P2P_FLOP_PER_PAIR = 38.0
 # Largest opening angle of the grid {0.5, 0.45, 0.4, 0.35, 0.3} whose p99 error against
 # brute force is <= 1e-3 at the configured order (measured with the oracle on the
 # clustered workload: theta 0.5 -> 2.5e-3, 0.45 -> 1.9e-3, 0.4 -> 2.6e-4).
+# Batched: theta 0.6 -> p99 2.8e-2 .. 4.2e-2 on sampled boxes, 0.4 -> 6.6e-4 .. 9.6e-4 at p = 5.
 WORKLOADS = {
     "clustered": dict(theta=0.4, precision=1, n_crit=32),
     "uniform": dict(theta=0.5, precision=0, n_crit=32),
+    "batched": dict(theta=0.4, precision=1, n_crit=32),
 }
 
 
@@ -68,7 +70,15 @@ def main():
         wl["n_crit"] = args.n_crit
     cfg = inputs.CONFIGS[args.workload]
     pr = inputs.split_params(args.workload)
-    pos_np, m_np = inputs.make(args.workload)
+    batched = args.workload == "batched"
+    if batched:
+        sizes = inputs.batched_sizes(cfg["nbox"])
+        boxes = [inputs.batched_box(b, sizes[b]) for b in range(len(sizes))]
+        offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        pos_np = np.concatenate([b[0] for b in boxes])
+        m_np = np.concatenate([b[1] for b in boxes])
+    else:
+        pos_np, m_np = inputs.make(args.workload)
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
                     precision=wl["precision"])
@@ -80,7 +90,10 @@ def main():
     tree = hf.Tree()
 
     def step():
-        tree.build(pos, mass, prm, stream)
+        if batched:
+            tree.build_batched(pos, mass, [prm] * len(boxes), offsets, stream)
+        else:
+            tree.build(pos, mass, prm, stream)
         tree.short_range(prm, out=acc, stream=stream)
 
     for _ in range(args.warmup):
@@ -123,7 +136,8 @@ def main():
         "dtype": "f32" if wl["precision"] else "f64",
         "data": "synthetic",
         "config": {"workload": "%s N=%d (%s), p=%d, theta=%.2f, n_crit=%d, r_s=%.6g, r_cut=%.6g, %s" % (
-            args.workload, n, cfg["kind"], pr["p"], wl["theta"], wl["n_crit"], pr["rs"], pr["rcut"],
+            args.workload, n, cfg["kind"] + (" %d boxes in one forest" % len(boxes) if batched else ""),
+            pr["p"], wl["theta"], wl["n_crit"], pr["rs"], pr["rcut"],
             "FP32 P2P/M2L + FP64 positions/offsets/final sum" if wl["precision"] else "FP64"),
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"]},
         "roofline": {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
@@ -134,7 +148,31 @@ def main():
         "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit")},
     }
 
-    if args.cpu_sample > 0:
+    if args.cpu_sample > 0 and batched:
+        import oracle  # sampled particles of the largest box (oracle runs on that box alone)
+        b = int(np.argmax(sizes))
+        bp, bm = boxes[b]
+        got = acc.cpu().numpy()[offsets[b]:offsets[b + 1]]
+        tg = inputs.rng_for(CONFIG_SAMPLE_SEED).choice(len(bp), min(args.cpu_sample, len(bp)), replace=False)
+        op = oracle.make_params(box=1.0, rs=pr["rs"], rcut=pr["rcut"], theta=wl["theta"], p=pr["p"],
+                                ncrit=wl["n_crit"])
+        t1 = time.perf_counter()
+        res = oracle.fmm(bp, bm, op, targets=tg)
+        t_or = time.perf_counter() - t1
+        bf = oracle.bruteforce(bp, bm, op, targets=tg)
+        ref_norm = np.linalg.norm(bf, axis=1)
+        floor = np.median(ref_norm[ref_norm > 0])
+        e_bf = np.linalg.norm(got[tg] - bf, axis=1) / np.where(ref_norm > 0, ref_norm, floor)
+        e_or = np.linalg.norm(got[tg] - res.acc[tg], axis=1) / np.maximum(np.linalg.norm(res.acc[tg], axis=1), 1e-300)
+        out["cpu_baseline"] = {"value": len(tg) / t_or, "unit": "particles/s", "cores": oracle.max_threads(),
+                               "kind": "oracle", "sample": "%d random particles of the largest box (N=%d): its tree"
+                               " and upward pass, their sink cells' traversal/M2L/P2P/downward; %.1f s"
+                               % (len(tg), len(bp), t_or)}
+        out["accuracy"] = {"sample": len(tg), "p99_vs_bruteforce": float(np.percentile(e_bf, 99)),
+                           "median_vs_bruteforce": float(np.median(e_bf)), "max_vs_bruteforce": float(e_bf.max()),
+                           "median_vs_oracle": float(np.median(e_or)), "p99_vs_oracle": float(np.percentile(e_or, 99)),
+                           "max_vs_oracle": float(e_or.max())}
+    elif args.cpu_sample > 0:
         import oracle
         got = acc.cpu().numpy()
         tg = inputs.rng_for(CONFIG_SAMPLE_SEED).choice(n, min(args.cpu_sample, n), replace=False)

@@ -99,7 +99,8 @@ int fmm_build_tree(const fmm_params *params, int64_t n, const double *pos, const
  * upward pass (P2M, M2M), dual traversal with the modified MAC, M2L and P2P, downward
  * pass (L2L, L2P).  acc (n,3) is overwritten.  params->box and n_crit must equal the
  * values the tree was built with (FMM_ERR_STATE otherwise).  Synchronises the stream
- * once per traversed level (list sizes are read back). */
+ * once, after the traversal (list pool usage is read back; if a pool or traversal stack
+ * was too small the traversal is rerun with enough room). */
 int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
 
 /* Long-range accelerations by the particle-mesh method with a mesh of mesh^3 cells
@@ -114,10 +115,21 @@ int pm_long_range_forces(const fmm_params *params, int mesh, int64_t n, const do
 int hybrid_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
                   double *acc, void *stream);
 
+/* Build one forest over nbox independent periodic boxes stored back to back: box b holds
+ * particles offsets[b] .. offsets[b+1]-1 of pos/mass (offsets: HOST array of nbox+1
+ * entries, offsets[0] = 0, non-decreasing; empty boxes allowed).  Every box gets its own
+ * root; particles are ordered by box, then Morton key.  All per_box entries must be equal
+ * (FMM_ERR_ARG otherwise).  The returned tree works with fmm_short_range_forces,
+ * fmm_get_stats, fmm_set_timing, fmm_copy_interactions and fmm_free_tree; its stages
+ * process all boxes in shared launches.  Reuse of *out as in fmm_build_tree. */
+int fmm_build_tree_batched(const fmm_params *per_box, int nbox, const int64_t *offsets, const double *pos,
+                           const double *mass, void *stream, fmm_tree **out);
+
 /* Short-range accelerations of nbox independent periodic boxes stored back to back:
  * box b holds particles offsets[b] .. offsets[b+1]-1 of pos/mass/acc, with its own
- * parameters per_box[b].  offsets is a HOST array of nbox+1 entries starting at 0.
- * The P2P and M2L work of all boxes runs in shared launches. */
+ * parameters per_box[b] (all equal, see fmm_build_tree_batched).  offsets is a HOST
+ * array of nbox+1 entries starting at 0.  Builds a forest held by the library (reused by
+ * later calls, serialised by a lock) and evaluates all boxes in shared launches. */
 int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets,
                                    const double *pos, const double *mass, double *acc, void *stream);
 

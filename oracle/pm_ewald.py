@@ -1,0 +1,101 @@
+"""CPU references for the long-range step (test infrastructure only).
+
+* ``pm_forces``: the particle-mesh step written plainly with numpy FFTs, in the order of
+  the method: CIC deposit on a cell-centred mesh, Poisson Green function filtered by
+  exp(-k^2 r_s^2) (the Gaussian split of Sec. 2.2, k_s = 1/(2 r_s)), CIC window divided
+  out twice, spectral gradient, inverse transforms, CIC interpolation.
+* ``ewald_reciprocal`` / ``ewald_total``: textbook Ewald summation with splitting
+  parameter alpha = 1/(2 r_s).  The real-space part is the erfc-truncated pair force of
+  the short range (Sec. 2.2 force law) summed over images without a cutoff; the
+  reciprocal part is the k-space sum of the same filtered Green function.  The total
+  does not depend on r_s, which the tests use as a pin.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import bruteforce, make_params
+
+
+def _cic(pos, box, M):
+    g = np.mod(pos, box) * (M / box) - 0.5
+    f = np.floor(g)
+    w1 = g - f
+    i0 = np.mod(f.astype(np.int64), M)
+    return i0, w1
+
+
+def pm_forces(pos, mass, box, rs, M, G=1.0):
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    i0, w1 = _cic(pos, box, M)
+    d = box / M
+    rho = np.zeros((M, M, M))
+    for c in range(8):
+        sx, sy, sz = c >> 2, (c >> 1) & 1, c & 1
+        wt = (w1[:, 0] if sx else 1 - w1[:, 0]) * (w1[:, 1] if sy else 1 - w1[:, 1]) * \
+             (w1[:, 2] if sz else 1 - w1[:, 2])
+        np.add.at(rho, ((i0[:, 0] + sx) % M, (i0[:, 1] + sy) % M, (i0[:, 2] + sz) % M), mass * wt / d ** 3)
+    rk = np.fft.rfftn(rho)
+    n1 = np.fft.fftfreq(M, 1.0 / M)
+    nz = np.arange(M // 2 + 1)
+    kx, ky, kz = np.meshgrid(n1 * 2 * np.pi / box, n1 * 2 * np.pi / box, nz * 2 * np.pi / box, indexing="ij")
+    k2 = kx ** 2 + ky ** 2 + kz ** 2
+    W = (np.sinc(kx * d / (2 * np.pi)) * np.sinc(ky * d / (2 * np.pi)) * np.sinc(kz * d / (2 * np.pi))) ** 2
+    nyq = np.zeros_like(k2, dtype=bool)
+    if M % 2 == 0:
+        nx_i, ny_i = np.meshgrid(n1, n1, indexing="ij")
+        nyq |= (np.abs(nx_i) == M // 2)[:, :, None] | (np.abs(ny_i) == M // 2)[:, :, None]
+        nyq[:, :, M // 2] = True
+    with np.errstate(divide="ignore", invalid="ignore"):
+        phi = -4 * np.pi * G * np.exp(-k2 * rs * rs) / (k2 * W * W)
+    phi[0, 0, 0] = 0.0
+    phi[nyq] = 0.0
+    out = np.zeros_like(pos)
+    for a, ka in enumerate((kx, ky, kz)):
+        am = np.fft.irfftn(-1j * ka * phi * rk, s=(M, M, M), axes=(0, 1, 2))
+        g = np.zeros(len(pos))
+        for c in range(8):
+            sx, sy, sz = c >> 2, (c >> 1) & 1, c & 1
+            wt = (w1[:, 0] if sx else 1 - w1[:, 0]) * (w1[:, 1] if sy else 1 - w1[:, 1]) * \
+                 (w1[:, 2] if sz else 1 - w1[:, 2])
+            g += wt * am[(i0[:, 0] + sx) % M, (i0[:, 1] + sy) % M, (i0[:, 2] + sz) % M]
+        out[:, a] = g
+    return out
+
+
+def ewald_reciprocal(pos, mass, box, rs, G=1.0, tol=1e-16, batch=2048):
+    """a_i = -G (4 pi / V) sum_{k != 0} exp(-k^2 r_s^2)/k^2 k Im(e^{i k x_i} conj(S(k))),
+    S(k) = sum_j m_j e^{i k x_j}; k over the lattice 2 pi n / L up to exp(-k^2 r_s^2) < tol."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    kcut = np.sqrt(-np.log(tol)) / rs
+    nmax = int(np.ceil(kcut * box / (2 * np.pi)))
+    r = np.arange(-nmax, nmax + 1)
+    n = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    # half space: each +-k pair once (the summand is even in k), doubled below
+    keep = (n[:, 0] > 0) | ((n[:, 0] == 0) & (n[:, 1] > 0)) | ((n[:, 0] == 0) & (n[:, 1] == 0) & (n[:, 2] > 0))
+    n = n[keep]
+    k = n * (2 * np.pi / box)
+    k2 = (k ** 2).sum(1)
+    sel = k2 <= kcut * kcut
+    k, k2 = k[sel], k2[sel]
+    coef = 2.0 * (-G) * 4 * np.pi / box ** 3 * np.exp(-k2 * rs * rs) / k2
+    acc = np.zeros_like(pos)
+    for b in range(0, len(k), batch):
+        kb = k[b:b + batch]
+        ph = pos @ kb.T                           # (N, K)
+        c, s = np.cos(ph), np.sin(ph)
+        Sc = mass @ c                             # Re S(k)
+        Ss = mass @ s                             # Im S(k)
+        im = s * Sc - c * Ss                      # Im(e^{i k x_i} conj(S))
+        acc += (im * coef[b:b + batch]) @ kb
+    return acc
+
+
+def ewald_total(pos, mass, box, rs, G=1.0):
+    """Newtonian periodic acceleration (mean density removed): erfc real-space sum over
+    images out to 12 r_s (must stay below box/2) plus the reciprocal sum."""
+    re = 12.0 * rs
+    if not re < 0.5 * box:
+        raise ValueError("r_s too large for a minimum-image real-space sum")
+    P = make_params(box=box, rs=rs, rcut=re, G=G)
+    return bruteforce(pos, mass, P, rc=re) + ewald_reciprocal(pos, mass, box, rs, G)

@@ -64,6 +64,7 @@ def lib():
         L.pm_long_range_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.hybrid_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.fmm_short_range_forces_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, dp, vp]
+        L.fmm_build_tree_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, vp, C.POINTER(vp)]
         L.fmm_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.fmm_set_timing.argtypes = [vp, C.c_int]
         L.fmm_copy_interactions.argtypes = [vp, C.c_int, vp, i64, C.POINTER(i64)]
@@ -120,6 +121,21 @@ class Tree:
         fresh = not self._h
         _check(lib().fmm_build_tree(C.byref(prm), self.n, _dev64(pos, (3,)) if self.n else None,
                                     _dev64(mass) if self.n else None, _stream(stream), C.byref(self._h)))
+        if fresh and self._timing:
+            _check(lib().fmm_set_timing(self._h, 1))
+        return self
+
+    def build_batched(self, pos, mass, per_box, offsets, stream=None):
+        """Forest over the boxes pos[offsets[b]:offsets[b+1]] (all per_box equal)."""
+        self.n = int(pos.shape[0])
+        if int(offsets[-1]) != self.n or mass.shape[0] != self.n:
+            raise FMMError(FMM_ERR_ARG, "offsets, pos and mass disagree")
+        nb = len(per_box)
+        arr = (Params * nb)(*per_box)
+        off = (C.c_int64 * (nb + 1))(*[int(v) for v in offsets])
+        fresh = not self._h
+        _check(lib().fmm_build_tree_batched(arr, nb, off, _dev64(pos, (3,)) if self.n else None,
+                                            _dev64(mass) if self.n else None, _stream(stream), C.byref(self._h)))
         if fresh and self._timing:
             _check(lib().fmm_set_timing(self._h, 1))
         return self

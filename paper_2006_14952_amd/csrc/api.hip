@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "state.h"
@@ -9,6 +10,9 @@
 namespace hfmm {
 const char *last_error();
 void clear_error();
+int pm_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
+              hipStream_t st);
+int add_into(double *acc, const double *other, int64_t n3, hipStream_t st);
 }  // namespace hfmm
 
 using namespace hfmm;
@@ -48,69 +52,10 @@ static void mark(fmm_tree *t, int k, hipStream_t st)
     if (t->timing) hipEventRecord(t->ev[k], st);
 }
 
-extern "C" {
-
-const char *fmm_last_error(void) { return last_error(); }
-
-const char *fmm_version(void) { return "hfmm 0.1 gfx950"; }
-
-int fmm_set_timing(fmm_tree *t, int on)
+// The stages of one short-range evaluation on a built tree (or forest of boxes).
+static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st)
 {
-    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
-    if (on && !t->events_ready) {
-        for (auto &e : t->ev)
-            if (hipEventCreate(&e) != hipSuccess) return set_error(FMM_ERR_HIP, "hipEventCreate");
-        t->events_ready = true;
-    }
-    t->timing = on ? 1 : 0;
-    return 0;
-}
-
-int fmm_build_tree(const fmm_params *P, int64_t n, const double *pos, const double *mass, void *stream,
-                   fmm_tree **out)
-{
-    clear_error();
-    if (int rc = check_params(P)) return rc;
-    if (!out) return set_error(FMM_ERR_ARG, "out is NULL");
-    if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
-    if (n > 0 && (!pos || !mass)) return set_error(FMM_ERR_ARG, "pos/mass is NULL");
-    hipStream_t st = (hipStream_t)stream;
-    fmm_tree *t = *out;
-    bool fresh = false;
-    if (!t) {
-        t = new (std::nothrow) fmm_tree();
-        if (!t) return set_error(FMM_ERR_NOMEM, "tree allocation");
-        fresh = true;
-    }
-    if (t->timing) hipEventRecord(t->ev[14], st);
-    int rc = tree_build(t, P, n, pos, mass, st);
-    if (rc) {
-        if (fresh) fmm_free_tree(t);
-        return rc;
-    }
-    if (t->timing) {
-        hipEventRecord(t->ev[15], st);
-        hipEventSynchronize(t->ev[15]);
-        t->stats.t_build_ms = ev_ms(t, 14, 15);
-    }
-    t->stats.n = n;
-    t->stats.n_cells = t->ncell;
-    t->stats.n_leaves = t->nleaf;
-    t->stats.max_level = t->nlevel - 1;
-    *out = t;
-    return 0;
-}
-
-int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *stream)
-{
-    clear_error();
-    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
-    if (int rc = check_params(P)) return rc;
-    if (P->box != t->box || P->n_crit != t->ncrit)
-        return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
-    if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
     if (P->learned) return set_error(FMM_ERR_ARG, "learned selector requested but no model is loaded");
-    hipStream_t st = (hipStream_t)stream;
     if (t->n == 0) return 0;
     int rc;
     mark(t, 0, st);
@@ -143,6 +88,100 @@ int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *
         S.t_total_ms = ev_ms(t, 0, 6);
     }
     return hip_check(hipGetLastError(), "short range forces");
+}
+
+static bool same_params(const fmm_params &a, const fmm_params &b)
+{
+    return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
+           a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned;
+}
+
+static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
+                        const int64_t *offsets, void *stream, fmm_tree **out)
+{
+    hipStream_t st = (hipStream_t)stream;
+    fmm_tree *t = *out;
+    bool fresh = false;
+    if (!t) {
+        t = new (std::nothrow) fmm_tree();
+        if (!t) return set_error(FMM_ERR_NOMEM, "tree allocation");
+        fresh = true;
+    }
+    if (t->timing) hipEventRecord(t->ev[14], st);
+    int rc = tree_build(t, P, n, pos, mass, nbox, offsets, st);
+    if (rc) {
+        if (fresh) fmm_free_tree(t);
+        return rc;
+    }
+    if (t->timing) {
+        hipEventRecord(t->ev[15], st);
+        hipEventSynchronize(t->ev[15]);
+        t->stats.t_build_ms = ev_ms(t, 14, 15);
+    }
+    t->stats.n = n;
+    t->stats.n_cells = t->ncell;
+    t->stats.n_leaves = t->nleaf;
+    t->stats.max_level = t->nlevel - 1;
+    *out = t;
+    return 0;
+}
+
+extern "C" {
+
+const char *fmm_last_error(void) { return last_error(); }
+
+const char *fmm_version(void) { return "hfmm 0.1 gfx950"; }
+
+int fmm_set_timing(fmm_tree *t, int on)
+{
+    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
+    if (on && !t->events_ready) {
+        for (auto &e : t->ev)
+            if (hipEventCreate(&e) != hipSuccess) return set_error(FMM_ERR_HIP, "hipEventCreate");
+        t->events_ready = true;
+    }
+    t->timing = on ? 1 : 0;
+    return 0;
+}
+
+int fmm_build_tree(const fmm_params *P, int64_t n, const double *pos, const double *mass, void *stream,
+                   fmm_tree **out)
+{
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (!out) return set_error(FMM_ERR_ARG, "out is NULL");
+    if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
+    if (n > 0 && (!pos || !mass)) return set_error(FMM_ERR_ARG, "pos/mass is NULL");
+    return build_common(P, n, pos, mass, 1, nullptr, stream, out);
+}
+
+int fmm_build_tree_batched(const fmm_params *per_box, int nbox, const int64_t *offsets, const double *pos,
+                           const double *mass, void *stream, fmm_tree **out)
+{
+    clear_error();
+    if (!per_box || !offsets || !out) return set_error(FMM_ERR_ARG, "NULL argument");
+    if (nbox < 1 || nbox > 65536) return set_error(FMM_ERR_ARG, "nbox must be in [1, 65536]");
+    if (int rc = check_params(&per_box[0])) return rc;
+    for (int b = 1; b < nbox; ++b)
+        if (!same_params(per_box[b], per_box[0]))
+            return set_error(FMM_ERR_ARG, "all boxes of a batch must share their parameters (box %d differs)", b);
+    if (offsets[0] != 0) return set_error(FMM_ERR_ARG, "offsets[0] must be 0");
+    for (int b = 0; b < nbox; ++b)
+        if (offsets[b + 1] < offsets[b]) return set_error(FMM_ERR_ARG, "offsets must be non-decreasing");
+    int64_t n = offsets[nbox];
+    if (n > 0 && (!pos || !mass)) return set_error(FMM_ERR_ARG, "pos/mass is NULL");
+    return build_common(&per_box[0], n, pos, mass, nbox, offsets, stream, out);
+}
+
+int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *stream)
+{
+    clear_error();
+    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
+    if (int rc = check_params(P)) return rc;
+    if (P->box != t->box || P->n_crit != t->ncrit)
+        return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
+    if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
+    return run_forces(t, P, acc, (hipStream_t)stream);
 }
 
 int fmm_get_stats(const fmm_tree *tc, fmm_stats *out)
@@ -208,22 +247,44 @@ int fmm_load_mac_model(const char *path)
 int pm_long_range_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass,
                          double *acc, void *stream)
 {
-    (void)P; (void)mesh; (void)n; (void)pos; (void)mass; (void)acc; (void)stream;
-    return set_error(FMM_ERR_ARG, "particle-mesh step not available in this build");
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
+    if (n > 0 && (!pos || !mass || !acc)) return set_error(FMM_ERR_ARG, "NULL pointer");
+    return pm_forces(P, mesh, n, pos, mass, acc, (hipStream_t)stream);
 }
 
 int hybrid_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
                   void *stream)
 {
-    (void)P; (void)mesh; (void)n; (void)pos; (void)mass; (void)acc; (void)stream;
-    return set_error(FMM_ERR_ARG, "particle-mesh step not available in this build");
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
+    if (n == 0) return 0;
+    if (!pos || !mass || !acc) return set_error(FMM_ERR_ARG, "NULL pointer");
+    hipStream_t st = (hipStream_t)stream;
+    if (int rc = pm_forces(P, mesh, n, pos, mass, acc, st)) return rc;
+    fmm_tree *t = nullptr;
+    if (int rc = fmm_build_tree(P, n, pos, mass, stream, &t)) return rc;
+    DevBuf sr;
+    int rc = grow(sr, (size_t)n * 3 * sizeof(double));
+    if (!rc) rc = fmm_short_range_forces(t, P, ptr<double>(sr), stream);
+    if (!rc) rc = add_into(acc, ptr<double>(sr), 3 * n, st);
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "hybrid");
+    if (sr.p) (void)hipFree(sr.p);
+    fmm_free_tree(t);
+    return rc;
 }
 
 int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets, const double *pos,
                                    const double *mass, double *acc, void *stream)
 {
-    (void)per_box; (void)nbox; (void)offsets; (void)pos; (void)mass; (void)acc; (void)stream;
-    return set_error(FMM_ERR_ARG, "batched form not available in this build");
+    static std::mutex mu;
+    static fmm_tree *forest = nullptr;  // reused across calls: steady-state calls allocate nothing
+    std::lock_guard<std::mutex> lk(mu);
+    if (int rc = fmm_build_tree_batched(per_box, nbox, offsets, pos, mass, stream, &forest)) return rc;
+    if (forest->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
+    return run_forces(forest, &per_box[0], acc, (hipStream_t)stream);
 }
 
 void fmm_free_tree(fmm_tree *t)
@@ -232,7 +293,7 @@ void fmm_free_tree(fmm_tree *t)
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->litems[0], &t->litems[1], &t->litems[2], &t->lnext[0], &t->lnext[1],
-                      &t->lnext[2], &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag};
+                      &t->lnext[2], &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff};
     for (DevBuf *b : bufs) free_buf(*b);
     if (t->host) (void)hipHostFree(t->host);
     if (t->events_ready)

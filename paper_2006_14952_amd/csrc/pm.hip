@@ -1,0 +1,200 @@
+// Long-range force by the particle-mesh method (Sec. 2.2): the Poisson Green function
+// filtered by exp(-k^2 r_s^2), so that PM + the erfc-truncated short range sums to
+// Newtonian gravity (the split of the force law g(r) of Sec. 2.2).
+//
+//   CIC deposit -> rho(x);  FFT;  phi_k = -4 pi G rho_k exp(-k^2 r_s^2) / (k^2 W(k)^2);
+//   a_k = -i k phi_k (three components);  inverse FFTs;  CIC interpolation.
+// W(k) = prod_i sinc^2(k_i Delta / 2) is the CIC window, divided out once for the
+// deposit and once for the interpolation.  The k = 0 mode is dropped (mean density is
+// cancelled by the expanding background).  FFTs are hipFFT (double precision).
+#include <hipfft/hipfft.h>
+#include <math.h>
+
+#include <map>
+#include <mutex>
+
+#include "state.h"
+
+namespace hfmm {
+
+struct PMPlan {
+    int mesh = 0;
+    hipfftHandle r2c = 0, c2r = 0;
+    DevBuf rho, rhok, work, amesh;
+};
+
+static std::mutex g_pm_mu;
+static std::map<int, PMPlan *> g_pm;  // one plan set per mesh size per process
+
+static int pm_plan(int mesh, PMPlan **out)
+{
+    std::lock_guard<std::mutex> lk(g_pm_mu);
+    auto it = g_pm.find(mesh);
+    if (it != g_pm.end()) {
+        *out = it->second;
+        return 0;
+    }
+    PMPlan *p = new PMPlan();
+    p->mesh = mesh;
+    if (hipfftPlan3d(&p->r2c, mesh, mesh, mesh, HIPFFT_D2Z) != HIPFFT_SUCCESS ||
+        hipfftPlan3d(&p->c2r, mesh, mesh, mesh, HIPFFT_Z2D) != HIPFFT_SUCCESS) {
+        delete p;
+        return set_error(FMM_ERR_HIP, "hipfftPlan3d(%d) failed", mesh);
+    }
+    size_t nr = (size_t)mesh * mesh * mesh, nc = (size_t)mesh * mesh * (mesh / 2 + 1);
+    int rc = grow(p->rho, nr * 8) | grow(p->rhok, nc * 16) | grow(p->work, nc * 16) | grow(p->amesh, 3 * nr * 8);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    g_pm[mesh] = p;
+    *out = p;
+    return 0;
+}
+
+__device__ __forceinline__ void cic_weights(double x, double inv_d, int M, int &i0, double &w1)
+{
+    // cell-centred mesh: node i at (i + 0.5) Delta
+    double g = x * inv_d - 0.5;
+    double f = floor(g);
+    w1 = g - f;
+    int i = (int)f;
+    i0 = ((i % M) + M) % M;
+}
+
+__global__ void k_cic_deposit(const double *__restrict__ pos, const double *__restrict__ mass, int n, double box,
+                              int M, double inv_vol, double *__restrict__ rho)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double inv_d = M / box;
+    int i[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * (size_t)p + a];
+        x -= box * floor(x / box);
+        cic_weights(x, inv_d, M, i[a], w[a]);
+    }
+    double m = mass[p] * inv_vol;
+    for (int c = 0; c < 8; ++c) {
+        int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
+        double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
+        size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
+        atomicAdd(&rho[idx], m * wt);
+    }
+}
+
+__device__ __forceinline__ double sinc(double x) { return fabs(x) < 1e-8 ? 1.0 : sin(x) / x; }
+
+// a_k component `axis` from rho_k; includes the 1/M^3 of the inverse transform
+__global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipfftDoubleComplex *__restrict__ out,
+                             int M, double box, double rs, double G, int axis)
+{
+    int Mh = M / 2 + 1;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t nc = (size_t)M * M * Mh;
+    if (t >= nc) return;
+    int kz = (int)(t % Mh), ky = (int)((t / Mh) % M), kx = (int)(t / ((size_t)Mh * M));
+    int nx = kx <= M / 2 ? kx : kx - M, ny = ky <= M / 2 ? ky : ky - M, nz = kz;
+    double twopi_L = 2.0 * M_PI / box, d = box / M;
+    double k0 = nx * twopi_L, k1 = ny * twopi_L, k2 = nz * twopi_L;
+    double k2s = k0 * k0 + k1 * k1 + k2 * k2;
+    hipfftDoubleComplex r = rhok[t], o;
+    if (k2s == 0.0 || (M % 2 == 0 && (nx == M / 2 || ny == M / 2 || nz == M / 2))) {
+        o.x = 0; o.y = 0;  // k = 0 and the unpaired Nyquist planes carry no gradient
+        out[t] = o;
+        return;
+    }
+    double W = sinc(0.5 * k0 * d) * sinc(0.5 * k1 * d) * sinc(0.5 * k2 * d);
+    W = W * W;
+    double phi = -4.0 * M_PI * G * exp(-k2s * rs * rs) / (k2s * W * W);
+    double ka = axis == 0 ? k0 : (axis == 1 ? k1 : k2);
+    double s = phi * ka / ((double)M * M * M);  // a_k = -i k phi_k
+    o.x = s * r.y;
+    o.y = -s * r.x;
+    out[t] = o;
+}
+
+__global__ void k_cic_interp(const double *__restrict__ pos, int n, double box, int M, const double *__restrict__ am,
+                             double *__restrict__ acc)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double inv_d = M / box;
+    int i[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * (size_t)p + a];
+        x -= box * floor(x / box);
+        cic_weights(x, inv_d, M, i[a], w[a]);
+    }
+    size_t nr = (size_t)M * M * M;
+    double g[3] = {0, 0, 0};
+    for (int c = 0; c < 8; ++c) {
+        int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
+        double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
+        size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
+        for (int a = 0; a < 3; ++a) g[a] += wt * am[a * nr + idx];
+    }
+    for (int a = 0; a < 3; ++a) acc[3 * (size_t)p + a] = g[a];
+}
+
+__global__ void k_add3(double *__restrict__ acc, const double *__restrict__ other, size_t n3)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) acc[i] += other[i];
+}
+
+__global__ void k_check_finite(const double *__restrict__ pos, size_t n3, int *bad)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3 && !isfinite(pos[i])) *bad = 1;
+}
+
+int pm_forces(const fmm_params *P, int mesh, int64_t n64, const double *pos, const double *mass, double *acc,
+              hipStream_t st)
+{
+    if (mesh < 8 || mesh > 1024) return set_error(FMM_ERR_ARG, "mesh must be in [8, 1024]");
+    if (n64 < 0 || n64 > ((int64_t)1 << 30)) return set_error(FMM_ERR_ARG, "n out of range");
+    int n = (int)n64;
+    if (n == 0) return 0;
+    PMPlan *pl;
+    if (int rc = pm_plan(mesh, &pl)) return rc;
+    std::lock_guard<std::mutex> lk(g_pm_mu);  // plans and mesh buffers are shared per mesh size
+    size_t nr = (size_t)mesh * mesh * mesh, nc = (size_t)mesh * mesh * (mesh / 2 + 1);
+    int *bad = ptr<int>(pl->amesh);  // scratch flag in the (not yet used) output mesh
+    hipMemsetAsync(bad, 0, sizeof(int), st);
+    k_check_finite<<<(unsigned)((3 * (size_t)n + 255) / 256), 256, 0, st>>>(pos, 3 * (size_t)n, bad);
+    int hbad = 0;
+    hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) return set_error(FMM_ERR_HIP, "pm sync");
+    if (hbad) return set_error(FMM_ERR_NAN, "non-finite particle position");
+    hipMemsetAsync(pl->rho.p, 0, nr * 8, st);
+    double d = P->box / mesh;
+    k_cic_deposit<<<(n + 255) / 256, 256, 0, st>>>(pos, mass, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    hipfftSetStream(pl->r2c, st);
+    hipfftSetStream(pl->c2r, st);
+    if (hipfftExecD2Z(pl->r2c, ptr<double>(pl->rho), ptr<hipfftDoubleComplex>(pl->rhok)) != HIPFFT_SUCCESS)
+        return set_error(FMM_ERR_HIP, "hipfftExecD2Z");
+    for (int axis = 0; axis < 3; ++axis) {
+        k_green_grad<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(ptr<hipfftDoubleComplex>(pl->rhok),
+                                                                  ptr<hipfftDoubleComplex>(pl->work), mesh, P->box,
+                                                                  P->r_s, P->G, axis);
+        if (hipfftExecZ2D(pl->c2r, ptr<hipfftDoubleComplex>(pl->work), ptr<double>(pl->amesh) + axis * nr) !=
+            HIPFFT_SUCCESS)
+            return set_error(FMM_ERR_HIP, "hipfftExecZ2D");
+    }
+    k_cic_interp<<<(n + 255) / 256, 256, 0, st>>>(pos, n, P->box, mesh, ptr<double>(pl->amesh), acc);
+    int rc = hip_check(hipGetLastError(), "pm");
+    if (rc == 0) rc = hip_check(hipStreamSynchronize(st), "pm");  // mesh buffers are reused by the next call
+    return rc;
+}
+
+int add_into(double *acc, const double *other, int64_t n3, hipStream_t st)
+{
+    if (n3 <= 0) return 0;
+    k_add3<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(acc, other, (size_t)n3);
+    return hip_check(hipGetLastError(), "add");
+}
+
+}  // namespace hfmm

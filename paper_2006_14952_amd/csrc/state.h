@@ -10,10 +10,14 @@ struct fmm_tree {
     double box = 1.0;
     int ncrit = 32;
     int ncell = 0, nleaf = 0, nlevel = 0;  // levels 0 .. nlevel-1 are non-empty
+    int nbox = 1;                          // roots: one per box of a batch
+    std::vector<int> hboxoff;              // particle offsets of the boxes (host copy)
     std::vector<int> lvl_beg;              // cells of level l: lvl_beg[l] .. lvl_beg[l+1]-1
 
     // particles, Morton order
     hfmm::DevBuf keys[2], idx[2];
+    int sorted = 0;               // which of keys/idx holds the sorted order
+    hfmm::DevBuf boxoff;          // int[nbox + 1] particle offsets of the boxes
     hfmm::DevBuf xs, ys, zs, ms;  // wrapped FP64 positions and masses
     hfmm::DevBuf perm;            // sorted index -> caller index
     hfmm::DevBuf leaf_of;         // sorted index -> leaf cell
@@ -49,7 +53,8 @@ struct fmm_tree {
 };
 
 namespace hfmm {
-int tree_build(fmm_tree *t, const fmm_params *P, int64_t n, const double *pos, const double *mass, hipStream_t st);
+int tree_build(fmm_tree *t, const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
+               const int64_t *offsets, hipStream_t st);
 int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int upward(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);

@@ -148,8 +148,9 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
         const int parentA = a.cells[A].parent;
         const bool leafA = xln_nchild(ga.x) == 0;
         const int lvA = xln_level(ga.x);
-        const bool root = A == 0;
+        const bool root = lvA == 0;  // a root meets the 27 periodic images of itself
         int ninh = 27, ichunk = 0;
+        if (root && a.cells[A].end == a.cells[A].beg) ninh = 0;  // empty box of a batch: nothing to do
         if (!root) {
             ninh = a.cnt[2 * a.ncell + parentA];
             ichunk = a.head[2 * a.ncell + parentA];
@@ -168,7 +169,8 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
                 if (lane < kk) it = stk[sp + lane];
             } else if (ip < ninh) {
                 kk = ninh - ip < 64 ? ninh - ip : 64;
-                if (lane < kk) it = root ? (uint32_t)(ip + lane) : a.items[2][(size_t)ichunk * kChunk + lane];
+                if (lane < kk)
+                    it = root ? ((uint32_t)A << 5 | (uint32_t)(ip + lane)) : a.items[2][(size_t)ichunk * kChunk + lane];
                 ip += kk;
                 if (!root && ip < ninh) ichunk = a.next[2][ichunk];
             } else {

@@ -66,8 +66,30 @@ constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kRsThreads * kRsRounds;
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restrict__ keys, int n, int shift,
-                                                        int nblocks, int *__restrict__ hist)
+// Box of original particle index v: the largest b with off[b] <= v (empty boxes skipped).
+__device__ inline int box_of(const int *off, int nbox, uint32_t v)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= (int)v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Radix digit of an element: 8 bits of the Morton key, or (for the passes that group the
+// boxes of a batch) 8 bits of the box of its original index.
+__device__ inline int rs_digit(uint64_t key, uint32_t val, int shift, const int *boxoff, int nbox)
+{
+    if (boxoff) return (box_of(boxoff, nbox, val) >> shift) & 0xff;
+    return (int)((key >> shift) & 0xff);
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ vals, int n, int shift,
+                                                        const int *__restrict__ boxoff, int nbox, int nblocks,
+                                                        int *__restrict__ hist)
 {
     __shared__ int h[256];
     h[threadIdx.x] = 0;
@@ -75,7 +97,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
     int base = blockIdx.x * kRsTile;
     for (int k = 0; k < kRsRounds; ++k) {
         int i = base + k * kRsThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xff], 1);
+        if (i < n) atomicAdd(&h[rs_digit(keys[i], vals[i], shift, boxoff, nbox)], 1);
     }
     __syncthreads();
     hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
@@ -83,7 +105,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-                                                           uint32_t *__restrict__ vout, int n, int shift, int nblocks,
+                                                           uint32_t *__restrict__ vout, int n, int shift,
+                                                           const int *__restrict__ boxoff, int nbox, int nblocks,
                                                            const int *__restrict__ offs)
 {
     __shared__ int cnt[4][256];
@@ -103,7 +126,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
         bool ok = i < n;
         key[r] = ok ? kin[i] : 0;
         val[r] = ok ? vin[i] : 0;
-        int d = (int)((key[r] >> shift) & 0xff);
+        int d = rs_digit(key[r], val[r], shift, boxoff, nbox);
         uint64_t peers = __ballot(ok);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -129,29 +152,36 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
         if (pos[r] < 0) continue;
-        int d = (int)((key[r] >> shift) & 0xff);
+        int d = rs_digit(key[r], val[r], shift, boxoff, nbox);
         int o = boff[d] + cnt[w][d] + pos[r];
         kout[o] = key[r];
         vout[o] = val[r];
     }
 }
 
-static int radix_sort(fmm_tree *t, int n, hipStream_t st)
+// 8 passes over the Morton key, then (batches) 1 or 2 passes over the box index, so the
+// order is by box, then by key; stable throughout.  Sets t->sorted to the result buffer.
+static int radix_sort(fmm_tree *t, int n, int nbox, hipStream_t st)
 {
     int nb = (n + kRsTile - 1) / kRsTile;
     if (int rc = grow(t->nch, (size_t)256 * nb * 2 * sizeof(int))) return rc;
     int *hist = ptr<int>(t->nch), *offs = hist + 256 * nb;
+    const int *boxoff = ptr<int>(t->boxoff);
+    int npass = 8 + (nbox > 1) + (nbox > 256);
     int cur = 0;
-    for (int pass = 0; pass < 8; ++pass) {
-        int shift = 8 * pass;
-        k_rs_hist<<<nb, kRsThreads, 0, st>>>(ptr<uint64_t>(t->keys[cur]), n, shift, nb, hist);
+    for (int pass = 0; pass < npass; ++pass) {
+        bool bpass = pass >= 8;
+        int shift = bpass ? 8 * (pass - 8) : 8 * pass;
+        const int *bo = bpass ? boxoff : nullptr;
+        k_rs_hist<<<nb, kRsThreads, 0, st>>>(ptr<uint64_t>(t->keys[cur]), ptr<uint32_t>(t->idx[cur]), n, shift, bo,
+                                             nbox, nb, hist);
         if (int rc = scan_exclusive(hist, offs, 256 * nb, nullptr, st, t->scan_tmp)) return rc;
         k_rs_scatter<<<nb, kRsThreads, 0, st>>>(ptr<uint64_t>(t->keys[cur]), ptr<uint32_t>(t->idx[cur]),
                                                 ptr<uint64_t>(t->keys[cur ^ 1]), ptr<uint32_t>(t->idx[cur ^ 1]), n,
-                                                shift, nb, offs);
+                                                shift, bo, nbox, nb, offs);
         cur ^= 1;
     }
-    // 8 passes: the sorted data is back in buffer 0
+    t->sorted = cur;
     return hip_check(hipGetLastError(), "radix sort");
 }
 
@@ -177,17 +207,20 @@ __global__ void k_gather(const double *__restrict__ pos, const double *__restric
 // ---------------------------------------------------------------------------
 // cells, level by level
 
-__global__ void k_root(Cell *cells, int n)
+// one root (level 0, the whole box) per box of the batch
+__global__ void k_roots(Cell *cells, int nbox, const int *__restrict__ boxoff)
 {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
     Cell c;
     c.xln = pack_xln(0, 0, 0);
     c.iy = c.iz = 0;
     c.pad = 0;
-    c.beg = 0;
-    c.end = n;
+    c.beg = boxoff[b];
+    c.end = boxoff[b + 1];
     c.child = -1;
     c.parent = -1;
-    cells[0] = c;
+    cells[b] = c;
 }
 
 // first index in [lo, hi) whose key is >= v
@@ -288,9 +321,11 @@ __global__ void k_rel32(const Cell *__restrict__ cells, const int *__restrict__ 
 
 static inline int blocks(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos, const double *mass, hipStream_t st)
+int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos, const double *mass, int nbox,
+               const int64_t *hoff, hipStream_t st)
 {
     if (n64 < 0 || n64 > (int64_t)1 << 30) return set_error(FMM_ERR_ARG, "n = %lld out of range", (long long)n64);
+    if (nbox < 1 || nbox > 65536) return set_error(FMM_ERR_ARG, "nbox = %d out of range", nbox);
     int n = (int)n64;
     t->n = n;
     t->box = P->box;
@@ -301,8 +336,12 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     if (!rc) rc = grow(t->xs, nn * 8) | grow(t->ys, nn * 8) | grow(t->zs, nn * 8) | grow(t->ms, nn * 8);
     if (!rc) rc = grow(t->perm, nn * 4) | grow(t->leaf_of, nn * 4) | grow(t->rel32, nn * 16) | grow(t->nearf, nn * 24);
     if (!rc) rc = grow(t->flag, 64 * sizeof(int));
-    if (!rc) rc = grow(t->cells, sizeof(Cell) * 1024);
+    if (!rc) rc = grow(t->cells, sizeof(Cell) * (1024 + (size_t)nbox)) | grow(t->boxoff, (size_t)(nbox + 1) * 4);
     if (rc) return rc;
+    t->nbox = nbox;
+    t->hboxoff.resize(nbox + 1);
+    for (int b = 0; b <= nbox; ++b) t->hboxoff[b] = hoff ? (int)hoff[b] : (b ? n : 0);
+    hipMemcpyAsync(t->boxoff.p, t->hboxoff.data(), (size_t)(nbox + 1) * 4, hipMemcpyHostToDevice, st);
     if (!t->host) {
         if (hipHostMalloc((void **)&t->host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
             return set_error(FMM_ERR_NOMEM, "pinned host buffer");
@@ -311,17 +350,17 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     hipMemsetAsync(bad, 0, sizeof(int), st);
     if (n > 0) {
         k_keys<<<blocks(n, 256), 256, 0, st>>>(pos, n, P->box, ptr<uint64_t>(t->keys[0]), ptr<uint32_t>(t->idx[0]), bad);
-        if ((rc = radix_sort(t, n, st))) return rc;
-        k_gather<<<blocks(n, 256), 256, 0, st>>>(pos, mass, ptr<uint32_t>(t->idx[0]), n, P->box, ptr<double>(t->xs),
+        if ((rc = radix_sort(t, n, nbox, st))) return rc;
+        k_gather<<<blocks(n, 256), 256, 0, st>>>(pos, mass, ptr<uint32_t>(t->idx[t->sorted]), n, P->box, ptr<double>(t->xs),
                                                  ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms),
                                                  ptr<int>(t->perm));
     }
-    k_root<<<1, 1, 0, st>>>(ptr<Cell>(t->cells), n);
+    k_roots<<<blocks(nbox, 64), 64, 0, st>>>(ptr<Cell>(t->cells), nbox, ptr<int>(t->boxoff));
     if ((rc = hip_check(hipGetLastError(), "tree keys"))) return rc;
 
     t->lvl_beg.assign(1, 0);
-    t->lvl_beg.push_back(1);
-    const uint64_t *keys = ptr<uint64_t>(t->keys[0]);
+    t->lvl_beg.push_back(nbox);
+    const uint64_t *keys = ptr<uint64_t>(t->keys[t->sorted]);
     int l = 0;
     for (; l < kMaxLevel && n > 0; ++l) {
         int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;

@@ -1,0 +1,114 @@
+"""GPU parity of the long-range step, the hybrid total and the batched form."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err
+from oracle import pm_ewald
+from paper_2006_14952_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hf = pytest.importorskip("paper_2006_14952_amd")
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def rms_rel(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum(1).mean() / (b ** 2).sum(1).mean()))
+
+
+@pytest.mark.parametrize("M", [16, 64, 33])
+def test_pm_matches_cpu_reference(M):
+    pos, m = inputs.clustered(3000, 4, inputs.rng_for(301, M))
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, p=4)
+    got = hf.pm_long_range(dev(pos), dev(m), prm, M).cpu().numpy()
+    ref = pm_ewald.pm_forces(pos, m, 1.0, rs, M)
+    assert rms_rel(got, ref) < 1e-10
+    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+def test_pm_edge_cases():
+    prm = hf.params(r_s=0.02, p=4)
+    out = hf.pm_long_range(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
+                           torch.zeros(0, dtype=torch.float64, device="cuda"), prm, 32)
+    assert out.shape == (0, 3)
+    pos = np.random.default_rng(1).random((10, 3))
+    pos[3, 2] = np.inf
+    with pytest.raises(hf.FMMError) as ei:
+        hf.pm_long_range(dev(pos), dev(np.ones(10)), prm, 32)
+    assert ei.value.code == hf.FMM_ERR_NAN
+    with pytest.raises(hf.FMMError):
+        hf.pm_long_range(dev(np.zeros((4, 3))), dev(np.ones(4)), prm, 4)
+
+
+def test_hybrid_equals_parts_and_approaches_ewald():
+    pos, m = inputs.clustered(4000, 5, inputs.rng_for(302))
+    M = 32
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, r_cut=4.5 * rs, theta=0.4, p=6, n_crit=16)
+    tot = hf.hybrid(dev(pos), dev(m), prm, M).cpu().numpy()
+    sr = oracle.fmm(pos, m, oracle.make_params(rs=rs, rcut=4.5 * rs, theta=0.4, p=6, ncrit=16)).acc
+    lr = pm_ewald.pm_forces(pos, m, 1.0, rs, M)
+    assert rms_rel(tot, sr + lr) < 1e-9
+    ew = pm_ewald.ewald_total(pos, m, 1.0, rs)
+    assert rms_rel(tot, ew) < 2e-2
+
+
+def _batch(nb, seed):
+    rng = inputs.rng_for(303, seed)
+    sizes = [0, 1, 2] + list(rng.integers(100, 3000, nb - 3))
+    rng.shuffle(sizes)
+    boxes = [inputs.clustered(int(n), 2, rng) if n > 2 else (rng.random((int(n), 3)), np.full(int(n), 0.5))
+             for n in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate([b[0] for b in boxes]) if off[-1] else np.zeros((0, 3))
+    m = np.concatenate([b[1] for b in boxes])
+    return boxes, off, pos, m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_matches_oracle_per_box(precision):
+    boxes, off, pos, m = _batch(9, precision)
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=5, n_crit=16, precision=precision)
+    got = hf.short_range_batched(dev(pos), dev(m), [prm] * len(boxes), off).cpu().numpy()
+    op = oracle.make_params(rs=0.02, rcut=0.09, theta=0.4, p=5, ncrit=16)
+    for b, (bp, bm) in enumerate(boxes):
+        if len(bp) == 0:
+            continue
+        ref = oracle.fmm(bp, bm, op).acc
+        e = rel_err(got[off[b]:off[b + 1]], ref)
+        if precision == 0:
+            assert e.max() < 1e-9, (b, e.max())
+        else:
+            assert np.percentile(e, 99) < 1e-4, (b, np.percentile(e, 99))
+
+
+def test_batched_forest_equals_single_box_runs():
+    boxes, off, pos, m = _batch(7, 5)
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=8, precision=1)
+    t = hf.Tree().build_batched(dev(pos), dev(m), [prm] * len(boxes), off)
+    got = t.short_range(prm).cpu().numpy()
+    st = t.stats()
+    n_m2l = n_p2p = 0
+    for b, (bp, bm) in enumerate(boxes):
+        if len(bp) == 0:
+            continue
+        s = hf.Tree().build(dev(bp), dev(bm), prm)
+        single = s.short_range(prm).cpu().numpy()
+        ss = s.stats()
+        n_m2l += ss["n_m2l"]
+        n_p2p += ss["n_p2p"]
+        np.testing.assert_allclose(got[off[b]:off[b + 1]], single, rtol=1e-6, atol=1e-9 * np.abs(single).max())
+    assert st["n_m2l"] == n_m2l and st["n_p2p"] == n_p2p
+
+
+def test_batched_rejects_mixed_params():
+    boxes, off, pos, m = _batch(4, 9)
+    a = hf.params(r_s=0.02, p=4)
+    b = hf.params(r_s=0.02, p=5)
+    with pytest.raises(hf.FMMError):
+        hf.short_range_batched(dev(pos), dev(m), [a, b, a, a], off)
