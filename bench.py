@@ -44,6 +44,8 @@ def main():
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--n-crit", type=int, default=None)
+    ap.add_argument("--learned", action="store_true",
+                    help="per-pair acceptance and order from the trained selector (packaged model file)")
     ap.add_argument("--cpu-sample", type=int, default=20000, help="oracle targets for cpu_baseline (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes (calibrates HBM counters) and exit")
@@ -81,7 +83,14 @@ def main():
         pos_np, m_np = inputs.make(args.workload)
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                    precision=wl["precision"])
+                    precision=wl["precision"], learned=int(args.learned))
+    sel = None
+    if args.learned:
+        from paper_2006_14952_amd import learned
+        learned.load_model()
+        hdr = learned.read_model(learned.DEFAULT_MODEL)
+        sel = "learned selector (theta_max %.2f, eps %.0e, safety %d)" % (hdr["theta_max"], hdr["eps"],
+                                                                          hdr["safety"])
     dev = torch.device("cuda:0")
     pos = torch.tensor(pos_np, device=dev)
     mass = torch.tensor(m_np, device=dev)
@@ -138,14 +147,17 @@ def main():
         "config": {"workload": "%s N=%d (%s), p=%d, theta=%.2f, n_crit=%d, r_s=%.6g, r_cut=%.6g, %s" % (
             args.workload, n, cfg["kind"] + (" %d boxes in one forest" % len(boxes) if batched else ""),
             pr["p"], wl["theta"], wl["n_crit"], pr["rs"], pr["rcut"],
-            "FP32 P2P/M2L + FP64 positions/offsets/final sum" if wl["precision"] else "FP64"),
-            "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"]},
+            "FP32 P2P/M2L + FP64 positions/offsets/final sum" if wl["precision"] else "FP64")
+            + (", " + sel + " in place of p and theta" if sel else ""),
+            "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
+            "selector": sel or "fixed p and theta"},
         "roofline": {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_launch, "p2p_ms_per_launch": p2p_s * 1e3},
         "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
         "build_ms": float(np.mean(build_ms)),
-        "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit")},
+        "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit",
+                                      "n_m2l_by_order")},
     }
 
     if args.cpu_sample > 0 and batched:

@@ -78,7 +78,7 @@ typedef struct fmm_stats {
     int64_t p2p_pairs;         /* listed particle pairs (sum over P2P leaf pairs of n_A n_B) */
     int64_t n_visit;           /* cell pairs examined by the traversal */
     int64_t levels_traversed;
-    int64_t reserved_i[7];
+    int64_t n_m2l_by_order[7]; /* learned selector: accepted pairs at order 2..8 (else 0) */
     double t_tree_ms, t_upward_ms, t_traverse_ms, t_m2l_ms, t_p2p_ms, t_downward_ms, t_total_ms;
     double t_build_ms;         /* last fmm_build_tree */
     double reserved_d[8];
@@ -147,9 +147,62 @@ int fmm_set_timing(fmm_tree *tree, int on);
  * cap triples are written and *count receives the number written. */
 int fmm_copy_interactions(const fmm_tree *tree, int kind, uint64_t *out, int64_t cap, int64_t *count);
 
-/* Load the learned MAC/order selector from a model file written by fmm_save_mac_model
- * (global for the process; path NULL unloads it). */
+/* ---- learned acceptance / order selector -----------------------------------------
+ * A small MLP (16 features -> 64 -> 64 -> 8 classes, ReLU) decides, for every cell pair
+ * that passes MAC items 1 and 3 (Sec. 2.3) and has L/S_c <= theta_max, whether to open it
+ * (class 0) or accept it with an M2L of order c + 1 (classes 1..7, orders 2..8).  Pairs
+ * that fail items 1 or 3, or exceed theta_max, are handled by the plain rules (neglect /
+ * open), so the selector never accepts a pair the hard rules forbid.  Used when
+ * params->learned = 1 (expansions are then kept at order 8).  One model per process.
+ * Parameter vector (FP32, 5768 floats, row-major [in][out]): W1 16x64 at 0, b1 at 1024,
+ * W2 64x64 at 1088, b2 at 5184, W3 64x8 at 5248, b3 at 5760.  Features are normalised
+ * as (x - mu) * isd before the first layer. */
+
+/* Load a model file: "HFMMMAC1", int32 version (1), nfeat (16), hidden (64), nclass (8);
+ * double theta_max, eps_label; int32 safety, reserved; float mu[16], isd[16],
+ * params[5768], adam_m[5768], adam_v[5768]; int64 step; int32 length; JSON training
+ * configuration.  path NULL unloads the model.  Weights are rounded to BF16 for the
+ * selector's MFMA inference. */
 int fmm_load_mac_model(const char *path);
+
+/* Install a model from HOST arrays (params 5768, mu 16, isd 16); theta_max in (0, 0.75),
+ * safety in [0, 6] orders added to the predicted order (capped at 8).  NULL params
+ * unloads. */
+int fmm_set_mac_model(const float *params, const float *mu, const float *isd, double theta_max, int safety);
+
+/* Training data: on a built tree, export every candidate pair of a traversal with the
+ * plain MAC of params (candidates: pass items 1 and 3, L/S_c <= theta_max) and label it
+ * with the smallest order p in 2..8 whose error, measured by the library against the
+ * exact pair force (FP64), satisfies max_i |a_i^(p) - a_i^direct| / |acc_ref_i| <= eps over
+ * the sink's particles (class p - 1), else class 0.  acc_ref: DEVICE (n,3) total
+ * short-range acceleration in caller order.  Only candidates whose (sink index + list
+ * position) is a multiple of stride are labelled (stride >= 1, a deterministic subsample).
+ * Outputs (DEVICE): feats (cap x 16 floats), labels (cap ints), errs (cap x 7 floats, per
+ * order, may be NULL), pairs (cap x 3: sink cell key, source cell key, image; keys as in
+ * fmm_copy_interactions; may be NULL).  *count (HOST) receives the number written (the
+ * order of the records is not deterministic).  Pairs with n_A n_B > 2^18 are skipped. */
+int fmm_mac_training_data(fmm_tree *tree, const fmm_params *params, double theta_max, const double *acc_ref,
+                          double eps, int stride, float *feats, int *labels, float *errs, uint64_t *pairs,
+                          int64_t cap, int64_t *count, void *stream);
+
+/* FP32 forward pass of a parameter vector (DEVICE params, mu, isd, X (B x 16)) -> logits
+ * (DEVICE B x 8). */
+int fmm_mlp_forward(const float *params, const float *mu, const float *isd, const float *X, int B, float *logits,
+                    void *stream);
+
+/* Logits of the loaded model through the BF16 MFMA path used inside the traversal. */
+int fmm_mlp_infer(const float *X, int B, float *logits, void *stream);
+
+/* Gradient (DEVICE 5768 floats) and loss (DEVICE scalar) of the class-weighted softmax
+ * cross-entropy, mean over the batch weighted by class_w (DEVICE 8 floats), of the
+ * labels y (DEVICE B ints) for features X (DEVICE B x 16).  Synchronises the stream. */
+int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const float *X, const int *y,
+                 const float *class_w, int B, float *grad, float *loss, void *stream);
+
+/* One Adam step (DEVICE params, grad, m, v of 5768 floats), step >= 1 (bias correction),
+ * decoupled weight decay weight_decay * params added to the gradient. */
+int fmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
+                 float beta2, float eps, float weight_decay, void *stream);
 
 void fmm_free_tree(fmm_tree *tree);
 

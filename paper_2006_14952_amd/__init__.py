@@ -37,13 +37,15 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_cells", C.c_int64), ("n_leaves", C.c_int64), ("max_level", C.c_int64),
                 ("n_m2l", C.c_int64), ("n_p2p", C.c_int64), ("p2p_pairs", C.c_int64), ("n_visit", C.c_int64),
-                ("levels_traversed", C.c_int64), ("reserved_i", C.c_int64 * 7),
+                ("levels_traversed", C.c_int64), ("n_m2l_by_order", C.c_int64 * 7),
                 ("t_tree_ms", C.c_double), ("t_upward_ms", C.c_double), ("t_traverse_ms", C.c_double),
                 ("t_m2l_ms", C.c_double), ("t_p2p_ms", C.c_double), ("t_downward_ms", C.c_double),
                 ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("reserved_d", C.c_double * 8)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
+        d["n_m2l_by_order"] = list(d["n_m2l_by_order"])
+        return d
 
 
 def exported_names():
@@ -69,6 +71,14 @@ def lib():
         L.fmm_set_timing.argtypes = [vp, C.c_int]
         L.fmm_copy_interactions.argtypes = [vp, C.c_int, vp, i64, C.POINTER(i64)]
         L.fmm_load_mac_model.argtypes = [C.c_char_p]
+        fp = C.c_void_p
+        L.fmm_set_mac_model.argtypes = [fp, fp, fp, C.c_double, C.c_int]
+        L.fmm_mac_training_data.argtypes = [vp, C.POINTER(Params), C.c_double, dp, C.c_double, C.c_int, fp, fp, fp,
+                                            fp, i64, C.POINTER(i64), vp]
+        L.fmm_mlp_forward.argtypes = [fp, fp, fp, fp, C.c_int, fp, vp]
+        L.fmm_mlp_infer.argtypes = [fp, C.c_int, fp, vp]
+        L.fmm_mlp_grad.argtypes = [fp, fp, fp, fp, fp, fp, C.c_int, fp, fp, vp]
+        L.fmm_mlp_adam.argtypes = [fp, fp, fp, fp, i64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.fmm_free_tree.argtypes = [vp]
         L.fmm_free_tree.restype = None
         L.fmm_last_error.restype = C.c_char_p

@@ -20,7 +20,9 @@ ARCH = os.environ.get("HFMM_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-result",
-         "-munsafe-fp-atomics", "-ffp-contract=fast"]
+         "-munsafe-fp-atomics", "-ffp-contract=fast",
+         # the order-8 expansion kernels unroll term tables of ~1400 entries
+         "-mllvm", "-pragma-unroll-threshold=200000"]
 
 
 def _compile(src):

@@ -5,6 +5,7 @@
 #include <mutex>
 #include <vector>
 
+#include "mlp.h"
 #include "state.h"
 
 namespace hfmm {
@@ -13,6 +14,10 @@ void clear_error();
 int pm_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
               hipStream_t st);
 int add_into(double *acc, const double *other, int64_t n3, hipStream_t st);
+const MacModel *current_model(MacModel *host_copy);
+int run_labels(fmm_tree *t, const fmm_params *P, const double *aref_sorted, double eps, int stride, float *feats,
+               int *labels, float *errs, uint64_t *pairs, int cap, int *dcounter, hipStream_t st);
+int sort_soa(fmm_tree *t, const double *acc, double *out, hipStream_t st);
 }  // namespace hfmm
 
 using namespace hfmm;
@@ -55,21 +60,33 @@ static void mark(fmm_tree *t, int k, hipStream_t st)
 // The stages of one short-range evaluation on a built tree (or forest of boxes).
 static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st)
 {
-    if (P->learned) return set_error(FMM_ERR_ARG, "learned selector requested but no model is loaded");
+    MacModel hm;
+    const MacModel *dm = nullptr;
+    if (P->learned) {
+        dm = current_model(&hm);
+        if (!dm) return set_error(FMM_ERR_STATE, "learned selector requested but no model is loaded");
+    }
     if (t->n == 0) return 0;
+    // the learned selector chooses orders up to 8: expansions are kept at order 8
+    fmm_params P8 = *P;
+    if (P->learned) P8.p = 8;
     int rc;
     mark(t, 0, st);
-    if ((rc = upward(t, P, st))) return rc;
+    if ((rc = upward(t, &P8, st))) return rc;
     mark(t, 1, st);
-    if ((rc = traverse(t, P, st))) return rc;
+    if (P->learned)
+        rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st);
+    else
+        rc = traverse(t, P, st);
+    if (rc) return rc;
     mark(t, 2, st);
-    if ((rc = m2l(t, P, st))) return rc;
+    if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
     mark(t, 3, st);
-    if ((rc = downward_l2l(t, P, st))) return rc;
+    if ((rc = downward_l2l(t, &P8, st))) return rc;
     mark(t, 4, st);
     if ((rc = p2p(t, P, st))) return rc;
     mark(t, 5, st);
-    if ((rc = l2p_combine(t, P, acc, st))) return rc;
+    if ((rc = l2p_combine(t, &P8, acc, st))) return rc;
     mark(t, 6, st);
     t->last_p = P->p;
     t->last_prec = P->precision;
@@ -89,6 +106,8 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     }
     return hip_check(hipGetLastError(), "short range forces");
 }
+
+static int copy_kind(fmm_tree *t, int kind, uint64_t *out, int64_t cap, int64_t *count);
 
 static bool same_params(const fmm_params &a, const fmm_params &b)
 {
@@ -207,6 +226,21 @@ int fmm_copy_interactions(const fmm_tree *tc, int kind, uint64_t *out, int64_t c
         *count = total;
         return 0;
     }
+    if (kind == 0 && t->trav_mode == 2) {  // learned selector: M2L pairs of every order
+        int64_t w = 0;
+        for (int k = 4; k < 11 && w < cap; ++k) {
+            int64_t c = 0;
+            if (int rc = copy_kind(t, k, out + 3 * w, cap - w, &c)) return rc;
+            w += c;
+        }
+        *count = w;
+        return 0;
+    }
+    return copy_kind(t, kind, out, cap, count);
+}
+
+static int copy_kind(fmm_tree *t, int kind, uint64_t *out, int64_t cap, int64_t *count)
+{
     int nc = t->ncell;
     std::vector<Cell> cells(nc);
     std::vector<int> head(nc), cnt(nc);
@@ -238,10 +272,43 @@ int fmm_copy_interactions(const fmm_tree *tc, int kind, uint64_t *out, int64_t c
     return 0;
 }
 
-int fmm_load_mac_model(const char *path)
+int fmm_mac_training_data(fmm_tree *t, const fmm_params *P, double theta_max, const double *acc_ref, double eps,
+                          int stride, float *feats, int *labels, float *errs, uint64_t *pairs, int64_t cap,
+                          int64_t *count, void *stream)
 {
-    (void)path;
-    return set_error(FMM_ERR_ARG, "learned selector not available in this build");
+    clear_error();
+    if (!t || !count || !acc_ref) return set_error(FMM_ERR_ARG, "NULL argument");
+    if (int rc = check_params(P)) return rc;
+    if (P->box != t->box || P->n_crit != t->ncrit) return set_error(FMM_ERR_STATE, "tree / params mismatch");
+    if (!(theta_max > 0) || !(theta_max < 0.75)) return set_error(FMM_ERR_ARG, "theta_max must be in (0, 0.75)");
+    if (cap > 0 && (!feats || !labels)) return set_error(FMM_ERR_ARG, "output buffers are NULL");
+    if (cap > INT32_MAX) cap = INT32_MAX;
+    hipStream_t st = (hipStream_t)stream;
+    *count = 0;
+    if (t->n == 0) return 0;
+    fmm_params P8 = *P;
+    P8.p = 8;
+    P8.precision = 0;
+    P8.learned = 0;
+    int rc = upward(t, &P8, st);  // FP64 multipoles of order 8
+    if (!rc) rc = traverse_mode(t, P, 1, theta_max, t->Mc.p, ncoef(8), 0, nullptr, st);
+    if (rc) return rc;
+    DevBuf aref, ctr;
+    rc = grow(aref, (size_t)t->n * 24) | grow(ctr, 16);
+    if (!rc) rc = sort_soa(t, acc_ref, ptr<double>(aref), st);
+    if (!rc) {
+        hipMemsetAsync(ctr.p, 0, 4, st);
+        rc = run_labels(t, P, ptr<double>(aref), eps, stride, feats, labels, errs, pairs, (int)cap, ptr<int>(ctr), st);
+    }
+    int n = 0;
+    if (!rc) {
+        hipMemcpyAsync(&n, ctr.p, 4, hipMemcpyDeviceToHost, st);
+        rc = hip_check(hipStreamSynchronize(st), "training data");
+    }
+    if (aref.p) (void)hipFree(aref.p);
+    if (ctr.p) (void)hipFree(ctr.p);
+    *count = n < cap ? n : cap;
+    return rc;
 }
 
 int pm_long_range_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass,
@@ -292,9 +359,13 @@ void fmm_free_tree(fmm_tree *t)
     if (!t) return;
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
-                      &t->lcnt, &t->litems[0], &t->litems[1], &t->litems[2], &t->lnext[0], &t->lnext[1],
-                      &t->lnext[2], &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff};
+                      &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
+                      &t->m2l_off, &t->m2l_pairs};
     for (DevBuf *b : bufs) free_buf(*b);
+    for (int k = 0; k < 11; ++k) {
+        free_buf(t->litems[k]);
+        free_buf(t->lnext[k]);
+    }
     if (t->host) (void)hipHostFree(t->host);
     if (t->events_ready)
         for (auto &e : t->ev) (void)hipEventDestroy(e);

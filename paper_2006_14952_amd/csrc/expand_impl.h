@@ -175,6 +175,20 @@ template <int P, class T> __device__ __forceinline__ void dtensor(T Rx, T Ry, T 
 // ---------------------------------------------------------------------------
 // kernels
 
+// Separation R = z_A - (z_B + image shift) in units of h_A, from the cells' integer
+// coordinates (exact): R / h_A = R_int / (2 w_A), R_int in units of box / 2^(l+1).
+template <class T> __device__ __forceinline__ void pair_sep(const Cell &ca, const Cell &cb, int s, T &Rx, T &Ry, T &Rz)
+{
+    const int la = cell_level(ca), lb = cell_level(cb);
+    const int l = la > lb ? la : lb;
+    const int64_t wa = (int64_t)1 << (l - la), wb = (int64_t)1 << (l - lb);
+    const int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
+    const T inv2wa = (T)(0.5 / (double)wa);
+    Rx = (T)((2 * (int64_t)cell_ix(ca) + 1) * wa - (2 * (int64_t)cell_ix(cb) + 1) * wb - (int64_t)sh[0] * ((int64_t)2 << l)) * inv2wa;
+    Ry = (T)((2 * (int64_t)ca.iy + 1) * wa - (2 * (int64_t)cb.iy + 1) * wb - (int64_t)sh[1] * ((int64_t)2 << l)) * inv2wa;
+    Rz = (T)((2 * (int64_t)ca.iz + 1) * wa - (2 * (int64_t)cb.iz + 1) * wb - (int64_t)sh[2] * ((int64_t)2 << l)) * inv2wa;
+}
+
 __device__ __forceinline__ double cell_h(const Cell &c, double box) { return ldexp(box, -cell_level(c)); }
 
 template <int P, class T>
@@ -237,11 +251,13 @@ __global__ __launch_bounds__(64) void k_m2m(const Cell *__restrict__ cells, int 
 }
 
 template <int P, class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_m2l(const Cell *__restrict__ cells, int ncell, const int *__restrict__ head,
-                                            const int *__restrict__ cnt, const uint32_t *__restrict__ items,
-                                            const int *__restrict__ next, const T *__restrict__ M, T *__restrict__ L,
-                                            double box, double rs)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 : 2))) void k_m2l(
+    const Cell *__restrict__ cells, int ncell, const int *__restrict__ head, const int *__restrict__ cnt,
+    const uint32_t *__restrict__ items, const int *__restrict__ next, const T *__restrict__ M, T *__restrict__ L,
+    double box, double rs, int stride, int accumulate)
 {
+    // M and L hold ncoef(order of storage) coefficients per cell (stride); this kernel
+    // reads and writes the first ncoef(P) of them (multi-indices are ordered by degree).
     constexpr int NC = Tab<P>::NC;
     constexpr Tab<P> tb{};
     constexpr PairTab<P> pt{};
@@ -262,14 +278,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             int B = (int)(it >> 5), s = (int)(it & 31);
             Cell cb = cells[B];
             int lb = cell_level(cb);
-            int l = la > lb ? la : lb;
-            int64_t wa = (int64_t)1 << (l - la), wb = (int64_t)1 << (l - lb);
-            int sh[3] = {s / 9 - 1, (s / 3) % 3 - 1, s % 3 - 1};
-            // R / h_A = R_int / (2 w_a), R_int the integer separation in units of box/2^(l+1)
-            T inv2wa = (T)(0.5 / (double)wa);
-            T Rx = (T)((2 * (int64_t)cell_ix(ca) + 1) * wa - (2 * (int64_t)cell_ix(cb) + 1) * wb - (int64_t)sh[0] * ((int64_t)2 << l)) * inv2wa;
-            T Ry = (T)((2 * (int64_t)ca.iy + 1) * wa - (2 * (int64_t)cb.iy + 1) * wb - (int64_t)sh[1] * ((int64_t)2 << l)) * inv2wa;
-            T Rz = (T)((2 * (int64_t)ca.iz + 1) * wa - (2 * (int64_t)cb.iz + 1) * wb - (int64_t)sh[2] * ((int64_t)2 << l)) * inv2wa;
+            T Rx, Ry, Rz;
+            pair_sep<T>(ca, cb, s, Rx, Ry, Rz);
             T f[P + 1], D[NC];
             prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, rsh, f);
             dtensor<P, T>(Rx, Ry, Rz, f, D);
@@ -278,13 +288,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             rp[0] = 1;
 #pragma unroll
             for (int k = 1; k <= P; ++k) rp[k] = rp[k - 1] * rho;
-            const T *Mb = M + (size_t)B * NC;
+            const T *Mb = M + (size_t)B * stride;
             m2l_contract<P, T, 0, 16>(Mb, rp, D, acc);
         }
     }
-    T *out = L + (size_t)A * NC;
+    if (accumulate && nl == 0) return;
+    T *out = L + (size_t)A * stride;
+    if (accumulate) {
 #pragma unroll
-    for (int k = 0; k < NC; ++k) out[k] = acc[k];
+        for (int k = 0; k < NC; ++k) out[k] += acc[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) out[k] = acc[k];
+    }
 }
 
 template <int P, class T>
@@ -352,6 +368,273 @@ __global__ __launch_bounds__(256) void k_l2p(const Cell *__restrict__ cells, con
 }
 
 // ---------------------------------------------------------------------------
+// High orders (P >= 7).  Order 8 has 165 coefficients: a thread cannot hold a cell's
+// expansion, a derivative tensor and a source block in registers at once.  M2M and L2L
+// therefore run a wave per cell, and M2L (FP32) a lane per interaction pair.
+
+// Terms of a translation (M2M when UP, else L2L) sorted by output coefficient and dealt to
+// the 64 lanes of a wave in contiguous runs of CH terms.  Slot i of lane l is stored at
+// [i * 64 + l] so that every load of the table is coalesced.  A term reads coefficient
+// `src` of the input, multiplies it by coef and by the sign (-1)^(parity . flip) of the
+// child's octant, and adds it to output `out`.
+//   M2M: out m, src m - n (n <= m), parity of n, coef 2^-|n| / n! * 2^-|m|
+//   L2L: out n, src n + m (|m| <= P - |n|), parity of m, coef 4^-|m| / m! * 2^-(|n|+1)
+template <int P, bool UP> struct ShiftTab {
+    static constexpr int NT = binom(P + 6, 6);
+    static constexpr int CH = (NT + 63) / 64;
+    uint32_t code[CH * 64];  // out | src << 8 | parity << 16 | 1 << 19 (term present)
+    double coef[CH * 64];
+    constexpr ShiftTab() : code(), coef()
+    {
+        Tab<P> T{};
+        int e = 0;
+        for (int o = 0; o < ncoef(P); ++o) {
+            if (UP) {
+                for (int a = 0; a <= T.x[o]; ++a)
+                    for (int b = 0; b <= T.y[o]; ++b)
+                        for (int c = 0; c <= T.z[o]; ++c) {
+                            int kn = midx(a, b, c);
+                            put(e++, o, midx(T.x[o] - a, T.y[o] - b, T.z[o] - c), (a & 1) | (b & 1) << 1 | (c & 1) << 2,
+                                T.invf[kn] / (double)(1 << T.d[kn]) / (double)(1 << T.d[o]));
+                        }
+            } else {
+                for (int km = 0; km < ncoef(P - T.d[o]); ++km)
+                    put(e++, o, midx(T.x[o] + T.x[km], T.y[o] + T.y[km], T.z[o] + T.z[km]),
+                        (T.x[km] & 1) | (T.y[km] & 1) << 1 | (T.z[km] & 1) << 2,
+                        T.invf[km] / (double)(1 << (2 * T.d[km])) / (double)(2 << T.d[o]));
+            }
+        }
+    }
+    constexpr void put(int e, int o, int src, int par, double c)
+    {
+        int slot = (e % CH) * 64 + e / CH;
+        code[slot] = (uint32_t)o | (uint32_t)src << 8 | (uint32_t)par << 16 | 1u << 19;
+        coef[slot] = c;
+    }
+};
+
+template <int P, bool UP> static __constant__ ShiftTab<P, UP> kShiftTab{};
+
+// M2M (UP: children -> parent, output overwritten) or L2L (parent -> child, added) for
+// the cells of one level, one wave per cell.  Each lane keeps its run of terms in
+// registers, sums consecutive terms of the same output and flushes the partial sum into
+// the LDS output with an atomic add.
+template <int P, class T, bool UP>
+__global__ __launch_bounds__(64) void k_shift_wave(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ C)
+{
+    using Tb = ShiftTab<P, UP>;
+    constexpr int NC = ncoef(P), CH = Tb::CH;
+    __shared__ T src[NC], out[NC];
+    const int lane = threadIdx.x;
+    uint32_t code[CH];
+    T coef[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+        code[i] = kShiftTab<P, UP>.code[i * 64 + lane];
+        coef[i] = (T)kShiftTab<P, UP>.coef[i * 64 + lane];
+    }
+    for (int t = blockIdx.x; t < ln; t += gridDim.x) {
+        const int c = lbeg + t;
+        const Cell cc = cells[c];
+        const int nsrc = UP ? cell_nchild(cc) : 1;
+        if (nsrc == 0) continue;
+        for (int k = lane; k < NC; k += 64) out[k] = 0;
+        for (int q = 0; q < nsrc; ++q) {
+            int sc, flip;
+            if (UP) {
+                sc = cc.child + q;
+                const Cell cq = cells[sc];
+                flip = (cell_ix(cq) & 1) | (cq.iy & 1) << 1 | (cq.iz & 1) << 2;
+            } else {
+                sc = cc.parent;
+                flip = ~((cell_ix(cc) & 1) | (cc.iy & 1) << 1 | (cc.iz & 1) << 2) & 7;
+            }
+            __syncthreads();
+            for (int k = lane; k < NC; k += 64) src[k] = C[(size_t)sc * NC + k];
+            __syncthreads();
+            int cur = -1;
+            T sum = 0;
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const uint32_t w = code[i];
+                if (w >> 19) {
+                    const int o = (int)(w & 255), j = (int)((w >> 8) & 255), par = (int)((w >> 16) & 7);
+                    if (o != cur) {
+                        if (cur >= 0) atomicAdd(&out[cur], sum);
+                        sum = 0;
+                        cur = o;
+                    }
+                    const T v = coef[i] * src[j];
+                    sum += (__popc(par & flip) & 1) ? -v : v;
+                }
+            }
+            if (cur >= 0) atomicAdd(&out[cur], sum);
+        }
+        __syncthreads();
+        T *dst = C + (size_t)c * NC;
+        for (int k = lane; k < NC; k += 64) {
+            if (UP) dst[k] = out[k];
+            else dst[k] += out[k];
+        }
+        __syncthreads();
+    }
+}
+
+// M2L of the high orders, a lane per pair of the flattened (sink-sorted) pair array.  A
+// lane builds its pair's derivative tensor in registers and contracts it with the source
+// multipole, streamed in blocks of MB coefficients (the next block is loaded while the
+// current one is used).  The partial local expansion lives in LDS, one row per lane,
+// except for the kLo lowest outputs, which every block updates and which stay in
+// registers.  At the end the wave sums each output over the runs of lanes that share a
+// sink and adds the sums into L with one atomic per run.
+constexpr int kLo = 10;  // outputs of degree <= 2
+
+// Terms of one source block KB .. KB+MB-1 in output-major order: (output n, source k,
+// derivative index n + k), with flags marking the first and last term of each output.
+template <int P> constexpr int block_terms(int kb, int ke)
+{
+    Tab<P> T{};
+    int c = 0;
+    for (int n = 0; n < ncoef(P); ++n)
+        for (int k = kb; k < ke; ++k)
+            if (T.d[k] + T.d[n] <= P) ++c;
+    return c;
+}
+
+template <int P, int KB, int MB> struct BlockTab {
+    static constexpr int KE = KB + MB < ncoef(P) ? KB + MB : ncoef(P);
+    static constexpr int NQ = block_terms<P>(KB, KE);
+    short n[NQ], k[NQ], nm[NQ];
+    bool first[NQ], last[NQ];
+    constexpr BlockTab() : n(), k(), nm(), first(), last()
+    {
+        Tab<P> T{};
+        int q = 0;
+        for (int kn = 0; kn < ncoef(P); ++kn) {
+            int q0 = q;
+            for (int km = KB; km < KE; ++km)
+                if (T.d[km] + T.d[kn] <= P) {
+                    n[q] = (short)kn;
+                    k[q] = (short)(km - KB);
+                    nm[q] = (short)midx(T.x[kn] + T.x[km], T.y[kn] + T.y[km], T.z[kn] + T.z[km]);
+                    first[q] = q == q0;
+                    last[q] = false;
+                    ++q;
+                }
+            if (q > q0) last[q - 1] = true;
+        }
+    }
+};
+
+template <int P, class T, int KB, int MB>
+__device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T *rp, const T *D, T *lo, T *row,
+                                               const T *Mcur)
+{
+    constexpr Tab<P> tb{};
+    constexpr BlockTab<P, KB, MB> bt{};
+    constexpr int NC = ncoef(P);
+    constexpr int KE = BlockTab<P, KB, MB>::KE;
+    constexpr int KE2 = KE + MB < NC ? KE + MB : NC;
+    T Mnext[MB];
+    if constexpr (KE < NC) {
+#pragma unroll
+        for (int k = KE; k < KE2; ++k) Mnext[k - KE] = Mb[k];
+    }
+    T Ms[MB];
+#pragma unroll
+    for (int k = KB; k < KE; ++k) Ms[k - KB] = Mcur[k - KB] * rp[tb.d[k]];
+    T a = 0;
+#pragma unroll
+    for (int q = 0; q < BlockTab<P, KB, MB>::NQ; ++q) {
+        const int n = bt.n[q];
+        if (bt.first[q]) a = n < kLo ? lo[n] : row[n - kLo];
+        a += Ms[bt.k[q]] * D[bt.nm[q]];
+        if (bt.last[q]) {
+            if (n < kLo) lo[n] = a;
+            else row[n - kLo] = a;
+        }
+    }
+    if constexpr (KE < NC) m2l_pair_block<P, T, KE, MB>(Mb, rp, D, lo, row, Mnext);
+}
+
+template <int P, class T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_m2l_pairs(
+    const Cell *__restrict__ cells, const int2 *__restrict__ pairs, int64_t npair, const T *__restrict__ M,
+    T *__restrict__ L, double box, double rs, int stride)
+{
+    constexpr int NC = ncoef(P), NHI = NC - kLo, STR = NHI | 1;  // odd row stride: no bank conflicts
+    constexpr int MB = 16;
+    __shared__ T accs[64 * STR];
+    __shared__ int sid[64];
+    const int lane = threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    T *row = accs + lane * STR;
+    for (int k = 0; k < NHI; ++k) row[k] = 0;
+    T lo[kLo];
+#pragma unroll
+    for (int k = 0; k < kLo; ++k) lo[k] = 0;
+    int A = -1;
+    if (idx < npair) {
+        const int2 pr = pairs[idx];
+        A = pr.x;
+        const uint32_t it = (uint32_t)pr.y;
+        const int B = (int)(it >> 5), s = (int)(it & 31);
+        const Cell ca = cells[A], cb = cells[B];
+        const T *Mb = M + (size_t)B * stride;
+        T M0[MB];
+#pragma unroll
+        for (int k = 0; k < MB; ++k) M0[k] = Mb[k];
+        T Rx, Ry, Rz;
+        pair_sep<T>(ca, cb, s, Rx, Ry, Rz);
+        T f[P + 1], D[NC];
+        prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, (T)(rs / cell_h(ca, box)), f);
+        dtensor<P, T>(Rx, Ry, Rz, f, D);
+        const T rho = (T)ldexp(1.0, cell_level(ca) - cell_level(cb));
+        T rp[P + 1];
+        rp[0] = 1;
+#pragma unroll
+        for (int k = 1; k <= P; ++k) rp[k] = rp[k - 1] * rho;
+        m2l_pair_block<P, T, 0, MB>(Mb, rp, D, lo, row, M0);
+    }
+    sid[lane] = A;
+    __syncthreads();
+    for (int r = kLo + lane; r < NC; r += 64) {
+        T sum = 0;
+        int cur = sid[0];
+        for (int j = 0; j < 64; ++j) {
+            const int a = sid[j];
+            if (a != cur) {
+                if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + r], sum);
+                sum = 0;
+                cur = a;
+            }
+            sum += accs[j * STR + (r - kLo)];
+        }
+        if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + r], sum);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kLo; ++k) row[k] = lo[k];
+    __syncthreads();
+    if (lane < kLo) {
+        T sum = 0;
+        int cur = sid[0];
+        for (int j = 0; j < 64; ++j) {
+            const int a = sid[j];
+            if (a != cur) {
+                if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + lane], sum);
+                sum = 0;
+                cur = a;
+            }
+            sum += accs[j * STR + lane];
+        }
+        if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + lane], sum);
+    }
+}
+
+int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // dispatch over P and precision
 
 template <template <int, class> class F, class T, class... Args> int dispatch_p(int p, Args &&...args)
@@ -383,18 +666,34 @@ template <int P, class T> struct Upward {
                                                        ptr<double>(t->ms), t->box, ptr<T>(t->Mc));
         for (int l = t->nlevel - 2; l >= 0; --l) {
             int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
-            k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+            if constexpr (P >= 7)
+                k_shift_wave<P, T, true><<<ln < 8192 ? ln : 8192, 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+            else
+                k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
         }
         return hip_check(hipGetLastError(), "upward pass");
     }
 };
 
 template <int P, class T> struct M2L {
-    static int run(fmm_tree *t, double rs, hipStream_t st)
+    // list kind `kind` of the traversal; coefficient storage of order `pstore`
+    static int run(fmm_tree *t, double rs, int kind, int pstore, int accumulate, hipStream_t st)
     {
-        k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead),
-                                                       ptr<int>(t->lcnt), ptr<uint32_t>(t->litems[0]),
-                                                       ptr<int>(t->lnext[0]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs);
+        if constexpr (P >= 7 && sizeof(T) == 4) {
+            const int64_t np = kind == 0 ? t->n_m2l : t->stats.n_m2l_by_order[kind - 4];
+            if (!accumulate) hipMemsetAsync(t->Lc.p, 0, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st);
+            if (np == 0) return hip_check(hipGetLastError(), "m2l");
+            if (int rc = flatten_pairs(t, kind, np, st)) return rc;
+            k_m2l_pairs<P, T><<<(unsigned)((np + 63) / 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int2>(t->m2l_pairs),
+                                                                       np, ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs,
+                                                                       ncoef(pstore));
+            return hip_check(hipGetLastError(), "m2l pairs");
+        }
+        size_t off = (size_t)kind * t->ncell;
+        k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead) + off,
+                                                       ptr<int>(t->lcnt) + off, ptr<uint32_t>(t->litems[kind]),
+                                                       ptr<int>(t->lnext[kind]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box,
+                                                       rs, ncoef(pstore), accumulate);
         return hip_check(hipGetLastError(), "m2l");
     }
 };
@@ -404,7 +703,10 @@ template <int P, class T> struct L2L {
     {
         for (int l = 1; l < t->nlevel; ++l) {
             int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
-            k_l2l<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
+            if constexpr (P >= 7)
+                k_shift_wave<P, T, false><<<ln < 8192 ? ln : 8192, 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
+            else
+                k_l2l<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
         }
         return hip_check(hipGetLastError(), "l2l");
     }
@@ -422,7 +724,10 @@ template <int P, class T> struct L2P {
 };
 
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
-template <class T> int m2l_t(fmm_tree *t, int p, double rs, hipStream_t st) { return dispatch_p<M2L, T>(p, t, rs, st); }
+template <class T> int m2l_t(fmm_tree *t, int p, double rs, int kind, int pstore, int accumulate, hipStream_t st)
+{
+    return dispatch_p<M2L, T>(p, t, rs, kind, pstore, accumulate, st);
+}
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
 template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, hipStream_t st)
 {

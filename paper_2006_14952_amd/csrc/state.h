@@ -29,11 +29,13 @@ struct fmm_tree {
     hfmm::DevBuf leaves;          // int[nleaf]
     hfmm::DevBuf Mc, Lc;          // expansion coefficients, ncell x ncoef(p) (float or double)
 
-    // interaction lists: per cell and list kind (0 M2L, 1 P2P, 2 handed to the children)
+    // interaction lists: per cell and list kind (0 M2L, 1 P2P, 2 handed to the children,
+    // 3 candidate pairs, 4..10 M2L at order 2..8 of the learned selector)
     // a chain of 64-entry chunks; head[k * ncell + c], cnt[k * ncell + c]
     hfmm::DevBuf lhead, lcnt;
-    hfmm::DevBuf litems[3], lnext[3];
-    int lcap[3] = {0, 0, 0};                         // chunks (one more is allocated as overflow bin)
+    hfmm::DevBuf litems[11], lnext[11];
+    int lcap[11] = {0};                              // chunks (one more is allocated as overflow bin)
+    int trav_mode = 0;                               // mode of the last traversal
     hfmm::DevBuf tstack;                             // per-wave traversal stacks
     int stk_cap = 16384;
     bool global_stack = false;                       // set once an input overflowed the LDS stack
@@ -42,6 +44,7 @@ struct fmm_tree {
 
     // scratch
     hfmm::DevBuf scan_tmp, nch, flag;
+    hfmm::DevBuf m2l_off, m2l_pairs;  // flattened M2L pairs (sink, item) for the high-order kernel
     int *host = nullptr;  // pinned readback area (64 ints)
     int last_p = -1, last_prec = -1;
 
@@ -56,8 +59,12 @@ namespace hfmm {
 int tree_build(fmm_tree *t, const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
                const int64_t *offsets, hipStream_t st);
 int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st);
+struct MacModel;
+int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, const void *M, int mstride,
+                  int mprec, const MacModel *model, hipStream_t st);
 int upward(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st);

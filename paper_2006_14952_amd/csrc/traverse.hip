@@ -16,6 +16,7 @@
 // traversal is rerun with enough room.  Per-sink list order is deterministic.
 #include <string.h>
 
+#include "mlp.h"
 #include "state.h"
 
 namespace hfmm {
@@ -49,18 +50,32 @@ __device__ __forceinline__ int mac_decide(int4 a, int4 b, int s, const MacConst 
     return 2;
 }
 
+// List kinds: 0 M2L, 1 P2P, 2 handed to the children, 3 candidate pairs (training
+// export), 4..10 M2L at order 2..8 chosen by the learned selector.
+constexpr int kKinds = 11;
+constexpr int kKindCand = 3, kKindOrd = 4;
+
+// Traversal modes: plain MAC; plain MAC plus export of candidate pairs; learned selector.
+enum { kModePlain = 0, kModeExport = 1, kModeLearned = 2 };
+
 struct TravArgs {
     const Cell *cells;
     int lbeg, ln, ncell;
-    uint32_t *items[3];
-    int *next[3];
-    int cap[3];
-    int *pool;       // [3] chunk counters (chunks handed out, in blocks of kChunkBlock)
-    int *head, *cnt; // [3][ncell]
+    uint32_t *items[kKinds];
+    int *next[kKinds];
+    int cap[kKinds];
+    int *pool;       // [kKinds] chunk counters (chunks handed out, in blocks of kChunkBlock)
+    int *head, *cnt; // [kKinds][ncell]
     uint32_t *stack; // per-wave stacks when they do not fit in LDS
     int stk_cap;
     int *err;        // bit 0: stack overflow, bit 1: pool overflow
     unsigned long long *counters;  // [0] visits, [1] listed particle pairs (P2P kernel), [2] M2L, [3] P2P
+    // candidate pairs / learned selector
+    double theta_max2;             // candidates have (L/S_c)^2 <= theta_max2
+    double box, rs, rcut;
+    const void *M;                 // scaled multipoles (features), stride mstride
+    int mstride, mprec;            // mprec 0: double, 1: float
+    const MacModel *model;
 };
 
 constexpr int kChunkBlock = 16;   // chunks taken from a pool per atomic
@@ -130,18 +145,51 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
     return v;
 }
 
+// Full MAC evaluation for the candidate logic: code as mac_decide, plus whether item 3
+// forced the opening and (L / S_c)^2.
+struct MacEval {
+    int code;
+    bool straddle;
+    double q2;
+};
+
+__device__ __forceinline__ MacEval mac_eval(int4 a, int4 b, int s, const MacConst &mc)
+{
+    MacEval r;
+    PairGeo g = pair_geo(a, b, s);
+    double cut2 = ldexp(mc.cut2[0], 2 * g.l);
+    double w = (mc.mode & 2) ? g.wb : fmax(g.wa, g.wb);
+    r.q2 = 4.0 * w * w / g.sc2;
+    r.straddle = false;
+    if (g.sm2 > cut2) {
+        r.code = 0;
+        return r;
+    }
+    r.straddle = (mc.mode & 1) ? (g.sc2 > cut2) : (g.sM2 > cut2);
+    if (r.straddle) {
+        r.code = 2;
+        return r;
+    }
+    r.code = (4.0 * w * w <= mc.theta2 * g.sc2) ? 1 : 2;
+    return r;
+}
+
 // Sinks t = blockIdx.x, blockIdx.x + gridDim.x, ... of one level.
-template <bool GLOBAL_STACK>
+template <int MODE, bool GLOBAL_STACK>
 __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
 {
     __shared__ uint32_t lds_stack[GLOBAL_STACK ? 1 : kLdsStack];
+    __shared__ short mlp_act[MODE == kModeLearned ? 64 * 64 : 1];
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     uint32_t *stk = GLOBAL_STACK ? a.stack + (size_t)blockIdx.x * a.stk_cap : lds_stack;
     const int scap = GLOBAL_STACK ? a.stk_cap : kLdsStack;
     const int4 *cell4 = reinterpret_cast<const int4 *>(a.cells);  // two int4 per cell
     unsigned long long visits = 0, nm2l = 0, np2p = 0;
-    int bnext[3] = {0, 0, 0}, bend[3] = {0, 0, 0};
+    unsigned long long nord[7] = {0, 0, 0, 0, 0, 0, 0};
+    int bnext[kKinds], bend[kKinds];
+#pragma unroll
+    for (int k = 0; k < kKinds; ++k) bnext[k] = bend[k] = 0;
     for (int t = blockIdx.x; t < a.ln; t += gridDim.x) {
         const int A = a.lbeg + t;
         const int4 ga = cell4[2 * A];
@@ -155,9 +203,13 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
             ninh = a.cnt[2 * a.ncell + parentA];
             ichunk = a.head[2 * a.ncell + parentA];
         }
-        ListState Ls[3];
+        double mA0 = 0.0;
+        if (MODE == kModeLearned)
+            mA0 = a.mprec ? (double)static_cast<const float *>(a.M)[(size_t)A * a.mstride]
+                          : static_cast<const double *>(a.M)[(size_t)A * a.mstride];
+        ListState Ls[kKinds];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) Ls[k] = ListState{-1, -1, 0, 0};
+        for (int k = 0; k < kKinds; ++k) Ls[k] = ListState{-1, -1, 0, 0};
         int sp = 0, ip = 0;
         bool failed = false;
         for (;;) {
@@ -179,21 +231,57 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
             visits += kk;
             const bool valid = lane < kk;
             int d = 0;
+            bool cand = false;
             int4 gb = make_int4(0, 0, 0, 0);
             const int B = (int)(it >> 5), s = (int)(it & 31);
             if (valid) {
                 gb = cell4[2 * B];
-                d = mac_decide(ga, gb, s, mc);
+                if (MODE == kModePlain) {
+                    d = mac_decide(ga, gb, s, mc);
+                } else {
+                    MacEval ev = mac_eval(ga, gb, s, mc);
+                    d = ev.code;
+                    cand = d != 0 && !ev.straddle && ev.q2 <= a.theta_max2;
+                }
             }
             const int lvB = xln_level(gb.x);
             const bool leafB = xln_nchild(gb.x) == 0;
-            bool is_m2l = d == 1;
-            bool is_p2p = d == 2 && leafA && leafB;
-            bool is_pd = d == 2 && !is_p2p && !leafA && (lvA <= lvB || leafB);
-            bool open_src = d == 2 && !is_p2p && !is_pd;
-            emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
+            int ord = 0;  // learned: M2L order of an accepted candidate
+            if (MODE == kModeLearned) {
+                if (d == 1) d = 2;  // the plain acceptance is replaced by the selector
+                if (__ballot(cand)) {
+                    float fv[kFeat];
+                    if (cand) {
+                        PairGeo g = pair_geo(ga, gb, s);
+                        if (a.mprec)
+                            pair_features<float>(g, lvA, lvB, a.box, a.rs, a.rcut, mA0,
+                                                 static_cast<const float *>(a.M) + (size_t)B * a.mstride, fv);
+                        else
+                            pair_features<double>(g, lvA, lvB, a.box, a.rs, a.rcut, mA0,
+                                                  static_cast<const double *>(a.M) + (size_t)B * a.mstride, fv);
+                    } else {
+                        for (int k = 0; k < kFeat; ++k) fv[k] = 0.0f;
+                    }
+                    float lg[kCls];
+                    mlp_logits_wave(a.model, fv, mlp_act, lg);
+                    if (cand) ord = decode_order(lg, a.model->safety);
+                }
+            }
+            bool is_m2l = MODE == kModeLearned ? ord >= 2 : d == 1;
+            bool opened = MODE == kModeLearned ? (d == 2 && ord < 2) : d == 2;
+            bool is_p2p = opened && leafA && leafB;
+            bool is_pd = opened && !is_p2p && !leafA && (lvA <= lvB || leafB);
+            bool open_src = opened && !is_p2p && !is_pd;
+            if (MODE == kModeLearned) {
+#pragma unroll
+                for (int o = 2; o <= 8; ++o)
+                    emit(a, kKindOrd + o - 2, Ls[kKindOrd + o - 2], bnext, bend, is_m2l && ord == o, it, lt, lane);
+            } else {
+                emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
+            }
             emit(a, 1, Ls[1], bnext, bend, is_p2p, it, lt, lane);
             emit(a, 2, Ls[2], bnext, bend, is_pd, it, lt, lane);
+            if (MODE == kModeExport) emit(a, kKindCand, Ls[kKindCand], bnext, bend, cand, it, lt, lane);
             int nch = open_src ? xln_nchild(gb.x) : 0;
             int incl = wave_incl_scan(nch, lane);
             int tot = __builtin_amdgcn_readlane(incl, 63);
@@ -214,18 +302,28 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
         if (failed) continue;
         if (lane == 0) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < kKinds; ++k) {
                 a.head[k * a.ncell + A] = Ls[k].head;
                 a.cnt[k * a.ncell + A] = Ls[k].tot;
             }
         }
-        nm2l += Ls[0].tot;
+        if (MODE == kModeLearned) {
+#pragma unroll
+            for (int k = kKindOrd; k < kKinds; ++k) {
+                nm2l += Ls[k].tot;
+                nord[k - kKindOrd] += Ls[k].tot;
+            }
+        } else {
+            nm2l += Ls[0].tot;
+        }
         np2p += Ls[1].tot;
     }
     if (lane == 0) {
         atomicAdd(&a.counters[0], visits);
         atomicAdd(&a.counters[2], nm2l);
         atomicAdd(&a.counters[3], np2p);
+        if (MODE == kModeLearned)
+            for (int k = 0; k < 7; ++k) atomicAdd(&a.counters[16 + k], nord[k]);
     }
 }
 
@@ -242,9 +340,9 @@ void mac_setup(const fmm_params *P, MacConst &mc)
 
 constexpr int kTravWaves = 8192;
 
-static int ensure_pools(fmm_tree *t, const int want[3])
+static int ensure_pools(fmm_tree *t, const int *want)
 {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKinds; ++k) {
         if (want[k] <= t->lcap[k]) continue;
         int cap = want[k] + want[k] / 4 + 64;
         if (int rc = grow(t->litems[k], (size_t)(cap + 1) * kChunk * 4) | grow(t->lnext[k], (size_t)(cap + 1) * 4))
@@ -254,14 +352,28 @@ static int ensure_pools(fmm_tree *t, const int want[3])
     return 0;
 }
 
-int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st)
+// mode: kModePlain / kModeExport / kModeLearned.  For the last two, theta_max bounds the
+// candidates, M/mstride/mprec give the multipoles used by the features, model the
+// selector (learned only).
+int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, const void *M, int mstride,
+                  int mprec, const MacModel *model, hipStream_t st)
 {
     MacConst mc;
     mac_setup(P, mc);
     const int ncell = t->ncell;
-    int rc = grow(t->lhead, (size_t)3 * ncell * 4) | grow(t->lcnt, (size_t)3 * ncell * 4) | grow(t->counters, 256);
+    int rc = grow(t->lhead, (size_t)kKinds * ncell * 4) | grow(t->lcnt, (size_t)kKinds * ncell * 4) |
+             grow(t->counters, 256);
     if (rc) return rc;
-    int want[3] = {2 * ncell + 64 * kChunkBlock, 8 * t->nleaf + 64 * kChunkBlock, 2 * ncell + 64 * kChunkBlock};
+    int want[kKinds];
+    for (int k = 0; k < kKinds; ++k) want[k] = 64 * kChunkBlock;
+    want[1] += 8 * t->nleaf;
+    want[2] += 2 * ncell;
+    if (mode == kModeLearned) {
+        for (int k = kKindOrd; k < kKinds; ++k) want[k] += ncell / 2;
+    } else {
+        want[0] += 2 * ncell;
+        if (mode == kModeExport) want[kKindCand] += 2 * ncell;
+    }
     if ((rc = ensure_pools(t, want))) return rc;
     for (int attempt = 0; attempt < 4; ++attempt) {
         int nw = 1;
@@ -271,56 +383,81 @@ int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st)
         }
         nw = nw < kTravWaves ? nw : kTravWaves;
         if (t->global_stack && (rc = grow(t->tstack, (size_t)nw * t->stk_cap * 4))) return rc;
-        // counters: [0..3] 64-bit stats, then int pool[3], err, sink counters per level
+        // counters: [0..3] 64-bit stats, int pool[kKinds] at byte 32, err at byte 96,
+        // 64-bit M2L counts per learned order at byte 128
         unsigned char *cb = ptr<unsigned char>(t->counters);
         hipMemsetAsync(cb, 0, 256, st);
-        hipMemsetAsync(t->lcnt.p, 0, (size_t)3 * ncell * 4, st);
+        hipMemsetAsync(t->lcnt.p, 0, (size_t)kKinds * ncell * 4, st);
         TravArgs a;
         a.cells = ptr<Cell>(t->cells);
         a.ncell = ncell;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kKinds; ++k) {
             a.items[k] = ptr<uint32_t>(t->litems[k]);
             a.next[k] = ptr<int>(t->lnext[k]);
             a.cap[k] = t->lcap[k];
         }
         a.counters = reinterpret_cast<unsigned long long *>(cb);
         a.pool = reinterpret_cast<int *>(cb + 32);
-        a.err = reinterpret_cast<int *>(cb + 44);
+        a.err = reinterpret_cast<int *>(cb + 96);
         a.head = ptr<int>(t->lhead);
         a.cnt = ptr<int>(t->lcnt);
         a.stack = ptr<uint32_t>(t->tstack);
         a.stk_cap = t->stk_cap;
+        a.theta_max2 = theta_max * theta_max;
+        a.box = P->box;
+        a.rs = P->r_s;
+        a.rcut = P->r_cut;
+        a.M = M;
+        a.mstride = mstride;
+        a.mprec = mprec;
+        a.model = model;
         for (int l = 0; l < t->nlevel; ++l) {
             a.lbeg = t->lvl_beg[l];
             a.ln = t->lvl_beg[l + 1] - a.lbeg;
             int g = a.ln < nw ? a.ln : nw;
-            if (t->global_stack) k_traverse<true><<<g, 64, 0, st>>>(a, mc);
-            else k_traverse<false><<<g, 64, 0, st>>>(a, mc);
+            bool gs = t->global_stack;
+            if (mode == kModePlain) {
+                if (gs) k_traverse<kModePlain, true><<<g, 64, 0, st>>>(a, mc);
+                else k_traverse<kModePlain, false><<<g, 64, 0, st>>>(a, mc);
+            } else if (mode == kModeExport) {
+                if (gs) k_traverse<kModeExport, true><<<g, 64, 0, st>>>(a, mc);
+                else k_traverse<kModeExport, false><<<g, 64, 0, st>>>(a, mc);
+            } else {
+                if (gs) k_traverse<kModeLearned, true><<<g, 64, 0, st>>>(a, mc);
+                else k_traverse<kModeLearned, false><<<g, 64, 0, st>>>(a, mc);
+            }
         }
         if ((rc = hip_check(hipGetLastError(), "traversal"))) return rc;
-        hipMemcpyAsync(t->host, cb, 48, hipMemcpyDeviceToHost, st);
+        hipMemcpyAsync(t->host, cb, 184, hipMemcpyDeviceToHost, st);
         if ((rc = hip_check(hipStreamSynchronize(st), "traversal sync"))) return rc;
         unsigned long long c64[4];
-        int c32[4];
+        int pools[kKinds], err;
         memcpy(c64, t->host, 32);
-        memcpy(c32, (char *)t->host + 32, 16);
-        int err = c32[3];
+        memcpy(pools, (char *)t->host + 32, sizeof(pools));
+        memcpy(&err, (char *)t->host + 96, 4);
         if (err == 0) {
+            unsigned long long ord[7];
+            memcpy(ord, (char *)t->host + 128, sizeof(ord));
+            for (int k = 0; k < 7; ++k) t->stats.n_m2l_by_order[k] = mode == kModeLearned ? (int64_t)ord[k] : 0;
             t->n_visit = (int64_t)c64[0];
             t->n_m2l = (int64_t)c64[2];
             t->n_p2p = (int64_t)c64[3];
+            t->trav_mode = mode;
             return 0;
         }
         if (err & 1) {  // LDS stack too small for this input: per-wave stacks in device memory
             if (t->global_stack) t->stk_cap *= 4;
             t->global_stack = true;
         }
-        if (err & 2) {
-            int need[3] = {c32[0], c32[1], c32[2]};
-            if ((rc = ensure_pools(t, need))) return rc;
-        }
+        if (err & 2)
+            if ((rc = ensure_pools(t, pools))) return rc;
     }
     return set_error(FMM_ERR_NOMEM, "traversal did not fit after resizing");
+}
+
+int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st)
+{
+    return traverse_mode(t, P, kModePlain, 0.0, nullptr, 0, 0, nullptr, st);
 }
 
 }  // namespace hfmm

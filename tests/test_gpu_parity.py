@@ -56,6 +56,24 @@ def test_fp64_every_order_small_clustered(p):
     assert e.max() < 1e-9
 
 
+@pytest.mark.parametrize("p", list(range(0, 9)))
+def test_fp32_every_order_clustered(p):
+    """Mixed precision at every order (orders 7 and 8 take the wave-per-cell M2M/L2L and the
+    lane-per-pair M2L with its per-sink segmented reduction): against the FP64 oracle at the
+    same order, on a box whose lists run over several 64-pair waves."""
+    rng = inputs.rng_for(104, p)
+    pos, m = inputs.clustered(20000, 12, rng)
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.5, p=p, n_crit=16, precision=1)
+    got, t = gpu_run(pos, m, prm)
+    ref = oracle.fmm(pos, m, opar(prm))
+    st = t.stats()
+    assert st["n_m2l"] == ref.stats["n_m2l"] and st["n_p2p"] == ref.stats["n_p2p"]
+    e = rel_err(got, ref.acc)
+    print("p=%d fp32 vs oracle: median %.2e p99 %.2e max %.2e" % (p, np.median(e), np.percentile(e, 99), e.max()))
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5 and e.max() <= 1e-3
+    t.free()
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_mac_modes_lists_identical(mode):
     rng = inputs.rng_for(102, mode)
