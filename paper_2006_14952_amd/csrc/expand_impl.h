@@ -489,6 +489,10 @@ __global__ __launch_bounds__(64) void k_shift_wave(const Cell *__restrict__ cell
 // sink and adds the sums into L with one atomic per run.
 constexpr int kLo = 10;  // outputs of degree <= 2
 
+// Orders whose M2L takes the lane-per-pair kernel: FP32 from order 3 up, FP64 from 3 to 6
+// (an order-7/8 FP64 derivative tensor does not fit in registers).
+template <int P, class T> constexpr bool pair_m2l() { return P >= 3 && (sizeof(T) == 4 || P <= 6); }
+
 // Terms of one source block KB .. KB+MB-1 in output-major order: (output n, source k,
 // derivative index n + k), with flags marking the first and last term of each output.
 template <int P> constexpr int block_terms(int kb, int ke)
@@ -679,7 +683,7 @@ template <int P, class T> struct M2L {
     // list kind `kind` of the traversal; coefficient storage of order `pstore`
     static int run(fmm_tree *t, double rs, int kind, int pstore, int accumulate, hipStream_t st)
     {
-        if constexpr (P >= 7 && sizeof(T) == 4) {
+        if constexpr (pair_m2l<P, T>()) {
             const int64_t np = kind == 0 ? t->n_m2l : t->stats.n_m2l_by_order[kind - 4];
             if (!accumulate) hipMemsetAsync(t->Lc.p, 0, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st);
             if (np == 0) return hip_check(hipGetLastError(), "m2l");

@@ -102,7 +102,9 @@ def test_batched_forest_equals_single_box_runs():
         ss = s.stats()
         n_m2l += ss["n_m2l"]
         n_p2p += ss["n_p2p"]
-        np.testing.assert_allclose(got[off[b]:off[b + 1]], single, rtol=1e-6, atol=1e-9 * np.abs(single).max())
+        # FP32 M2L partial sums are added with atomics in an order set by each pair's place in
+        # the flattened list, which differs between the forest and a lone box: rounding level
+        np.testing.assert_allclose(got[off[b]:off[b + 1]], single, rtol=2e-5, atol=1e-9 * np.abs(single).max())
     assert st["n_m2l"] == n_m2l and st["n_p2p"] == n_p2p
 
 
