@@ -122,7 +122,7 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     st = tree.stats()
 
-    flop_launch = P2P_FLOP_PER_PAIR * st["p2p_pairs"]
+    flop_launch = P2P_FLOP_PER_PAIR * st["p2p_evaluated"]  # pairs the kernel evaluates
     p2p_s = float(np.mean(p2p_ms)) * 1e-3
     peak = PEAK["fp32_vector"] if wl["precision"] else PEAK["fp64_vector"]
     achieved = flop_launch / p2p_s
@@ -157,7 +157,7 @@ def main():
         "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
         "build_ms": float(np.mean(build_ms)),
         "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit",
-                                      "n_m2l_by_order")},
+                                      "n_m2l_by_order", "p2p_evaluated")},
     }
 
     if args.cpu_sample > 0 and batched:

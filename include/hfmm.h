@@ -79,9 +79,12 @@ typedef struct fmm_stats {
     int64_t n_visit;           /* cell pairs examined by the traversal */
     int64_t levels_traversed;
     int64_t n_m2l_by_order[7]; /* learned selector: accepted pairs at order 2..8 (else 0) */
+    int64_t p2p_evaluated;     /* particle pairs the P2P kernel evaluated: the listed pairs less
+                                  those of source leaves whose particles' bounding box is
+                                  farther than r_cut from the sink leaf's (FP32 form) */
     double t_tree_ms, t_upward_ms, t_traverse_ms, t_m2l_ms, t_p2p_ms, t_downward_ms, t_total_ms;
     double t_build_ms;         /* last fmm_build_tree */
-    double reserved_d[8];
+    double reserved_d[7];
 } fmm_stats;
 
 typedef struct fmm_tree fmm_tree; /* opaque; owned by the library */

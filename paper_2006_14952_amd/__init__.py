@@ -38,9 +38,10 @@ class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_cells", C.c_int64), ("n_leaves", C.c_int64), ("max_level", C.c_int64),
                 ("n_m2l", C.c_int64), ("n_p2p", C.c_int64), ("p2p_pairs", C.c_int64), ("n_visit", C.c_int64),
                 ("levels_traversed", C.c_int64), ("n_m2l_by_order", C.c_int64 * 7),
+                ("p2p_evaluated", C.c_int64),
                 ("t_tree_ms", C.c_double), ("t_upward_ms", C.c_double), ("t_traverse_ms", C.c_double),
                 ("t_m2l_ms", C.c_double), ("t_p2p_ms", C.c_double), ("t_downward_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("reserved_d", C.c_double * 8)]
+                ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("reserved_d", C.c_double * 7)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}

@@ -208,10 +208,12 @@ int fmm_get_stats(const fmm_tree *tc, fmm_stats *out)
     if (!tc || !out) return set_error(FMM_ERR_ARG, "NULL argument");
     fmm_tree *t = const_cast<fmm_tree *>(tc);
     if (t->counters.p && t->n > 0) {  // the P2P kernel counts listed pairs on the device
-        unsigned long long v = 0;
-        if (hipMemcpy(&v, ptr<unsigned long long>(t->counters) + 1, 8, hipMemcpyDeviceToHost) != hipSuccess)
+        unsigned long long v = 0, e = 0;
+        if (hipMemcpy(&v, ptr<unsigned long long>(t->counters) + 1, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&e, ptr<unsigned long long>(t->counters) + 24, 8, hipMemcpyDeviceToHost) != hipSuccess)
             return set_error(FMM_ERR_HIP, "reading counters");
         t->stats.p2p_pairs = (int64_t)v;
+        t->stats.p2p_evaluated = (int64_t)e;
     }
     *out = t->stats;
     return 0;
@@ -360,7 +362,7 @@ void fmm_free_tree(fmm_tree *t)
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
-                      &t->m2l_off, &t->m2l_pairs};
+                      &t->m2l_off, &t->m2l_pairs, &t->bbox};
     for (DevBuf *b : bufs) free_buf(*b);
     for (int k = 0; k < 11; ++k) {
         free_buf(t->litems[k]);

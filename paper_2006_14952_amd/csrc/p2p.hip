@@ -14,7 +14,9 @@
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
 // degree-10 polynomial fitted on the host; the sum of each staged block is added to a
-// Kahan-compensated per-particle accumulator.
+// Kahan-compensated per-particle accumulator.  A listed source leaf whose particles'
+// bounding box lies farther than r_cut from the sink leaf's box holds no pair inside the
+// cutoff and is not staged (the lists themselves are unchanged).
 #include <math.h>
 
 #include <type_traits>
@@ -61,7 +63,32 @@ struct P2PArgs {
     double *nearf;  // 3 x n SoA
     int n;
     unsigned long long *pairs;  // listed particle pairs (sum of n_A n_B over P2P leaf pairs)
+    unsigned long long *evaluated;  // particle pairs actually evaluated (FP32 form: after the box test)
+    const float4 *bbox;             // per cell: lo, hi of the particles relative to the cell centre
 };
+
+// Bounding box of each leaf's particles in the FP32 cell-relative frame.
+__global__ void k_leaf_bbox(const Cell *__restrict__ cells, const int *__restrict__ leaves, int nleaf,
+                            const float4 *__restrict__ rel, float4 *__restrict__ bbox)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf) return;
+    int c = leaves[t];
+    Cell cc = cells[c];
+    float lx = 0, ly = 0, lz = 0, hx = 0, hy = 0, hz = 0;
+    if (cc.end > cc.beg) {
+        float4 r = rel[cc.beg];
+        lx = hx = r.x; ly = hy = r.y; lz = hz = r.z;
+        for (int i = cc.beg + 1; i < cc.end; ++i) {
+            r = rel[i];
+            lx = fminf(lx, r.x); hx = fmaxf(hx, r.x);
+            ly = fminf(ly, r.y); hy = fmaxf(hy, r.y);
+            lz = fminf(lz, r.z); hz = fmaxf(hz, r.z);
+        }
+    }
+    bbox[2 * (size_t)c] = make_float4(lx, ly, lz, 0.0f);
+    bbox[2 * (size_t)c + 1] = make_float4(hx, hy, hz, 0.0f);
+}
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 {
@@ -88,7 +115,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
     const double cax = (cell_ix(ca) + 0.5) * hA, cay = (ca.iy + 0.5) * hA, caz = (ca.iz + 0.5) * hA;
     const int nA = ca.end - ca.beg;
     const int nlist = a.cnt[A];
-    unsigned long long npairs = 0;
+    unsigned long long npairs = 0, nevald = 0;
+    float4 alo = make_float4(0, 0, 0, 0), ahi = alo;
+    if constexpr (!F64) {
+        alo = a.bbox[2 * (size_t)A];
+        ahi = a.bbox[2 * (size_t)A + 1];
+    }
 
     for (int ib = 0; ib < nA; ib += 64) {
         const int ns = min(64, nA - ib);
@@ -107,12 +139,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
         int chunk = a.head[A];
         for (int eb = 0; eb < nlist; eb += 64) {
             const int ne = min(64, nlist - eb);
-            int cntj = 0;
+            int cntj = 0, listed = 0;
             if (lane < ne) {
                 uint32_t it = a.items[(size_t)chunk * kChunk + lane];
                 int s = (int)(it & 31);
                 Cell cb = a.cells[it >> 5];
-                cntj = cb.end - cb.beg;
+                cntj = listed = cb.end - cb.beg;
                 ebeg[lane] = cb.beg;
                 double shx = (double)(s / 9 - 1) * a.box, shy = (double)((s / 3) % 3 - 1) * a.box,
                        shz = (double)(s % 3 - 1) * a.box;
@@ -120,15 +152,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
                     eoff[lane][0] = shx; eoff[lane][1] = shy; eoff[lane][2] = shz;
                 } else {  // exact in FP64: dyadic centres and integer image shifts
                     double hB = ldexp(a.box, -cell_level(cb));
-                    eoff[lane][0] = (float)((cell_ix(cb) + 0.5) * hB + shx - cax);
-                    eoff[lane][1] = (float)((cb.iy + 0.5) * hB + shy - cay);
-                    eoff[lane][2] = (float)((cb.iz + 0.5) * hB + shz - caz);
+                    const float ox = (float)((cell_ix(cb) + 0.5) * hB + shx - cax);
+                    const float oy = (float)((cb.iy + 0.5) * hB + shy - cay);
+                    const float oz = (float)((cb.iz + 0.5) * hB + shz - caz);
+                    eoff[lane][0] = ox; eoff[lane][1] = oy; eoff[lane][2] = oz;
+                    // gap between the two boxes; the margin covers FP32 rounding many times over
+                    const float4 blo = a.bbox[2 * (size_t)(it >> 5)], bhi = a.bbox[2 * (size_t)(it >> 5) + 1];
+                    const float gx = fmaxf(0.0f, fmaxf(alo.x - (bhi.x + ox), (blo.x + ox) - ahi.x));
+                    const float gy = fmaxf(0.0f, fmaxf(alo.y - (bhi.y + oy), (blo.y + oy) - ahi.y));
+                    const float gz = fmaxf(0.0f, fmaxf(alo.z - (bhi.z + oz), (blo.z + oz) - ahi.z));
+                    if (gx * gx + gy * gy + gz * gz > k.rc2 * 1.0001f) cntj = 0;
                 }
             }
             const int incl = wave_incl_scan(cntj);
             if (lane < ne) epref[lane] = incl - cntj;
             const int total = __builtin_amdgcn_readlane(incl, 63);
-            npairs += (unsigned long long)ns * (unsigned)total;
+            const int ltot = F64 ? total : __builtin_amdgcn_readlane(wave_incl_scan(listed), 63);
+            npairs += (unsigned long long)ns * (unsigned)ltot;
+            nevald += (unsigned long long)ns * (unsigned)total;
             __syncthreads();
             for (int sb = 0; sb < total; sb += kStage) {
                 const int nst = min(kStage, total - sb);
@@ -167,14 +208,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
                             const float4 s = src[q];
                             float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
                             float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            float rinv = __frsqrt_rn(r2);
+                            // a particle meets itself (and exact duplicates) at d = 0: the clamp
+                            // keeps w finite, so w d = 0 without a separate r > 0 test
+                            float rinv = __frsqrt_rn(fmaxf(r2, 1e-20f));
                             float t = fmaf(r2, k.two_over_rc2, -1.0f);
                             float S = k.c[kP2PPoly - 1];
 #pragma unroll
                             for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
                             float rinv2 = rinv * rinv;
                             float f1 = fmaf(S, k.inv8rs3, -rinv2 * rinv);
-                            float w = (r2 < k.rc2 && r2 > 0.0f) ? s.w * f1 : 0.0f;
+                            float w = r2 < k.rc2 ? s.w * f1 : 0.0f;
                             px = fmaf(w, dx, px);
                             py = fmaf(w, dy, py);
                             pz = fmaf(w, dz, pz);
@@ -212,7 +255,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
         }
         __syncthreads();
     }
-    if (lane == 0) atomicAdd(a.pairs, npairs);
+    if (lane == 0) {
+        atomicAdd(a.pairs, npairs);
+        atomicAdd(a.evaluated, nevald);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -286,6 +332,13 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
     a.nearf = ptr<double>(t->nearf);
     a.n = (int)t->n;
     a.pairs = ptr<unsigned long long>(t->counters) + 1;
+    a.evaluated = ptr<unsigned long long>(t->counters) + 24;
+    a.bbox = nullptr;
+    if (P->precision) {
+        if (int rc = grow(t->bbox, (size_t)t->ncell * 32)) return rc;
+        a.bbox = ptr<float4>(t->bbox);
+        k_leaf_bbox<<<(t->nleaf + 255) / 256, 256, 0, st>>>(a.cells, a.leaves, t->nleaf, a.rel, ptr<float4>(t->bbox));
+    }
     if (P->precision) k_p2p<false><<<t->nleaf, 64, 0, st>>>(a, k);
     else k_p2p<true><<<t->nleaf, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");

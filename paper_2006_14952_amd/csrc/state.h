@@ -45,6 +45,7 @@ struct fmm_tree {
     // scratch
     hfmm::DevBuf scan_tmp, nch, flag;
     hfmm::DevBuf m2l_off, m2l_pairs;  // flattened M2L pairs (sink, item) for the high-order kernel
+    hfmm::DevBuf bbox;                // per cell: float4 lo, hi of its particles relative to the centre (leaves)
     int *host = nullptr;  // pinned readback area (64 ints)
     int last_p = -1, last_prec = -1;
 

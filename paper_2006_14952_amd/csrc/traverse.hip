@@ -79,7 +79,7 @@ struct TravArgs {
 };
 
 constexpr int kChunkBlock = 16;   // chunks taken from a pool per atomic
-constexpr int kLdsStack = 2048;   // entries of the in-LDS traversal stack
+constexpr int kLdsStack = 1280;   // entries of the in-LDS traversal stack (5 KB: 7 waves per SIMD)
 
 struct ListState {
     int head, cur, fill, tot;
@@ -338,7 +338,29 @@ void mac_setup(const fmm_params *P, MacConst &mc)
     mc.pad = 0;
 }
 
-constexpr int kTravWaves = 8192;
+// Waves of one traversal kernel that fit on the device at once.  Sinks are dealt to the
+// waves statically, so the grid is never larger than this: a second partial round of
+// waves would only lengthen the tail of each level.
+template <int MODE, bool GS> static int resident_waves()
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_traverse<MODE, GS>, 64, 0) != hipSuccess)
+            return 4096;
+        cached = (ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
+    }
+    return cached;
+}
+
+static int resident_waves(int mode, bool gs)
+{
+    if (mode == kModePlain) return gs ? resident_waves<kModePlain, true>() : resident_waves<kModePlain, false>();
+    if (mode == kModeExport) return gs ? resident_waves<kModeExport, true>() : resident_waves<kModeExport, false>();
+    return gs ? resident_waves<kModeLearned, true>() : resident_waves<kModeLearned, false>();
+}
 
 static int ensure_pools(fmm_tree *t, const int *want)
 {
@@ -381,7 +403,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             int ln = t->lvl_beg[l + 1] - t->lvl_beg[l];
             nw = ln > nw ? ln : nw;
         }
-        nw = nw < kTravWaves ? nw : kTravWaves;
+        const int cap = resident_waves(mode, t->global_stack);
+        nw = nw < cap ? nw : cap;
         if (t->global_stack && (rc = grow(t->tstack, (size_t)nw * t->stk_cap * 4))) return rc;
         // counters: [0..3] 64-bit stats, int pool[kKinds] at byte 32, err at byte 96,
         // 64-bit M2L counts per learned order at byte 128

@@ -68,6 +68,8 @@ def test_fp32_every_order_clustered(p):
     ref = oracle.fmm(pos, m, opar(prm))
     st = t.stats()
     assert st["n_m2l"] == ref.stats["n_m2l"] and st["n_p2p"] == ref.stats["n_p2p"]
+    # the bounding-box test skips only leaf pairs with no particle pair inside r_cut
+    assert ref.stats["p2p_incut"] <= st["p2p_evaluated"] <= st["p2p_pairs"] == ref.stats["p2p_pairs"]
     e = rel_err(got, ref.acc)
     print("p=%d fp32 vs oracle: median %.2e p99 %.2e max %.2e" % (p, np.median(e), np.percentile(e, 99), e.max()))
     assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5 and e.max() <= 1e-3
