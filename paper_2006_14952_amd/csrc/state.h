@@ -4,6 +4,10 @@
 
 #include "common.h"
 
+namespace hfmm {
+constexpr int kHostInts = 1024;
+}
+
 struct fmm_tree {
     // shape
     int64_t n = 0;
@@ -45,8 +49,9 @@ struct fmm_tree {
     // scratch
     hfmm::DevBuf scan_tmp, nch, flag;
     hfmm::DevBuf m2l_off, m2l_pairs;  // flattened M2L pairs (sink, item) for the high-order kernel
+    hfmm::DevBuf wstate;              // per traversal wave: chunk block in use of each list kind
     hfmm::DevBuf bbox;                // per cell: float4 lo, hi of its particles relative to the centre (leaves)
-    int *host = nullptr;  // pinned readback area (64 ints)
+    int *host = nullptr;  // pinned readback area (kHostInts ints)
     int last_p = -1, last_prec = -1;
 
     // timing

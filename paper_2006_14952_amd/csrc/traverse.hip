@@ -64,7 +64,8 @@ struct TravArgs {
     uint32_t *items[kKinds];
     int *next[kKinds];
     int cap[kKinds];
-    int *pool;       // [kKinds] chunk counters (chunks handed out, in blocks of kChunkBlock)
+    int *pool;       // chunk counter of list kind k at pool[k * kPoolStride] (chunks handed out)
+    int *wstate;     // per wave w: [kKinds] next chunk, [kKinds] end of its block, kept across levels
     int *head, *cnt; // [kKinds][ncell]
     uint32_t *stack; // per-wave stacks when they do not fit in LDS
     int stk_cap;
@@ -78,7 +79,8 @@ struct TravArgs {
     const MacModel *model;
 };
 
-constexpr int kChunkBlock = 16;   // chunks taken from a pool per atomic
+constexpr int kChunkBlock = 32;   // chunks taken from a pool per atomic
+constexpr int kPoolStride = 32;   // ints between the pool counters (one 128-byte line each)
 constexpr int kLdsStack = 1280;   // entries of the in-LDS traversal stack (5 KB: 7 waves per SIMD)
 
 struct ListState {
@@ -86,13 +88,15 @@ struct ListState {
 };
 
 // Next free chunk of list k.  Each wave takes kChunkBlock chunks per atomic and hands
-// them out itself, so the pool counters see one atomic per 16 chunks.  All list state
-// is wave-uniform and kept in scalar registers.
+// them out itself; the unused rest of its block passes to the wave with the same index
+// in the next level's launch.  So the counters see one atomic per kChunkBlock chunks and
+// no burst when a level starts (same-address atomics are serialised in the L2).  All
+// list state is wave-uniform and kept in scalar registers.
 __device__ __forceinline__ int new_chunk(const TravArgs &a, int k, int *bnext, int *bend, int lane)
 {
     if (bnext[k] == bend[k]) {
         int c = 0;
-        if (lane == 0) c = atomicAdd(&a.pool[k], kChunkBlock);
+        if (lane == 0) c = atomicAdd(&a.pool[k * kPoolStride], kChunkBlock);
         c = __builtin_amdgcn_readfirstlane(c);
         bnext[k] = c;
         bend[k] = c + kChunkBlock;
@@ -188,8 +192,12 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
     unsigned long long visits = 0, nm2l = 0, np2p = 0;
     unsigned long long nord[7] = {0, 0, 0, 0, 0, 0, 0};
     int bnext[kKinds], bend[kKinds];
+    int *ws = a.wstate + (size_t)blockIdx.x * 2 * kKinds;
 #pragma unroll
-    for (int k = 0; k < kKinds; ++k) bnext[k] = bend[k] = 0;
+    for (int k = 0; k < kKinds; ++k) {
+        bnext[k] = __builtin_amdgcn_readfirstlane(ws[k]);
+        bend[k] = __builtin_amdgcn_readfirstlane(ws[kKinds + k]);
+    }
     for (int t = blockIdx.x; t < a.ln; t += gridDim.x) {
         const int A = a.lbeg + t;
         const int4 ga = cell4[2 * A];
@@ -319,6 +327,11 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
         np2p += Ls[1].tot;
     }
     if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < kKinds; ++k) {
+            ws[k] = bnext[k];
+            ws[kKinds + k] = bend[k];
+        }
         atomicAdd(&a.counters[0], visits);
         atomicAdd(&a.counters[2], nm2l);
         atomicAdd(&a.counters[3], np2p);
@@ -362,6 +375,10 @@ static int resident_waves(int mode, bool gs)
     return gs ? resident_waves<kModeLearned, true>() : resident_waves<kModeLearned, false>();
 }
 
+constexpr int kPoolByte = 256;
+constexpr int kCounterBytes = kPoolByte + kKinds * kPoolStride * 4;
+static_assert(kCounterBytes <= kHostInts * 4, "counter readback exceeds the pinned area");
+
 static int ensure_pools(fmm_tree *t, const int *want)
 {
     for (int k = 0; k < kKinds; ++k) {
@@ -384,17 +401,20 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
     mac_setup(P, mc);
     const int ncell = t->ncell;
     int rc = grow(t->lhead, (size_t)kKinds * ncell * 4) | grow(t->lcnt, (size_t)kKinds * ncell * 4) |
-             grow(t->counters, 256);
+             grow(t->counters, kCounterBytes);
     if (rc) return rc;
+    // list kinds written in this mode get room for their expected size plus the partly
+    // used chunk block each wave may hold at the end
     int want[kKinds];
-    for (int k = 0; k < kKinds; ++k) want[k] = 64 * kChunkBlock;
-    want[1] += 8 * t->nleaf;
-    want[2] += 2 * ncell;
+    const int slack = resident_waves(mode, t->global_stack) * kChunkBlock + 64;
+    for (int k = 0; k < kKinds; ++k) want[k] = 0;
+    want[1] = slack + 8 * t->nleaf;
+    want[2] = slack + 2 * ncell;
     if (mode == kModeLearned) {
-        for (int k = kKindOrd; k < kKinds; ++k) want[k] += ncell / 2;
+        for (int k = kKindOrd; k < kKinds; ++k) want[k] = slack + ncell / 2;
     } else {
-        want[0] += 2 * ncell;
-        if (mode == kModeExport) want[kKindCand] += 2 * ncell;
+        want[0] = slack + 2 * ncell;
+        if (mode == kModeExport) want[kKindCand] = slack + 2 * ncell;
     }
     if ((rc = ensure_pools(t, want))) return rc;
     for (int attempt = 0; attempt < 4; ++attempt) {
@@ -406,10 +426,12 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         const int cap = resident_waves(mode, t->global_stack);
         nw = nw < cap ? nw : cap;
         if (t->global_stack && (rc = grow(t->tstack, (size_t)nw * t->stk_cap * 4))) return rc;
-        // counters: [0..3] 64-bit stats, int pool[kKinds] at byte 32, err at byte 96,
-        // 64-bit M2L counts per learned order at byte 128
+        if ((rc = grow(t->wstate, (size_t)nw * 2 * kKinds * sizeof(int)))) return rc;
+        // counters: [0..3] 64-bit stats, err at byte 96, 64-bit M2L counts per learned order
+        // at byte 128, P2P evaluated pairs at byte 192, pool counters from byte kPoolByte
         unsigned char *cb = ptr<unsigned char>(t->counters);
-        hipMemsetAsync(cb, 0, 256, st);
+        hipMemsetAsync(cb, 0, kCounterBytes, st);
+        hipMemsetAsync(t->wstate.p, 0, (size_t)nw * 2 * kKinds * sizeof(int), st);
         hipMemsetAsync(t->lcnt.p, 0, (size_t)kKinds * ncell * 4, st);
         TravArgs a;
         a.cells = ptr<Cell>(t->cells);
@@ -420,7 +442,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             a.cap[k] = t->lcap[k];
         }
         a.counters = reinterpret_cast<unsigned long long *>(cb);
-        a.pool = reinterpret_cast<int *>(cb + 32);
+        a.pool = reinterpret_cast<int *>(cb + kPoolByte);
+        a.wstate = ptr<int>(t->wstate);
         a.err = reinterpret_cast<int *>(cb + 96);
         a.head = ptr<int>(t->lhead);
         a.cnt = ptr<int>(t->lcnt);
@@ -451,12 +474,12 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             }
         }
         if ((rc = hip_check(hipGetLastError(), "traversal"))) return rc;
-        hipMemcpyAsync(t->host, cb, 184, hipMemcpyDeviceToHost, st);
+        hipMemcpyAsync(t->host, cb, kCounterBytes, hipMemcpyDeviceToHost, st);
         if ((rc = hip_check(hipStreamSynchronize(st), "traversal sync"))) return rc;
         unsigned long long c64[4];
         int pools[kKinds], err;
         memcpy(c64, t->host, 32);
-        memcpy(pools, (char *)t->host + 32, sizeof(pools));
+        for (int k = 0; k < kKinds; ++k) pools[k] = t->host[kPoolByte / 4 + k * kPoolStride];
         memcpy(&err, (char *)t->host + 96, 4);
         if (err == 0) {
             unsigned long long ord[7];

@@ -343,7 +343,7 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     for (int b = 0; b <= nbox; ++b) t->hboxoff[b] = hoff ? (int)hoff[b] : (b ? n : 0);
     hipMemcpyAsync(t->boxoff.p, t->hboxoff.data(), (size_t)(nbox + 1) * 4, hipMemcpyHostToDevice, st);
     if (!t->host) {
-        if (hipHostMalloc((void **)&t->host, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void **)&t->host, kHostInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
             return set_error(FMM_ERR_NOMEM, "pinned host buffer");
     }
     int *bad = ptr<int>(t->flag);
