@@ -84,7 +84,8 @@ typedef struct fmm_stats {
                                   farther than r_cut from the sink leaf's (FP32 form) */
     double t_tree_ms, t_upward_ms, t_traverse_ms, t_m2l_ms, t_p2p_ms, t_downward_ms, t_total_ms;
     double t_build_ms;         /* last fmm_build_tree */
-    double reserved_d[7];
+    double t_pm_ms;            /* long-range (PM) part of the last fmm_hybrid_forces_tree */
+    double reserved_d[6];
 } fmm_stats;
 
 typedef struct fmm_tree fmm_tree; /* opaque; owned by the library */
@@ -113,8 +114,18 @@ int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc
 int pm_long_range_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
                          double *acc, void *stream);
 
-/* Total periodic acceleration: pm_long_range_forces + fmm_short_range_forces (builds a
- * temporary tree).  acc (n,3) is overwritten. */
+/* Total periodic acceleration of the hybrid method (Sec. 2.2 split): the PM long-range
+ * part written into acc, then the short-range part added to it by the final L2P +
+ * near-field kernel.  Builds the octree into *tree (a new tree if *tree is NULL, else
+ * the given tree is rebuilt in place; the caller frees it with fmm_free_tree), so the
+ * tree's statistics (fmm_get_stats, with t_pm_ms) describe this call.  acc (n,3) is
+ * overwritten.  Synchronises the stream like fmm_build_tree and fmm_short_range_forces. */
+int fmm_hybrid_forces_tree(fmm_tree **tree, const fmm_params *params, int mesh, int64_t n, const double *pos,
+                           const double *mass, double *acc, void *stream);
+
+/* fmm_hybrid_forces_tree on a tree owned by the library: it is kept (and grown) across
+ * calls until the process ends, so repeated calls allocate nothing once sizes are
+ * steady.  Calls are serialised by a lock.  acc (n,3) is overwritten. */
 int hybrid_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
                   double *acc, void *stream);
 

@@ -41,7 +41,8 @@ class Stats(C.Structure):
                 ("p2p_evaluated", C.c_int64),
                 ("t_tree_ms", C.c_double), ("t_upward_ms", C.c_double), ("t_traverse_ms", C.c_double),
                 ("t_m2l_ms", C.c_double), ("t_p2p_ms", C.c_double), ("t_downward_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("reserved_d", C.c_double * 7)]
+                ("t_total_ms", C.c_double), ("t_build_ms", C.c_double), ("t_pm_ms", C.c_double),
+                ("reserved_d", C.c_double * 6)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("reserved")}
@@ -66,6 +67,7 @@ def lib():
         L.fmm_short_range_forces.argtypes = [vp, C.POINTER(Params), dp, vp]
         L.pm_long_range_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.hybrid_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
+        L.fmm_hybrid_forces_tree.argtypes = [C.POINTER(vp), C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.fmm_short_range_forces_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, dp, vp]
         L.fmm_build_tree_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, vp, C.POINTER(vp)]
         L.fmm_get_stats.argtypes = [vp, C.POINTER(Stats)]
@@ -135,6 +137,23 @@ class Tree:
         if fresh and self._timing:
             _check(lib().fmm_set_timing(self._h, 1))
         return self
+
+    def hybrid(self, pos, mass, prm: Params, mesh, out=None, stream=None):
+        """Total acceleration, PM long range + short range (fmm_hybrid_forces_tree); the
+        tree is (re)built from pos and mass and holds the statistics of the call."""
+        import torch
+        self.n = int(pos.shape[0])
+        if mass.shape[0] != self.n:
+            raise FMMError(FMM_ERR_ARG, "pos and mass lengths differ")
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        fresh = not self._h
+        _check(lib().fmm_hybrid_forces_tree(C.byref(self._h), C.byref(prm), int(mesh), self.n,
+                                            _dev64(pos, (3,)) if self.n else None, _dev64(mass) if self.n else None,
+                                            _dev64(out, (3,)) if self.n else None, _stream(stream)))
+        if fresh and self._timing and self._h:
+            _check(lib().fmm_set_timing(self._h, 1))
+        return out
 
     def build_batched(self, pos, mass, per_box, offsets, stream=None):
         """Forest over the boxes pos[offsets[b]:offsets[b+1]] (all per_box equal)."""

@@ -58,7 +58,8 @@ static void mark(fmm_tree *t, int k, hipStream_t st)
 }
 
 // The stages of one short-range evaluation on a built tree (or forest of boxes).
-static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st)
+// accumulate: add the short-range accelerations to acc instead of overwriting it.
+static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st, int accumulate = 0)
 {
     MacModel hm;
     const MacModel *dm = nullptr;
@@ -86,7 +87,7 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     mark(t, 4, st);
     if ((rc = p2p(t, P, st))) return rc;
     mark(t, 5, st);
-    if ((rc = l2p_combine(t, &P8, acc, st))) return rc;
+    if ((rc = l2p_combine(t, &P8, acc, accumulate, st))) return rc;
     mark(t, 6, st);
     t->last_p = P->p;
     t->last_prec = P->precision;
@@ -323,26 +324,36 @@ int pm_long_range_forces(const fmm_params *P, int mesh, int64_t n, const double 
     return pm_forces(P, mesh, n, pos, mass, acc, (hipStream_t)stream);
 }
 
-int hybrid_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
-                  void *stream)
+int fmm_hybrid_forces_tree(fmm_tree **tree, const fmm_params *P, int mesh, int64_t n, const double *pos,
+                           const double *mass, double *acc, void *stream)
 {
     clear_error();
+    if (!tree) return set_error(FMM_ERR_ARG, "tree is NULL");
     if (int rc = check_params(P)) return rc;
     if (n < 0) return set_error(FMM_ERR_ARG, "n < 0");
     if (n == 0) return 0;
     if (!pos || !mass || !acc) return set_error(FMM_ERR_ARG, "NULL pointer");
     hipStream_t st = (hipStream_t)stream;
+    if (int rc = fmm_build_tree(P, n, pos, mass, stream, tree)) return rc;
+    fmm_tree *t = *tree;
+    mark(t, 7, st);
     if (int rc = pm_forces(P, mesh, n, pos, mass, acc, st)) return rc;
-    fmm_tree *t = nullptr;
-    if (int rc = fmm_build_tree(P, n, pos, mass, stream, &t)) return rc;
-    DevBuf sr;
-    int rc = grow(sr, (size_t)n * 3 * sizeof(double));
-    if (!rc) rc = fmm_short_range_forces(t, P, ptr<double>(sr), stream);
-    if (!rc) rc = add_into(acc, ptr<double>(sr), 3 * n, st);
-    if (!rc) rc = hip_check(hipStreamSynchronize(st), "hybrid");
-    if (sr.p) (void)hipFree(sr.p);
-    fmm_free_tree(t);
-    return rc;
+    mark(t, 8, st);
+    if (int rc = run_forces(t, P, acc, st, 1)) return rc;
+    if (t->timing) {
+        hipEventSynchronize(t->ev[8]);
+        t->stats.t_pm_ms = ev_ms(t, 7, 8);
+    }
+    return hip_check(hipGetLastError(), "hybrid");
+}
+
+int hybrid_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
+                  void *stream)
+{
+    static std::mutex mu;
+    static fmm_tree *tree = nullptr;  // kept between calls: a steady-state call allocates nothing
+    std::lock_guard<std::mutex> lk(mu);
+    return fmm_hybrid_forces_tree(&tree, P, mesh, n, pos, mass, acc, stream);
 }
 
 int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets, const double *pos,

@@ -6,7 +6,7 @@ namespace hfmm {
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st);
 template <class T> int m2l_t(fmm_tree *t, int p, double rs, int kind, int pstore, int accumulate, hipStream_t st);
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st);
-template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, hipStream_t st);
+template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st);
 
 int upward(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
@@ -68,9 +68,10 @@ int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return P->precision ? l2l_t<float>(t, P->p, st) : l2l_t<double>(t, P->p, st);
 }
 
-int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st)
+int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, int accumulate, hipStream_t st)
 {
-    return P->precision ? l2p_t<float>(t, P->p, P->G, acc, st) : l2p_t<double>(t, P->p, P->G, acc, st);
+    return P->precision ? l2p_t<float>(t, P->p, P->G, acc, accumulate, st)
+                        : l2p_t<double>(t, P->p, P->G, acc, accumulate, st);
 }
 
 }  // namespace hfmm

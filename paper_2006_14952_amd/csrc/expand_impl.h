@@ -332,7 +332,7 @@ __global__ __launch_bounds__(256) void k_l2p(const Cell *__restrict__ cells, con
                                              const double *__restrict__ xs, const double *__restrict__ ys,
                                              const double *__restrict__ zs, const T *__restrict__ L,
                                              const double *__restrict__ nearf, const int *__restrict__ perm, double box,
-                                             double G, double *__restrict__ acc)
+                                             double G, double *__restrict__ acc, int accumulate)
 {
     constexpr int NC = Tab<P>::NC;
     constexpr int NC1 = P > 0 ? ncoef(P - 1) : 1;
@@ -362,9 +362,17 @@ __global__ __launch_bounds__(256) void k_l2p(const Cell *__restrict__ cells, con
         g[2] = (double)gz * s;
     }
     size_t o = 3 * (size_t)perm[i];
-    acc[o] = G * (g[0] + nearf[i]);
-    acc[o + 1] = G * (g[1] + nearf[(size_t)n + i]);
-    acc[o + 2] = G * (g[2] + nearf[2 * (size_t)n + i]);
+    const double r0 = G * (g[0] + nearf[i]), r1 = G * (g[1] + nearf[(size_t)n + i]),
+                 r2 = G * (g[2] + nearf[2 * (size_t)n + i]);
+    if (accumulate) {
+        acc[o] += r0;
+        acc[o + 1] += r1;
+        acc[o + 2] += r2;
+    } else {
+        acc[o] = r0;
+        acc[o + 1] = r1;
+        acc[o + 2] = r2;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -717,12 +725,12 @@ template <int P, class T> struct L2L {
 };
 
 template <int P, class T> struct L2P {
-    static int run(fmm_tree *t, double G, double *acc, hipStream_t st)
+    static int run(fmm_tree *t, double G, double *acc, int accumulate, hipStream_t st)
     {
         k_l2p<P, T><<<nblk(t->n, 256), 256, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaf_of), (int)t->n,
                                                      ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
                                                      ptr<T>(t->Lc), ptr<double>(t->nearf), ptr<int>(t->perm), t->box,
-                                                     G, acc);
+                                                     G, acc, accumulate);
         return hip_check(hipGetLastError(), "l2p");
     }
 };
@@ -733,9 +741,9 @@ template <class T> int m2l_t(fmm_tree *t, int p, double rs, int kind, int pstore
     return dispatch_p<M2L, T>(p, t, rs, kind, pstore, accumulate, st);
 }
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
-template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, hipStream_t st)
+template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st)
 {
-    return dispatch_p<L2P, T>(p, t, G, acc, st);
+    return dispatch_p<L2P, T>(p, t, G, acc, accumulate, st);
 }
 
 }  // namespace hfmm

@@ -13,14 +13,22 @@ constexpr int kFeat = 16, kHid = 64, kCls = 8;
 constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 5248, kOffB3 = 5760;
 constexpr int kNParam = 5768;
 
-// Device copy of a loaded model: weights as BF16 MFMA B-operand fragments (see
-// mlp_fragments), FP32 biases, feature normalisation and decoding constants.
-struct MacModel {
-    short w1f[4][64][4];        // [col tile][lane][4]
-    short w2f[4][4][64][4];     // [k chunk][col tile][lane][4]
-    short w3f[4][64][4];        // [k chunk][lane][4]   (8 classes padded to 16 columns)
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+// The network as the inference reads it: BF16 MFMA B-operand fragments of the weights
+// (see build_model), FP32 biases and feature normalisation.
+struct MlpWeights {
+    short4v w1[4][64];      // [col tile][lane]
+    short4v w2[4][4][64];   // [k chunk][col tile][lane]
+    short4v w3[4][64];      // [k chunk][lane]
     float b1[64], b2[64], b3[16];
     float mu[kFeat], isd[kFeat];
+};
+
+// Device copy of a loaded model.
+struct MacModel {
+    MlpWeights w;
     double theta_max;           // pairs with L/S_c above this are always opened
     int safety;                 // orders added to the predicted one (0..)
     int pad;
@@ -62,31 +70,34 @@ template <class T>
 __device__ __forceinline__ void pair_features(const PairGeo &g, int la, int lb, double box, double rs, double rcut,
                                               double mA0, const T *MB, float *f)
 {
-    double u = ldexp(box, -(g.l + 1));
-    double Sc = sqrt(g.sc2) * u, Sm = sqrt(g.sm2) * u, SM = sqrt(g.sM2) * u;
-    double hA = 2.0 * g.wa * u, hB = 2.0 * g.wb * u;
-    double L = fmax(hA, hB);
-    double Rm = fmax(fabs(g.R[0]), fmax(fabs(g.R[1]), fabs(g.R[2]))) * u;
-    f[0] = (float)(L / Sc);
-    f[1] = (float)(hA / Sc);
-    f[2] = (float)(hB / Sc);
-    f[3] = (float)(Sc / rs);
-    f[4] = (float)(Sm / rs);
-    f[5] = (float)(SM / rs);
+    // geometry is exact in units u; the ratios are formed in FP32
+    const float u = (float)ldexp(box, -(g.l + 1));
+    const float Sc = sqrtf((float)g.sc2) * u, Sm = sqrtf((float)g.sm2) * u, SM = sqrtf((float)g.sM2) * u;
+    const float hA = 2.0f * (float)g.wa * u, hB = 2.0f * (float)g.wb * u;
+    const float L = fmaxf(hA, hB);
+    const float Rm = fmaxf(fabsf((float)g.R[0]), fmaxf(fabsf((float)g.R[1]), fabsf((float)g.R[2]))) * u;
+    const float irs = (float)(1.0 / rs), iSc = 1.0f / Sc;
+    f[0] = L * iSc;
+    f[1] = hA * iSc;
+    f[2] = hB * iSc;
+    f[3] = Sc * irs;
+    f[4] = Sm * irs;
+    f[5] = SM * irs;
     f[6] = (float)(rcut / rs);
     f[7] = (float)(la - lb);
-    f[8] = (float)(Rm / Sc);
-    f[9] = (float)log2(hA / rs);
-    double m0 = (double)MB[0];
-    double am0 = fabs(m0) > 0 ? fabs(m0) : 1e-300;
-    double n1 = 0, n2 = 0, n3 = 0;
-    for (int k = 1; k < 4; ++k) n1 += (double)MB[k] * MB[k];
-    for (int k = 4; k < 10; ++k) n2 += (double)MB[k] * MB[k];
-    for (int k = 10; k < 20; ++k) n3 += (double)MB[k] * MB[k];
-    f[10] = (float)(sqrt(n1) / am0);
-    f[11] = (float)(sqrt(n2) / am0);
-    f[12] = (float)(sqrt(n3) / am0);
-    f[13] = (float)log((am0 > 1e-300 ? am0 : 1e-300) / (mA0 > 1e-300 ? mA0 : 1e-300));
+    f[8] = Rm * iSc;
+    f[9] = log2f(hA * irs);
+    const float m0 = (float)MB[0];
+    const float am0 = fabsf(m0) > 0.0f ? fabsf(m0) : 1e-30f;
+    float n1 = 0, n2 = 0, n3 = 0;
+    for (int k = 1; k < 4; ++k) n1 += (float)MB[k] * (float)MB[k];
+    for (int k = 4; k < 10; ++k) n2 += (float)MB[k] * (float)MB[k];
+    for (int k = 10; k < 20; ++k) n3 += (float)MB[k] * (float)MB[k];
+    const float ia = 1.0f / am0;
+    f[10] = sqrtf(n1) * ia;
+    f[11] = sqrtf(n2) * ia;
+    f[12] = sqrtf(n3) * ia;
+    f[13] = logf(am0 / fmaxf((float)mA0, 1e-30f));
     f[14] = 0.0f;
     f[15] = 0.0f;
 }
@@ -98,72 +109,64 @@ __device__ __forceinline__ short f2bf(float x)  // round to nearest even
     return (short)(u >> 16);
 }
 
-typedef short short4v __attribute__((ext_vector_type(4)));
-typedef float float4v __attribute__((ext_vector_type(4)));
-
-// Logits of the 64 pairs of a wave (one per lane; lanes with valid == false still take
-// part).  `act` is 64 x 64 BF16 of LDS, `out` receives 8 logits per lane.
+// Logits of the 64 pairs of a wave (one per lane; lanes without a pair take part with
+// zero features).  `act` is 64 x 64 BF16 of LDS, `out` receives 8 logits per lane.
 // v_mfma_f32_16x16x16_bf16 operand layout (per lane l): A[i = l%16][k = 4(l/16)+r],
-// B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.
-__device__ __forceinline__ void mlp_logits_wave(const MacModel *__restrict__ M, const float *fin, short *act,
-                                                float *out)
+// B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.  Row tile t holds
+// pairs 16t .. 16t+15.  Each layer first reads all its input fragments, then writes its
+// output over the same LDS rows, so every weight fragment is read once per call (the
+// weights stay in global memory: 12 KB shared by all waves, cache resident).
+__device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float *fin, short *act, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    // features (normalised) -> act row `lane`, columns 0..15
-    for (int k = 0; k < kFeat; ++k) act[lane * 64 + k] = f2bf((fin[k] - M->mu[k]) * M->isd[k]);
+    for (int k = 0; k < kFeat; ++k) act[lane * 64 + k] = f2bf((fin[k] - W.mu[k]) * W.isd[k]);
     __syncthreads();
-    // layer 1: 16 -> 64, in place per row tile (row tile t reads only its own rows)
-    for (int t = 0; t < 4; ++t) {
-        short4v a;
-        for (int r = 0; r < 4; ++r) a[r] = act[(16 * t + li) * 64 + 4 * lk + r];
-        float4v c[4];
-        for (int u = 0; u < 4; ++u) {
-            short4v b;
-            for (int r = 0; r < 4; ++r) b[r] = M->w1f[u][lane][r];
-            c[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, float4v{0, 0, 0, 0}, 0, 0, 0);
+    // layer 1: 16 -> 64
+    short4v a1[4];
+    for (int t = 0; t < 4; ++t)
+        for (int r = 0; r < 4; ++r) a1[t][r] = act[(16 * t + li) * 64 + 4 * lk + r];
+    for (int u = 0; u < 4; ++u) {
+        const short4v b = W.w1[u][lane];
+        const float bias = W.b1[16 * u + li];
+        for (int t = 0; t < 4; ++t) {
+            float4v c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t], b, float4v{0, 0, 0, 0}, 0, 0, 0);
+            for (int r = 0; r < 4; ++r) act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[r] + bias, 0.0f));
         }
-        __syncthreads();
-        for (int u = 0; u < 4; ++u)
-            for (int r = 0; r < 4; ++r)
-                act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[u][r] + M->b1[16 * u + li], 0.0f));
-        __syncthreads();
     }
+    __syncthreads();
     // layer 2: 64 -> 64
-    for (int t = 0; t < 4; ++t) {
+    short4v a[4][4];
+    for (int t = 0; t < 4; ++t)
+        for (int kc = 0; kc < 4; ++kc)
+            for (int r = 0; r < 4; ++r) a[t][kc][r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
+    for (int u = 0; u < 4; ++u) {
         float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
         for (int kc = 0; kc < 4; ++kc) {
-            short4v a;
-            for (int r = 0; r < 4; ++r) a[r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
-            for (int u = 0; u < 4; ++u) {
-                short4v b;
-                for (int r = 0; r < 4; ++r) b[r] = M->w2f[kc][u][lane][r];
-                c[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c[u], 0, 0, 0);
-            }
+            const short4v b = W.w2[kc][u][lane];
+            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t][kc], b, c[t], 0, 0, 0);
         }
-        __syncthreads();
-        for (int u = 0; u < 4; ++u)
-            for (int r = 0; r < 4; ++r)
-                act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[u][r] + M->b2[16 * u + li], 0.0f));
-        __syncthreads();
+        const float bias = W.b2[16 * u + li];
+        for (int t = 0; t < 4; ++t)
+            for (int r = 0; r < 4; ++r) act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[t][r] + bias, 0.0f));
     }
-    // layer 3: 64 -> 8 (padded to 16); logits written as FP32 over the consumed row tile
+    __syncthreads();
+    // layer 3: 64 -> 8 (padded to 16 columns); logits as FP32 over the first 4 KB of act
+    for (int t = 0; t < 4; ++t)
+        for (int kc = 0; kc < 4; ++kc)
+            for (int r = 0; r < 4; ++r) a[t][kc][r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
+    float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int kc = 0; kc < 4; ++kc) {
+        const short4v b = W.w3[kc][lane];
+        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t][kc], b, c[t], 0, 0, 0);
+    }
+    __syncthreads();  // every lane has read its layer-3 inputs before the logits overwrite them
     float *fout = reinterpret_cast<float *>(act);
-    for (int t = 0; t < 4; ++t) {
-        float4v c = {0, 0, 0, 0};
-        for (int kc = 0; kc < 4; ++kc) {
-            short4v a, b;
-            for (int r = 0; r < 4; ++r) a[r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
-            for (int r = 0; r < 4; ++r) b[r] = M->w3f[kc][lane][r];
-            c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-        }
-        __syncthreads();
-        // row tile t occupies bytes [t*2048, (t+1)*2048) of act: 16 rows x 16 floats = 1 KB fits
-        for (int r = 0; r < 4; ++r) fout[t * 512 + (4 * lk + r) * 16 + li] = c[r] + M->b3[li];
-        __syncthreads();
-    }
-    const int t = lane >> 4, row = lane & 15;
-    for (int k = 0; k < kCls; ++k) out[k] = fout[t * 512 + row * 16 + k];
+    const float bias = W.b3[li];
+    for (int t = 0; t < 4; ++t)
+        for (int r = 0; r < 4; ++r) fout[(16 * t + 4 * lk + r) * 16 + li] = c[t][r] + bias;
+    __syncthreads();
+    for (int k = 0; k < kCls; ++k) out[k] = fout[lane * 16 + k];
     __syncthreads();
 }
 

@@ -48,29 +48,29 @@ static void build_model(const float *w, const float *mu, const float *isd, doubl
         for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
                 int k = 4 * (l / 16) + r, j = 16 * u + l % 16;
-                M.w1f[u][l][r] = host_bf16(w[kOffW1 + k * kHid + j]);
+                M.w.w1[u][l][r] = host_bf16(w[kOffW1 + k * kHid + j]);
             }
     for (int kc = 0; kc < 4; ++kc)
         for (int u = 0; u < 4; ++u)
             for (int l = 0; l < 64; ++l)
                 for (int r = 0; r < 4; ++r) {
                     int k = 16 * kc + 4 * (l / 16) + r, j = 16 * u + l % 16;
-                    M.w2f[kc][u][l][r] = host_bf16(w[kOffW2 + k * kHid + j]);
+                    M.w.w2[kc][u][l][r] = host_bf16(w[kOffW2 + k * kHid + j]);
                 }
     for (int kc = 0; kc < 4; ++kc)
         for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) {
                 int k = 16 * kc + 4 * (l / 16) + r, j = l % 16;
-                M.w3f[kc][l][r] = j < kCls ? host_bf16(w[kOffW3 + k * kCls + j]) : 0;
+                M.w.w3[kc][l][r] = j < kCls ? host_bf16(w[kOffW3 + k * kCls + j]) : 0;
             }
     for (int j = 0; j < kHid; ++j) {
-        M.b1[j] = w[kOffB1 + j];
-        M.b2[j] = w[kOffB2 + j];
+        M.w.b1[j] = w[kOffB1 + j];
+        M.w.b2[j] = w[kOffB2 + j];
     }
-    for (int j = 0; j < 16; ++j) M.b3[j] = j < kCls ? w[kOffB3 + j] : 0.0f;
+    for (int j = 0; j < 16; ++j) M.w.b3[j] = j < kCls ? w[kOffB3 + j] : 0.0f;
     for (int k = 0; k < kFeat; ++k) {
-        M.mu[k] = mu[k];
-        M.isd[k] = isd[k];
+        M.w.mu[k] = mu[k];
+        M.w.isd[k] = isd[k];
     }
     M.theta_max = theta_max;
     M.safety = safety;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(64) void k_mlp_infer(const MacModel *__restrict__ M
     int s = blockIdx.x * 64 + threadIdx.x;
     float f[kFeat], lg[kCls];
     for (int k = 0; k < kFeat; ++k) f[k] = s < B ? X[(size_t)s * kFeat + k] : 0.0f;
-    mlp_logits_wave(M, f, act, lg);
+    mlp_logits_wave(M->w, f, act, lg);
     if (s < B)
         for (int k = 0; k < kCls; ++k) Z[(size_t)s * kCls + k] = lg[k];
 }

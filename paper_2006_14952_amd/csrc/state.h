@@ -73,6 +73,6 @@ int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
-int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st);
+int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, int accumulate, hipStream_t st);
 uint64_t cell_key_host(int level, int ix, int iy, int iz);
 }  // namespace hfmm

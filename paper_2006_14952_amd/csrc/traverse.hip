@@ -81,6 +81,7 @@ struct TravArgs {
 
 constexpr int kChunkBlock = 32;   // chunks taken from a pool per atomic
 constexpr int kPoolStride = 32;   // ints between the pool counters (one 128-byte line each)
+constexpr int kCandQ = 128;       // learned: ring of candidate pairs (at most 63 wait between steps)
 constexpr int kLdsStack = 1280;   // entries of the in-LDS traversal stack (5 KB: 7 waves per SIMD)
 
 struct ListState {
@@ -180,10 +181,12 @@ __device__ __forceinline__ MacEval mac_eval(int4 a, int4 b, int s, const MacCons
 
 // Sinks t = blockIdx.x, blockIdx.x + gridDim.x, ... of one level.
 template <int MODE, bool GLOBAL_STACK>
-__global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_traverse(TravArgs a, MacConst mc)
 {
     __shared__ uint32_t lds_stack[GLOBAL_STACK ? 1 : kLdsStack];
     __shared__ short mlp_act[MODE == kModeLearned ? 64 * 64 : 1];
+    __shared__ uint32_t cand_q[MODE == kModeLearned ? kCandQ : 1];
+
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
     uint32_t *stk = GLOBAL_STACK ? a.stack + (size_t)blockIdx.x * a.stk_cap : lds_stack;
@@ -219,11 +222,60 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
 #pragma unroll
         for (int k = 0; k < kKinds; ++k) Ls[k] = ListState{-1, -1, 0, 0};
         int sp = 0, ip = 0;
+        int qhead = 0, qtail = 0;  // learned: queue of candidate pairs awaiting the selector
         bool failed = false;
+
+        // Lists and stack for decided pairs of the lanes with `valid`: `m2l_ord` >= 2 puts
+        // the pair on an M2L list (order m2l_ord in learned mode, else plain), `opened`
+        // hands it to P2P, to the children of A, or opens the source.  Returns false if
+        // the stack overflowed.
+        auto finish = [&](bool valid, uint32_t it, int4 gb, int m2l_ord, bool opened) __attribute__((always_inline))
+            -> bool {
+            const int lvB = xln_level(gb.x);
+            const bool leafB = xln_nchild(gb.x) == 0;
+            const bool is_m2l = valid && m2l_ord >= 2;
+            opened = valid && opened;
+            const bool is_p2p = opened && leafA && leafB;
+            const bool is_pd = opened && !is_p2p && !leafA && (lvA <= lvB || leafB);
+            const bool open_src = opened && !is_p2p && !is_pd;
+            if (MODE == kModeLearned) {
+#pragma unroll
+                for (int o = 2; o <= 8; ++o)
+                    emit(a, kKindOrd + o - 2, Ls[kKindOrd + o - 2], bnext, bend, is_m2l && m2l_ord == o, it, lt,
+                         lane);
+            } else {
+                emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
+            }
+            emit(a, 1, Ls[1], bnext, bend, is_p2p, it, lt, lane);
+            emit(a, 2, Ls[2], bnext, bend, is_pd, it, lt, lane);
+            const int nch = open_src ? xln_nchild(gb.x) : 0;
+            const int incl = wave_incl_scan(nch, lane);
+            const int tot = __builtin_amdgcn_readlane(incl, 63);
+            if (tot > 0) {
+                if (sp + tot > scap) {
+                    if (lane == 0) atomicOr(a.err, 1);
+                    return false;
+                }
+                if (nch > 0) {
+                    const int off = sp + incl - nch;
+                    const int s = (int)(it & 31);
+                    for (int q = 0; q < nch; ++q) stk[off + q] = (uint32_t)(gb.w + q) << 5 | (uint32_t)s;
+                }
+                sp += tot;
+                __syncthreads();  // pushes complete before the next pop reads them
+            }
+            return true;
+        };
+
         for (;;) {
-            int kk;
+            // next batch: a flush of the candidate queue (learned: when 64 wait, or when
+            // nothing else is left), else up to 64 pairs from the stack, else from the
+            // list inherited from the parent
+            int kk = 0, fk = 0;
             uint32_t it = 0;
-            if (sp > 0) {
+            if (MODE == kModeLearned && qtail - qhead >= 64) {
+                fk = 64;
+            } else if (sp > 0) {
                 kk = sp < 64 ? sp : 64;
                 sp -= kk;
                 if (lane < kk) it = stk[sp + lane];
@@ -233,78 +285,71 @@ __global__ __launch_bounds__(64) void k_traverse(TravArgs a, MacConst mc)
                     it = root ? ((uint32_t)A << 5 | (uint32_t)(ip + lane)) : a.items[2][(size_t)ichunk * kChunk + lane];
                 ip += kk;
                 if (!root && ip < ninh) ichunk = a.next[2][ichunk];
+            } else if (MODE == kModeLearned && qtail > qhead) {
+                fk = qtail - qhead;
             } else {
                 break;
             }
-            visits += kk;
-            const bool valid = lane < kk;
-            int d = 0;
-            bool cand = false;
+            bool valid, opened;
+            int ord;
             int4 gb = make_int4(0, 0, 0, 0);
-            const int B = (int)(it >> 5), s = (int)(it & 31);
-            if (valid) {
-                gb = cell4[2 * B];
-                if (MODE == kModePlain) {
-                    d = mac_decide(ga, gb, s, mc);
-                } else {
-                    MacEval ev = mac_eval(ga, gb, s, mc);
-                    d = ev.code;
-                    cand = d != 0 && !ev.straddle && ev.q2 <= a.theta_max2;
+            if (MODE == kModeLearned && fk > 0) {
+                // the selector decides fk queued candidates at once (features, MLP on the
+                // matrix cores, order decoding); not accepted means opened
+                __syncthreads();  // queued entries are written before other lanes read them
+                valid = lane < fk;
+                it = valid ? cand_q[(qhead + lane) & (kCandQ - 1)] : 0u;
+                qhead += fk;
+                const int B = (int)(it >> 5), s = (int)(it & 31);
+                float fv[kFeat];
+                for (int q = 0; q < kFeat; ++q) fv[q] = 0.0f;
+                if (valid) {
+                    gb = cell4[2 * B];
+                    PairGeo g = pair_geo(ga, gb, s);
+                    if (a.mprec)
+                        pair_features<float>(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0,
+                                             static_cast<const float *>(a.M) + (size_t)B * a.mstride, fv);
+                    else
+                        pair_features<double>(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0,
+                                              static_cast<const double *>(a.M) + (size_t)B * a.mstride, fv);
                 }
-            }
-            const int lvB = xln_level(gb.x);
-            const bool leafB = xln_nchild(gb.x) == 0;
-            int ord = 0;  // learned: M2L order of an accepted candidate
-            if (MODE == kModeLearned) {
-                if (d == 1) d = 2;  // the plain acceptance is replaced by the selector
-                if (__ballot(cand)) {
-                    float fv[kFeat];
-                    if (cand) {
-                        PairGeo g = pair_geo(ga, gb, s);
-                        if (a.mprec)
-                            pair_features<float>(g, lvA, lvB, a.box, a.rs, a.rcut, mA0,
-                                                 static_cast<const float *>(a.M) + (size_t)B * a.mstride, fv);
-                        else
-                            pair_features<double>(g, lvA, lvB, a.box, a.rs, a.rcut, mA0,
-                                                  static_cast<const double *>(a.M) + (size_t)B * a.mstride, fv);
-                    } else {
-                        for (int k = 0; k < kFeat; ++k) fv[k] = 0.0f;
-                    }
-                    float lg[kCls];
-                    mlp_logits_wave(a.model, fv, mlp_act, lg);
-                    if (cand) ord = decode_order(lg, a.model->safety);
-                }
-            }
-            bool is_m2l = MODE == kModeLearned ? ord >= 2 : d == 1;
-            bool opened = MODE == kModeLearned ? (d == 2 && ord < 2) : d == 2;
-            bool is_p2p = opened && leafA && leafB;
-            bool is_pd = opened && !is_p2p && !leafA && (lvA <= lvB || leafB);
-            bool open_src = opened && !is_p2p && !is_pd;
-            if (MODE == kModeLearned) {
-#pragma unroll
-                for (int o = 2; o <= 8; ++o)
-                    emit(a, kKindOrd + o - 2, Ls[kKindOrd + o - 2], bnext, bend, is_m2l && ord == o, it, lt, lane);
+                float lg[kCls];
+                mlp_logits_wave(a.model->w, fv, mlp_act, lg);
+                ord = valid ? decode_order(lg, a.model->safety) : 0;
+                opened = ord < 2;
             } else {
-                emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
+                visits += kk;
+                valid = lane < kk;
+                int d = 0;
+                bool cand = false;
+                const int B = (int)(it >> 5), s = (int)(it & 31);
+                if (valid) {
+                    gb = cell4[2 * B];
+                    if (MODE == kModePlain) {
+                        d = mac_decide(ga, gb, s, mc);
+                    } else {
+                        MacEval ev = mac_eval(ga, gb, s, mc);
+                        d = ev.code;
+                        cand = d != 0 && !ev.straddle && ev.q2 <= a.theta_max2;
+                    }
+                }
+                if (MODE == kModeExport) emit(a, kKindCand, Ls[kKindCand], bnext, bend, cand, it, lt, lane);
+                if (MODE == kModeLearned) {
+                    // candidates wait in the queue; the rest are pruned (d = 0) or opened
+                    const uint64_t cm = __ballot(cand);
+                    if (cand) cand_q[(qtail + __popcll(cm & lt)) & (kCandQ - 1)] = it;
+                    qtail += __popcll(cm);
+                    valid = valid && !cand;
+                    ord = 0;
+                    opened = d != 0;
+                } else {
+                    ord = d == 1 ? 2 : 0;
+                    opened = d == 2;
+                }
             }
-            emit(a, 1, Ls[1], bnext, bend, is_p2p, it, lt, lane);
-            emit(a, 2, Ls[2], bnext, bend, is_pd, it, lt, lane);
-            if (MODE == kModeExport) emit(a, kKindCand, Ls[kKindCand], bnext, bend, cand, it, lt, lane);
-            int nch = open_src ? xln_nchild(gb.x) : 0;
-            int incl = wave_incl_scan(nch, lane);
-            int tot = __builtin_amdgcn_readlane(incl, 63);
-            if (tot > 0) {
-                if (sp + tot > scap) {
-                    if (lane == 0) atomicOr(a.err, 1);
-                    failed = true;
-                    break;
-                }
-                if (nch > 0) {
-                    int off = sp + incl - nch;
-                    for (int q = 0; q < nch; ++q) stk[off + q] = (uint32_t)(gb.w + q) << 5 | (uint32_t)s;
-                }
-                sp += tot;
-                __syncthreads();  // pushes complete before the next pop reads them
+            if (!finish(valid, it, gb, ord, opened)) {
+                failed = true;
+                break;
             }
         }
         if (failed) continue;
@@ -379,6 +424,20 @@ constexpr int kPoolByte = 256;
 constexpr int kCounterBytes = kPoolByte + kKinds * kPoolStride * 4;
 static_assert(kCounterBytes <= kHostInts * 4, "counter readback exceeds the pinned area");
 
+// Wave w starts with chunks [w kChunkBlock, (w+1) kChunkBlock) of every list kind, and
+// the counters start past those blocks: no wave needs an atomic for its first block.
+__global__ void k_wstate_init(int *ws, int nw, int *pool)
+{
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < nw)
+        for (int k = 0; k < kKinds; ++k) {
+            ws[(size_t)w * 2 * kKinds + k] = w * kChunkBlock;
+            ws[(size_t)w * 2 * kKinds + kKinds + k] = (w + 1) * kChunkBlock;
+        }
+    if (w == 0)
+        for (int k = 0; k < kKinds; ++k) pool[k * kPoolStride] = nw * kChunkBlock;
+}
+
 static int ensure_pools(fmm_tree *t, const int *want)
 {
     for (int k = 0; k < kKinds; ++k) {
@@ -431,7 +490,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         // at byte 128, P2P evaluated pairs at byte 192, pool counters from byte kPoolByte
         unsigned char *cb = ptr<unsigned char>(t->counters);
         hipMemsetAsync(cb, 0, kCounterBytes, st);
-        hipMemsetAsync(t->wstate.p, 0, (size_t)nw * 2 * kKinds * sizeof(int), st);
+        k_wstate_init<<<(nw + 255) / 256, 256, 0, st>>>(ptr<int>(t->wstate), nw,
+                                                        reinterpret_cast<int *>(cb + kPoolByte));
         hipMemsetAsync(t->lcnt.p, 0, (size_t)kKinds * ncell * 4, st);
         TravArgs a;
         a.cells = ptr<Cell>(t->cells);
@@ -479,7 +539,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         unsigned long long c64[4];
         int pools[kKinds], err;
         memcpy(c64, t->host, 32);
-        for (int k = 0; k < kKinds; ++k) pools[k] = t->host[kPoolByte / 4 + k * kPoolStride];
+        for (int k = 0; k < kKinds; ++k)  // kinds this mode does not write keep their size
+            pools[k] = want[k] ? t->host[kPoolByte / 4 + k * kPoolStride] : 0;
         memcpy(&err, (char *)t->host + 96, 4);
         if (err == 0) {
             unsigned long long ord[7];

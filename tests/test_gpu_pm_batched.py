@@ -58,6 +58,29 @@ def test_hybrid_equals_parts_and_approaches_ewald():
     assert rms_rel(tot, ew) < 2e-2
 
 
+def test_hybrid_on_caller_tree_matches_parts_and_reuses_tree():
+    """fmm_hybrid_forces_tree: PM written first, the short range added by the final kernel;
+    the caller's tree is rebuilt in place for a second, smaller box and keeps its stats."""
+    M = 32
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, r_cut=4.5 * rs, theta=0.4, p=5, n_crit=16, precision=1)
+    t = hf.Tree()
+    t.set_timing(True)
+    for n, seed in ((6000, 1), (2500, 2)):
+        pos, m = inputs.clustered(n, 4, inputs.rng_for(304, seed))
+        dp, dm = dev(pos), dev(m)
+        tot = t.hybrid(dp, dm, prm, M).cpu().numpy()
+        tot = t.hybrid(dp, dm, prm, M).cpu().numpy()  # second call on the same tree: timed
+        st = t.stats()
+        assert st["n"] == n and st["t_pm_ms"] > 0 and st["n_m2l"] > 0
+        lr = hf.pm_long_range(dp, dm, prm, M).cpu().numpy()
+        sr = hf.short_range(dp, dm, prm).cpu().numpy()
+        assert rms_rel(tot, lr + sr) < 1e-6
+        lib_owned = hf.hybrid(dp, dm, prm, M).cpu().numpy()
+        assert rms_rel(tot, lib_owned) < 1e-6
+    t.free()
+
+
 def _batch(nb, seed):
     rng = inputs.rng_for(303, seed)
     sizes = [0, 1, 2] + list(rng.integers(100, 3000, nb - 3))
