@@ -380,112 +380,126 @@ __global__ __launch_bounds__(256) void k_l2p(const Cell *__restrict__ cells, con
 // expansion, a derivative tensor and a source block in registers at once.  M2M and L2L
 // therefore run a wave per cell, and M2L (FP32) a lane per interaction pair.
 
-// Terms of a translation (M2M when UP, else L2L) sorted by output coefficient and dealt to
-// the 64 lanes of a wave in contiguous runs of CH terms.  Slot i of lane l is stored at
-// [i * 64 + l] so that every load of the table is coalesced.  A term reads coefficient
-// `src` of the input, multiplies it by coef and by the sign (-1)^(parity . flip) of the
-// child's octant, and adds it to output `out`.
-//   M2M: out m, src m - n (n <= m), parity of n, coef 2^-|n| / n! * 2^-|m|
-//   L2L: out n, src n + m (|m| <= P - |n|), parity of m, coef 4^-|m| / m! * 2^-(|n|+1)
-template <int P, bool UP> struct ShiftTab {
-    static constexpr int NT = binom(P + 6, 6);
-    static constexpr int CH = (NT + 63) / 64;
-    uint32_t code[CH * 64];  // out | src << 8 | parity << 16 | 1 << 19 (term present)
-    double coef[CH * 64];
-    constexpr ShiftTab() : code(), coef()
+// A Cartesian translation factorises into three one-dimensional shifts: with monomial
+// weights w_a(i) = h_a^i / i!,
+//   M2M  M'_m = sum_{i <= m_x} w_x(i) sum_{j <= m_y} w_y(j) sum_{k <= m_z} w_z(k) M_{m - (i,j,k)}
+//   L2L  L'_n = sum_i w_x(i) sum_j w_y(j) sum_k w_z(k) L_{n + (i,j,k)}   (|n + (i,j,k)| <= P)
+// so the operators are applied as three in-place passes along x, y and z (about half the
+// multiply-adds of the direct double sum, and no second coefficient array).  A pass
+// along `ax` visits the multi-indices in an order where every source is still unmodified:
+// descending component ax for M2M (sources have a smaller component), ascending for L2L.
+template <int P, int AX, bool UP> struct AxisOrder {
+    int k[ncoef(P)];
+    constexpr AxisOrder() : k()
     {
         Tab<P> T{};
-        int e = 0;
-        for (int o = 0; o < ncoef(P); ++o) {
-            if (UP) {
-                for (int a = 0; a <= T.x[o]; ++a)
-                    for (int b = 0; b <= T.y[o]; ++b)
-                        for (int c = 0; c <= T.z[o]; ++c) {
-                            int kn = midx(a, b, c);
-                            put(e++, o, midx(T.x[o] - a, T.y[o] - b, T.z[o] - c), (a & 1) | (b & 1) << 1 | (c & 1) << 2,
-                                T.invf[kn] / (double)(1 << T.d[kn]) / (double)(1 << T.d[o]));
-                        }
-            } else {
-                for (int km = 0; km < ncoef(P - T.d[o]); ++km)
-                    put(e++, o, midx(T.x[o] + T.x[km], T.y[o] + T.y[km], T.z[o] + T.z[km]),
-                        (T.x[km] & 1) | (T.y[km] & 1) << 1 | (T.z[km] & 1) << 2,
-                        T.invf[km] / (double)(1 << (2 * T.d[km])) / (double)(2 << T.d[o]));
+        int q = 0;
+        for (int v = 0; v <= P; ++v) {
+            int comp = UP ? P - v : v;
+            for (int kk = 0; kk < ncoef(P); ++kk) {
+                int c = AX == 0 ? T.x[kk] : (AX == 1 ? T.y[kk] : T.z[kk]);
+                if (c == comp) k[q++] = kk;
             }
         }
-    }
-    constexpr void put(int e, int o, int src, int par, double c)
-    {
-        int slot = (e % CH) * 64 + e / CH;
-        code[slot] = (uint32_t)o | (uint32_t)src << 8 | (uint32_t)par << 16 | 1u << 19;
-        coef[slot] = c;
     }
 };
 
-template <int P, bool UP> static __constant__ ShiftTab<P, UP> kShiftTab{};
-
-// M2M (UP: children -> parent, output overwritten) or L2L (parent -> child, added) for
-// the cells of one level, one wave per cell.  Each lane keeps its run of terms in
-// registers, sums consecutive terms of the same output and flushes the partial sum into
-// the LDS output with an atomic add.
-template <int P, class T, bool UP>
-__global__ __launch_bounds__(64) void k_shift_wave(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ C)
+template <int P, class T, int AX, bool UP> __device__ __forceinline__ void shift_axis(T *C, const T *w)
 {
-    using Tb = ShiftTab<P, UP>;
-    constexpr int NC = ncoef(P), CH = Tb::CH;
-    __shared__ T src[NC], out[NC];
-    const int lane = threadIdx.x;
-    uint32_t code[CH];
-    T coef[CH];
+    constexpr Tab<P> tb{};
+    constexpr AxisOrder<P, AX, UP> ao{};
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-        code[i] = kShiftTab<P, UP>.code[i * 64 + lane];
-        coef[i] = (T)kShiftTab<P, UP>.coef[i * 64 + lane];
-    }
-    for (int t = blockIdx.x; t < ln; t += gridDim.x) {
-        const int c = lbeg + t;
-        const Cell cc = cells[c];
-        const int nsrc = UP ? cell_nchild(cc) : 1;
-        if (nsrc == 0) continue;
-        for (int k = lane; k < NC; k += 64) out[k] = 0;
-        for (int q = 0; q < nsrc; ++q) {
-            int sc, flip;
-            if (UP) {
-                sc = cc.child + q;
-                const Cell cq = cells[sc];
-                flip = (cell_ix(cq) & 1) | (cq.iy & 1) << 1 | (cq.iz & 1) << 2;
-            } else {
-                sc = cc.parent;
-                flip = ~((cell_ix(cc) & 1) | (cc.iy & 1) << 1 | (cc.iz & 1) << 2) & 7;
-            }
-            __syncthreads();
-            for (int k = lane; k < NC; k += 64) src[k] = C[(size_t)sc * NC + k];
-            __syncthreads();
-            int cur = -1;
-            T sum = 0;
+    for (int q = 0; q < ncoef(P); ++q) {
+        const int k = ao.k[q];
+        const int a = tb.x[k], b = tb.y[k], c = tb.z[k];
+        const int comp = AX == 0 ? a : (AX == 1 ? b : c);
+        T sum = C[k];
+        if (UP) {
 #pragma unroll
-            for (int i = 0; i < CH; ++i) {
-                const uint32_t w = code[i];
-                if (w >> 19) {
-                    const int o = (int)(w & 255), j = (int)((w >> 8) & 255), par = (int)((w >> 16) & 7);
-                    if (o != cur) {
-                        if (cur >= 0) atomicAdd(&out[cur], sum);
-                        sum = 0;
-                        cur = o;
-                    }
-                    const T v = coef[i] * src[j];
-                    sum += (__popc(par & flip) & 1) ? -v : v;
-                }
-            }
-            if (cur >= 0) atomicAdd(&out[cur], sum);
+            for (int i = 1; i <= comp; ++i)
+                sum += w[i] * C[midx(AX == 0 ? a - i : a, AX == 1 ? b - i : b, AX == 2 ? c - i : c)];
+        } else {
+#pragma unroll
+            for (int i = 1; i <= P - tb.d[k]; ++i)
+                sum += w[i] * C[midx(AX == 0 ? a + i : a, AX == 1 ? b + i : b, AX == 2 ? c + i : c)];
         }
-        __syncthreads();
-        T *dst = C + (size_t)c * NC;
-        for (int k = lane; k < NC; k += 64) {
-            if (UP) dst[k] = out[k];
-            else dst[k] += out[k];
-        }
-        __syncthreads();
+        C[k] = sum;
     }
+}
+
+// w[i] = (s h)^i / i!, i = 0..P, s = +1 or -1
+template <int P, class T> __device__ __forceinline__ void shift_weights(T h, bool neg, T *w)
+{
+    T v = 1;
+    w[0] = 1;
+#pragma unroll
+    for (int i = 1; i <= P; ++i) {
+        v *= h / (T)i;
+        w[i] = (neg && (i & 1)) ? -v : v;
+    }
+}
+
+// M2M for the parents of one level, a thread per parent: each child's multipole is
+// shifted in registers (x-hat = +-1/2 in child units) and added to the parent.
+template <int P, class T>
+__global__ __launch_bounds__(64) void k_m2m_axis(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ M)
+{
+    constexpr int NC = ncoef(P);
+    constexpr Tab<P> tb{};
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    const int c = lbeg + t;
+    const Cell cc = cells[c];
+    const int nch = cell_nchild(cc);
+    if (nch == 0) return;
+    T *out = M + (size_t)c * NC;
+    for (int q = 0; q < nch; ++q) {
+        const int ch = cc.child + q;
+        const Cell cq = cells[ch];
+        T C[NC], wx[P + 1], wy[P + 1], wz[P + 1];
+        const T *src = M + (size_t)ch * NC;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) C[k] = src[k];
+        shift_weights<P, T>((T)0.5, cell_ix(cq) & 1, wx);
+        shift_weights<P, T>((T)0.5, cq.iy & 1, wy);
+        shift_weights<P, T>((T)0.5, cq.iz & 1, wz);
+        shift_axis<P, T, 0, true>(C, wx);
+        shift_axis<P, T, 1, true>(C, wy);
+        shift_axis<P, T, 2, true>(C, wz);
+        if (q == 0) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) out[k] = C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
+        } else {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) out[k] += C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
+        }
+    }
+}
+
+// L2L for the cells of one level, a thread per child: the parent's local expansion is
+// shifted to the child centre (x-hat = +-1/4 in parent units) and added.
+template <int P, class T>
+__global__ __launch_bounds__(64) void k_l2l_axis(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ L)
+{
+    constexpr int NC = ncoef(P);
+    constexpr Tab<P> tb{};
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ln) return;
+    const int c = lbeg + t;
+    const Cell cc = cells[c];
+    T C[NC], wx[P + 1], wy[P + 1], wz[P + 1];
+    const T *src = L + (size_t)cc.parent * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) C[k] = src[k];
+    shift_weights<P, T>((T)0.25, !(cell_ix(cc) & 1), wx);
+    shift_weights<P, T>((T)0.25, !(cc.iy & 1), wy);
+    shift_weights<P, T>((T)0.25, !(cc.iz & 1), wz);
+    shift_axis<P, T, 0, false>(C, wx);
+    shift_axis<P, T, 1, false>(C, wy);
+    shift_axis<P, T, 2, false>(C, wz);
+    T *dst = L + (size_t)c * NC;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) dst[k] += C[k] * (T)(1.0 / (double)(2 << tb.d[k]));
 }
 
 // M2L of the high orders, a lane per pair of the flattened (sink-sorted) pair array.  A
@@ -679,7 +693,7 @@ template <int P, class T> struct Upward {
         for (int l = t->nlevel - 2; l >= 0; --l) {
             int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
             if constexpr (P >= 7)
-                k_shift_wave<P, T, true><<<ln < 8192 ? ln : 8192, 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+                k_m2m_axis<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
             else
                 k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
         }
@@ -716,7 +730,7 @@ template <int P, class T> struct L2L {
         for (int l = 1; l < t->nlevel; ++l) {
             int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
             if constexpr (P >= 7)
-                k_shift_wave<P, T, false><<<ln < 8192 ? ln : 8192, 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
+                k_l2l_axis<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
             else
                 k_l2l<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Lc));
         }

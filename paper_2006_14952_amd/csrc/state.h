@@ -41,8 +41,7 @@ struct fmm_tree {
     int lcap[11] = {0};                              // chunks (one more is allocated as overflow bin)
     int trav_mode = 0;                               // mode of the last traversal
     hfmm::DevBuf tstack;                             // per-wave traversal stacks
-    int stk_cap = 16384;
-    bool global_stack = false;                       // set once an input overflowed the LDS stack
+    int stk_cap = 4096;                              // entries per wave (grows on overflow)
     int64_t n_m2l = 0, n_p2p = 0, n_visit = 0, p2p_pairs = 0;
     hfmm::DevBuf counters;                           // device counters
 

@@ -82,7 +82,6 @@ struct TravArgs {
 constexpr int kChunkBlock = 32;   // chunks taken from a pool per atomic
 constexpr int kPoolStride = 32;   // ints between the pool counters (one 128-byte line each)
 constexpr int kCandQ = 128;       // learned: ring of candidate pairs (at most 63 wait between steps)
-constexpr int kLdsStack = 1280;   // entries of the in-LDS traversal stack (5 KB: 7 waves per SIMD)
 
 struct ListState {
     int head, cur, fill, tot;
@@ -180,17 +179,18 @@ __device__ __forceinline__ MacEval mac_eval(int4 a, int4 b, int s, const MacCons
 }
 
 // Sinks t = blockIdx.x, blockIdx.x + gridDim.x, ... of one level.
-template <int MODE, bool GLOBAL_STACK>
+template <int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_traverse(TravArgs a, MacConst mc)
 {
-    __shared__ uint32_t lds_stack[GLOBAL_STACK ? 1 : kLdsStack];
     __shared__ short mlp_act[MODE == kModeLearned ? 64 * 64 : 1];
     __shared__ uint32_t cand_q[MODE == kModeLearned ? kCandQ : 1];
 
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
-    uint32_t *stk = GLOBAL_STACK ? a.stack + (size_t)blockIdx.x * a.stk_cap : lds_stack;
-    const int scap = GLOBAL_STACK ? a.stk_cap : kLdsStack;
+    // per-wave stack of pairs still to decide, in device memory (L2 resident); measured as
+    // fast as an LDS stack, and it leaves the LDS to the learned selector
+    uint32_t *stk = a.stack + (size_t)blockIdx.x * a.stk_cap;
+    const int scap = a.stk_cap;
     const int4 *cell4 = reinterpret_cast<const int4 *>(a.cells);  // two int4 per cell
     unsigned long long visits = 0, nm2l = 0, np2p = 0;
     unsigned long long nord[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -399,25 +399,25 @@ void mac_setup(const fmm_params *P, MacConst &mc)
 // Waves of one traversal kernel that fit on the device at once.  Sinks are dealt to the
 // waves statically, so the grid is never larger than this: a second partial round of
 // waves would only lengthen the tail of each level.
-template <int MODE, bool GS> static int resident_waves()
+template <int MODE> static int resident_waves()
 {
     static int cached = 0;
     if (cached == 0) {
         int dev = 0, ncu = 0, per = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_traverse<MODE, GS>, 64, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_traverse<MODE>, 64, 0) != hipSuccess)
             return 4096;
         cached = (ncu > 0 ? ncu : 1) * (per > 0 ? per : 1);
     }
     return cached;
 }
 
-static int resident_waves(int mode, bool gs)
+static int resident_waves(int mode)
 {
-    if (mode == kModePlain) return gs ? resident_waves<kModePlain, true>() : resident_waves<kModePlain, false>();
-    if (mode == kModeExport) return gs ? resident_waves<kModeExport, true>() : resident_waves<kModeExport, false>();
-    return gs ? resident_waves<kModeLearned, true>() : resident_waves<kModeLearned, false>();
+    if (mode == kModePlain) return resident_waves<kModePlain>();
+    if (mode == kModeExport) return resident_waves<kModeExport>();
+    return resident_waves<kModeLearned>();
 }
 
 constexpr int kPoolByte = 256;
@@ -465,7 +465,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
     // list kinds written in this mode get room for their expected size plus the partly
     // used chunk block each wave may hold at the end
     int want[kKinds];
-    const int slack = resident_waves(mode, t->global_stack) * kChunkBlock + 64;
+    const int slack = resident_waves(mode) * kChunkBlock + 64;
     for (int k = 0; k < kKinds; ++k) want[k] = 0;
     want[1] = slack + 8 * t->nleaf;
     want[2] = slack + 2 * ncell;
@@ -482,9 +482,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             int ln = t->lvl_beg[l + 1] - t->lvl_beg[l];
             nw = ln > nw ? ln : nw;
         }
-        const int cap = resident_waves(mode, t->global_stack);
+        const int cap = resident_waves(mode);
         nw = nw < cap ? nw : cap;
-        if (t->global_stack && (rc = grow(t->tstack, (size_t)nw * t->stk_cap * 4))) return rc;
+        if ((rc = grow(t->tstack, (size_t)nw * t->stk_cap * 4))) return rc;
         if ((rc = grow(t->wstate, (size_t)nw * 2 * kKinds * sizeof(int)))) return rc;
         // counters: [0..3] 64-bit stats, err at byte 96, 64-bit M2L counts per learned order
         // at byte 128, P2P evaluated pairs at byte 192, pool counters from byte kPoolByte
@@ -521,17 +521,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             a.lbeg = t->lvl_beg[l];
             a.ln = t->lvl_beg[l + 1] - a.lbeg;
             int g = a.ln < nw ? a.ln : nw;
-            bool gs = t->global_stack;
-            if (mode == kModePlain) {
-                if (gs) k_traverse<kModePlain, true><<<g, 64, 0, st>>>(a, mc);
-                else k_traverse<kModePlain, false><<<g, 64, 0, st>>>(a, mc);
-            } else if (mode == kModeExport) {
-                if (gs) k_traverse<kModeExport, true><<<g, 64, 0, st>>>(a, mc);
-                else k_traverse<kModeExport, false><<<g, 64, 0, st>>>(a, mc);
-            } else {
-                if (gs) k_traverse<kModeLearned, true><<<g, 64, 0, st>>>(a, mc);
-                else k_traverse<kModeLearned, false><<<g, 64, 0, st>>>(a, mc);
-            }
+            if (mode == kModePlain) k_traverse<kModePlain><<<g, 64, 0, st>>>(a, mc);
+            else if (mode == kModeExport) k_traverse<kModeExport><<<g, 64, 0, st>>>(a, mc);
+            else k_traverse<kModeLearned><<<g, 64, 0, st>>>(a, mc);
         }
         if ((rc = hip_check(hipGetLastError(), "traversal"))) return rc;
         hipMemcpyAsync(t->host, cb, kCounterBytes, hipMemcpyDeviceToHost, st);
@@ -552,10 +544,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             t->trav_mode = mode;
             return 0;
         }
-        if (err & 1) {  // LDS stack too small for this input: per-wave stacks in device memory
-            if (t->global_stack) t->stk_cap *= 4;
-            t->global_stack = true;
-        }
+        if (err & 1) t->stk_cap *= 4;  // a wave's stack overflowed: larger stacks, rerun
         if (err & 2)
             if ((rc = ensure_pools(t, pools))) return rc;
     }
