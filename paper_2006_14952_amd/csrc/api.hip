@@ -72,23 +72,50 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     fmm_params P8 = *P;
     if (P->learned) P8.p = 8;
     int rc;
+    if (!t->aux) {
+        if (hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking) != hipSuccess)
+            return set_error(FMM_ERR_HIP, "hipStreamCreateWithFlags");
+        for (auto &e : t->dep)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return set_error(FMM_ERR_HIP, "hipEventCreateWithFlags");
+    }
+    hipStream_t ax = t->aux;
+    // Dependencies: upward -> M2L; traversal -> {M2L, P2P}; M2L -> L2L; {L2L, P2P} -> L2P.
+    // The plain traversal does not read multipoles, so the upward pass runs beside it on
+    // the second stream; P2P runs there beside M2L and L2L.
+    hipEventRecord(t->dep[0], st);
     mark(t, 0, st);
-    if ((rc = upward(t, &P8, st))) return rc;
-    mark(t, 1, st);
-    if (P->learned)
+    if (P->learned) {  // the selector's features read the multipoles
+        mark(t, 9, st);
+        if ((rc = upward(t, &P8, st))) return rc;
+        mark(t, 1, st);
+        hipEventRecord(t->dep[1], st);
         rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st);
-    else
+    } else {
+        hipStreamWaitEvent(ax, t->dep[0], 0);
+        mark(t, 9, ax);
+        if ((rc = upward(t, &P8, ax))) return rc;
+        mark(t, 1, ax);
+        hipEventRecord(t->dep[1], ax);
         rc = traverse(t, P, st);
+    }
     if (rc) return rc;
     mark(t, 2, st);
+    hipEventRecord(t->dep[2], st);
+    hipStreamWaitEvent(ax, t->dep[2], 0);
+    mark(t, 5, ax);
+    if ((rc = p2p(t, P, ax))) return rc;
+    mark(t, 6, ax);
+    hipEventRecord(t->dep[3], ax);
+    hipStreamWaitEvent(st, t->dep[1], 0);
     if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
     mark(t, 3, st);
     if ((rc = downward_l2l(t, &P8, st))) return rc;
     mark(t, 4, st);
-    if ((rc = p2p(t, P, st))) return rc;
-    mark(t, 5, st);
+    hipStreamWaitEvent(st, t->dep[3], 0);
+    mark(t, 10, st);
     if ((rc = l2p_combine(t, &P8, acc, accumulate, st))) return rc;
-    mark(t, 6, st);
+    mark(t, 11, st);
     t->last_p = P->p;
     t->last_prec = P->precision;
     fmm_stats &S = t->stats;
@@ -96,14 +123,14 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     S.n_p2p = t->n_p2p;
     S.n_visit = t->n_visit;
     S.levels_traversed = t->nlevel;
-    if (t->timing) {
-        hipEventSynchronize(t->ev[6]);
-        S.t_upward_ms = ev_ms(t, 0, 1);
-        S.t_traverse_ms = ev_ms(t, 1, 2);
+    if (t->timing) {  // stages overlap across the two streams; each time is its own span
+        hipEventSynchronize(t->ev[11]);
+        S.t_upward_ms = ev_ms(t, 9, 1);
+        S.t_traverse_ms = P->learned ? ev_ms(t, 1, 2) : ev_ms(t, 0, 2);
         S.t_m2l_ms = ev_ms(t, 2, 3);
-        S.t_downward_ms = ev_ms(t, 3, 4) + ev_ms(t, 5, 6);
-        S.t_p2p_ms = ev_ms(t, 4, 5);
-        S.t_total_ms = ev_ms(t, 0, 6);
+        S.t_downward_ms = ev_ms(t, 3, 4) + ev_ms(t, 10, 11);
+        S.t_p2p_ms = ev_ms(t, 5, 6);
+        S.t_total_ms = ev_ms(t, 0, 11);
     }
     return hip_check(hipGetLastError(), "short range forces");
 }
@@ -382,6 +409,11 @@ void fmm_free_tree(fmm_tree *t)
     if (t->host) (void)hipHostFree(t->host);
     if (t->events_ready)
         for (auto &e : t->ev) (void)hipEventDestroy(e);
+    if (t->aux) {
+        (void)hipStreamSynchronize(t->aux);
+        for (auto &e : t->dep) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(t->aux);
+    }
     delete t;
 }
 

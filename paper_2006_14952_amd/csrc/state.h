@@ -53,6 +53,10 @@ struct fmm_tree {
     int *host = nullptr;  // pinned readback area (kHostInts ints)
     int last_p = -1, last_prec = -1;
 
+    // second stream (default priority) for stages independent of the caller's stream
+    hipStream_t aux = nullptr;
+    hipEvent_t dep[4]{};
+
     // timing
     int timing = 0;
     fmm_stats stats{};
