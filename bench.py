@@ -34,7 +34,7 @@ P2P_FLOP_PER_PAIR = 38.0
 WORKLOADS = {
     "clustered": dict(theta=0.4, precision=1, n_crit=32, learned=False),
     "uniform": dict(theta=0.5, precision=0, n_crit=32, learned=False),
-    "batched": dict(theta=0.4, precision=1, n_crit=32, learned=False),
+    "batched": dict(theta=0.4, precision=1, n_crit=32, learned=False, autotune=True),
     "large": dict(theta=0.5, precision=1, n_crit=32, learned=False),
     "full": dict(theta=0.5, precision=1, n_crit=32, learned=True, hybrid=True),
 }
@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--n-crit", type=int, default=None)
+    ap.add_argument("--autotune", type=int, default=None, choices=(0, 1),
+                    help="1: choose n_crit with the library's autotuner before timing (default: batched only)")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
                     help="1: per-pair acceptance and order from the trained selector (packaged model file)")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -105,6 +107,11 @@ def main():
     dev = torch.device("cuda:0")
     pos = torch.tensor(pos_np, device=dev)
     mass = torch.tensor(m_np, device=dev)
+    tuned = None
+    if (args.autotune if args.autotune is not None else wl.get("autotune", False)) and not hybrid:
+        best, ms = hf.autotune(pos, mass, prm, offsets=offsets if batched else None)
+        prm.n_crit = wl["n_crit"] = best
+        tuned = {str(k): round(v, 3) for k, v in ms.items()}
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     tree = hf.Tree()
@@ -168,7 +175,7 @@ def main():
             + (", " + sel + " in place of p and theta" if sel else "")
             + (", full hybrid step: PM on %d^3 mesh + short range" % mesh if hybrid else ""),
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
-            "selector": sel or "fixed p and theta"},
+            "selector": sel or "fixed p and theta", "autotuned_n_crit_ms": tuned},
         "roofline": {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_launch, "p2p_ms_per_launch": p2p_s * 1e3},

@@ -147,6 +147,19 @@ int fmm_build_tree_batched(const fmm_params *per_box, int nbox, const int64_t *o
 int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const int64_t *offsets,
                                    const double *pos, const double *mass, double *acc, void *stream);
 
+/* Autotuner: times complete steps (tree build + fmm_short_range_forces with the
+ * parameters in params) for each leaf limit in candidates[0..ncand-1] (each >= 1), reps
+ * timed steps each after one untimed one, on the caller's particles, and returns the
+ * fastest in *best_n_crit.  The leaf limit sets the tile shape of every stage (P2P sink
+ * and source tiles, list lengths, tree depth).  nbox = 1 tunes one box (offsets may be
+ * NULL); nbox > 1 tunes the forest of fmm_build_tree_batched (offsets: HOST array of
+ * nbox+1 entries, offsets[nbox] = n).  ms_out (host, ncand entries, may be NULL)
+ * receives the mean step time of each candidate; acc (device, (n,3)) is scratch for the
+ * forces.  Uses a temporary tree; synchronises the stream. */
+int fmm_autotune(const fmm_params *params, int nbox, const int64_t *offsets, int64_t n, const double *pos,
+                 const double *mass, double *acc, const int *candidates, int ncand, int reps, void *stream,
+                 int *best_n_crit, double *ms_out);
+
 /* Counters and stage times of the last force evaluation (host struct, caller-owned). */
 int fmm_get_stats(const fmm_tree *tree, fmm_stats *out);
 

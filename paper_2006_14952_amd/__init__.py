@@ -71,6 +71,8 @@ def lib():
         L.fmm_short_range_forces_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, dp, vp]
         L.fmm_build_tree_batched.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), dp, dp, vp, C.POINTER(vp)]
         L.fmm_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.fmm_autotune.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), i64, dp, dp, dp, C.POINTER(C.c_int),
+                                   C.c_int, C.c_int, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.fmm_set_timing.argtypes = [vp, C.c_int]
         L.fmm_copy_interactions.argtypes = [vp, C.c_int, vp, i64, C.POINTER(i64)]
         L.fmm_load_mac_model.argtypes = [C.c_char_p]
@@ -217,6 +219,25 @@ def short_range(pos, mass, prm: Params, stream=None):
         return t.short_range(prm, stream=stream)
     finally:
         t.free()
+
+
+def autotune(pos, mass, prm: Params, candidates=(16, 24, 32, 48, 64), reps=2, offsets=None, stream=None):
+    """Leaf limit with the fastest build + short-range step on these particles
+    (fmm_autotune; a forest of boxes when offsets is given); returns
+    (best n_crit, {n_crit: ms per step})."""
+    import torch
+    n = int(pos.shape[0])
+    acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    cand = (C.c_int * len(candidates))(*[int(c) for c in candidates])
+    ms = (C.c_double * len(candidates))()
+    best = C.c_int()
+    nbox, off = 1, None
+    if offsets is not None:
+        nbox = len(offsets) - 1
+        off = (C.c_int64 * (nbox + 1))(*[int(v) for v in offsets])
+    _check(lib().fmm_autotune(C.byref(prm), nbox, off, n, _dev64(pos, (3,)), _dev64(mass), _dev64(acc, (3,)), cand,
+                              len(candidates), int(reps), _stream(stream), C.byref(best), ms))
+    return best.value, {int(c): float(m) for c, m in zip(candidates, ms)}
 
 
 def pm_long_range(pos, mass, prm: Params, mesh, out=None, stream=None):

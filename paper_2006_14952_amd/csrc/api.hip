@@ -231,6 +231,62 @@ int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *
     return run_forces(t, P, acc, (hipStream_t)stream);
 }
 
+int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t n, const double *pos,
+                 const double *mass, double *acc, const int *candidates, int ncand, int reps, void *stream,
+                 int *best_n_crit, double *ms_out)
+{
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (n <= 0 || !pos || !mass || !acc || !candidates || ncand <= 0 || !best_n_crit || nbox < 1 ||
+        (nbox > 1 && !offsets))
+        return set_error(FMM_ERR_ARG, "bad arguments");
+    if (nbox > 1 && offsets[nbox] != n) return set_error(FMM_ERR_ARG, "offsets[nbox] != n");
+    std::vector<fmm_params> per_box((size_t)nbox);
+    for (int c = 0; c < ncand; ++c)
+        if (candidates[c] < 1) return set_error(FMM_ERR_ARG, "n_crit candidate %d < 1", candidates[c]);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return set_error(FMM_ERR_HIP, "hipEventCreate");
+    fmm_tree *t = nullptr;
+    int rc = 0;
+    double best = 1e300;
+    *best_n_crit = candidates[0];
+    for (int c = 0; c < ncand && !rc; ++c) {
+        fmm_params Q = *P;
+        Q.n_crit = candidates[c];
+        for (auto &b : per_box) b = Q;
+        auto build = [&]() {
+            return nbox > 1 ? fmm_build_tree_batched(per_box.data(), nbox, offsets, pos, mass, stream, &t)
+                            : fmm_build_tree(&Q, n, pos, mass, stream, &t);
+        };
+        // one untimed step sizes the tree's buffers for this leaf size
+        rc = build();
+        if (!rc) rc = run_forces(t, &Q, acc, st);
+        float total = 0.0f;
+        for (int r = 0; r < (reps > 0 ? reps : 1) && !rc; ++r) {
+            hipEventRecord(e0, st);
+            rc = build();
+            if (!rc) rc = run_forces(t, &Q, acc, st);
+            hipEventRecord(e1, st);
+            if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune");
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            total += ms;
+        }
+        const double ms = total / (reps > 0 ? reps : 1);
+        if (ms_out) ms_out[c] = ms;
+        if (!rc && ms < best) {
+            best = ms;
+            *best_n_crit = Q.n_crit;
+        }
+    }
+    if (t) fmm_free_tree(t);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int fmm_get_stats(const fmm_tree *tc, fmm_stats *out)
 {
     if (!tc || !out) return set_error(FMM_ERR_ARG, "NULL argument");

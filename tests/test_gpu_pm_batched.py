@@ -131,6 +131,23 @@ def test_batched_forest_equals_single_box_runs():
     assert st["n_m2l"] == n_m2l and st["n_p2p"] == n_p2p
 
 
+def test_autotune_single_box_and_forest():
+    """fmm_autotune returns the fastest of its candidates (by its own timings), for one box
+    and for a forest; forces at the chosen leaf limit still match the oracle."""
+    pos, m = inputs.clustered(20000, 10, inputs.rng_for(305))
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.4, p=4, n_crit=32, precision=1)
+    best, ms = hf.autotune(dev(pos), dev(m), prm, candidates=(8, 16, 32, 64), reps=1)
+    assert best in ms and all(v > 0 for v in ms.values()) and ms[best] == min(ms.values())
+    prm.n_crit = best
+    got = hf.short_range(dev(pos), dev(m), prm).cpu().numpy()
+    ref = oracle.fmm(pos, m, oracle.make_params(rs=0.012, rcut=0.054, theta=0.4, p=4, ncrit=best)).acc
+    assert np.percentile(rel_err(got, ref), 99) <= 1e-4
+    boxes, off, bp, bm = _batch(6, 7)
+    bprm = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=16, precision=1)
+    best_b, ms_b = hf.autotune(dev(bp), dev(bm), bprm, candidates=(8, 16, 32), reps=1, offsets=off)
+    assert best_b in (8, 16, 32) and ms_b[best_b] == min(ms_b.values())
+
+
 def test_batched_rejects_mixed_params():
     boxes, off, pos, m = _batch(4, 9)
     a = hf.params(r_s=0.02, p=4)
