@@ -15,8 +15,9 @@
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
 // degree-10 polynomial fitted on the host; the sum of each staged block is added to a
 // Kahan-compensated per-particle accumulator.  A listed source leaf whose particles'
-// bounding box lies farther than r_cut from the sink leaf's box holds no pair inside the
-// cutoff and is not staged (the lists themselves are unchanged).
+// bounding box lies farther than r_cut from the sink leaf's box, and any single source
+// particle farther than r_cut from that box, hold no pair inside the cutoff and are not
+// staged (the lists themselves are unchanged).
 #include <math.h>
 
 #include <type_traits>
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
     __shared__ int ebeg[64], epref[64];
     __shared__ R eoff[64][3];
     const int lane = threadIdx.x;
+    const uint64_t lt = (1ull << lane) - 1ull;
     const int A = a.leaves[blockIdx.x];
     const Cell ca = a.cells[A];
     const double hA = ldexp(a.box, -cell_level(ca));
@@ -169,21 +171,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
             const int total = __builtin_amdgcn_readlane(incl, 63);
             const int ltot = F64 ? total : __builtin_amdgcn_readlane(wave_incl_scan(listed), 63);
             npairs += (unsigned long long)ns * (unsigned)ltot;
-            nevald += (unsigned long long)ns * (unsigned)total;
             __syncthreads();
             for (int sb = 0; sb < total; sb += kStage) {
-                const int nst = min(kStage, total - sb);
-                for (int q = lane; q < nst; q += 64) {
-                    int slot = sb + q;
-                    int e = find_entry(epref, ne, slot);
-                    int j = ebeg[e] + slot - epref[e];
-                    if constexpr (F64) {
+                const int nraw = min(kStage, total - sb);
+                int nst = nraw;
+                if constexpr (F64) {
+                    for (int q = lane; q < nraw; q += 64) {
+                        int slot = sb + q;
+                        int e = find_entry(epref, ne, slot);
+                        int j = ebeg[e] + slot - epref[e];
                         src[q] = make_double4(a.xs[j] + eoff[e][0], a.ys[j] + eoff[e][1], a.zs[j] + eoff[e][2], a.ms[j]);
-                    } else {
-                        float4 r = a.rel[j];
-                        src[q] = make_float4(r.x + eoff[e][0], r.y + eoff[e][1], r.z + eoff[e][2], r.w);
+                    }
+                } else {
+                    // a source particle farther than r_cut from the sink leaf's box meets no
+                    // sink particle inside the cutoff: it is not staged (ballot compaction)
+                    nst = 0;
+                    for (int q0 = 0; q0 < nraw; q0 += 64) {
+                        const int q = q0 + lane;
+                        bool keep = false;
+                        float4 sv = make_float4(0, 0, 0, 0);
+                        if (q < nraw) {
+                            int slot = sb + q;
+                            int e = find_entry(epref, ne, slot);
+                            int j = ebeg[e] + slot - epref[e];
+                            float4 r = a.rel[j];
+                            sv = make_float4(r.x + eoff[e][0], r.y + eoff[e][1], r.z + eoff[e][2], r.w);
+                            const float gx = fmaxf(0.0f, fmaxf(alo.x - sv.x, sv.x - ahi.x));
+                            const float gy = fmaxf(0.0f, fmaxf(alo.y - sv.y, sv.y - ahi.y));
+                            const float gz = fmaxf(0.0f, fmaxf(alo.z - sv.z, sv.z - ahi.z));
+                            keep = gx * gx + gy * gy + gz * gz <= k.rc2 * 1.0001f;
+                        }
+                        const uint64_t km = __ballot(keep);
+                        if (keep) src[nst + __popcll(km & lt)] = sv;
+                        nst += __popcll(km);
                     }
                 }
+                nevald += (unsigned long long)ns * (unsigned)nst;
                 __syncthreads();
                 if (valid) {
                     if constexpr (F64) {
