@@ -102,12 +102,13 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 constexpr int kStage = 192;
 
 template <bool F64>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8))) void k_p2p(P2PArgs a, P2PConst k)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6))) void k_p2p(P2PArgs a, P2PConst k)
 {
     using R = typename std::conditional<F64, double, float>::type;
     using V4 = typename std::conditional<F64, double4, float4>::type;
     __shared__ V4 src[kStage];
     __shared__ int ebeg[64], epref[64];
+    __shared__ int smark[kStage];
     __shared__ R eoff[64][3];
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -172,6 +173,53 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
             const int ltot = F64 ? total : __builtin_amdgcn_readlane(wave_incl_scan(listed), 63);
             npairs += (unsigned long long)ns * (unsigned)ltot;
             __syncthreads();
+            // FP32: the source records of a stage are loaded into registers one stage
+            // ahead, so their latency is covered by the pair work of the current stage
+            constexpr int kPer = kStage / 64;
+            float4 rv[kPer];
+            int ev[kPer];
+            // slot -> list entry for the kStage slots from sbase: each entry marks the slot it
+            // starts at (the largest entry wins, so entries left empty by the box test are
+            // skipped), and a max-scan over the slots carries the marks forward.  Lane l
+            // owns slots kPer l .. kPer l + kPer - 1.
+            auto fetch = [&](int sbase) __attribute__((always_inline)) {
+                const int nraw = min(kStage, total - sbase);
+                const int efirst = find_entry(epref, ne, sbase);
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) smark[kPer * lane + u] = 0;
+                __syncthreads();
+                if (lane < ne) {
+                    const int st = epref[lane] - sbase;
+                    if (st >= 0 && st < kStage) atomicMax(&smark[st], lane + 1);
+                }
+                __syncthreads();
+                int mrun[kPer], m = 0;
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    m = max(m, smark[kPer * lane + u]);
+                    mrun[u] = m;
+                }
+                int incl = m;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int v = __shfl_up(incl, o, 64);
+                    if (lane >= o) incl = max(incl, v);
+                }
+                int prev = __shfl_up(incl, 1, 64);
+                if (lane == 0) prev = 0;
+                const int base = max(prev, efirst + 1);
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const int q = kPer * lane + u;
+                    ev[u] = -1;
+                    if (q < nraw) {
+                        const int e = max(base, mrun[u]) - 1;
+                        ev[u] = e;
+                        rv[u] = a.rel[ebeg[e] + sbase + q - epref[e]];
+                    }
+                }
+            };
+            if (!F64 && total > 0) fetch(0);
             for (int sb = 0; sb < total; sb += kStage) {
                 const int nraw = min(kStage, total - sb);
                 int nst = nraw;
@@ -186,16 +234,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
                     // a source particle farther than r_cut from the sink leaf's box meets no
                     // sink particle inside the cutoff: it is not staged (ballot compaction)
                     nst = 0;
-                    for (int q0 = 0; q0 < nraw; q0 += 64) {
-                        const int q = q0 + lane;
+#pragma unroll
+                    for (int u = 0; u < kPer; ++u) {
                         bool keep = false;
                         float4 sv = make_float4(0, 0, 0, 0);
-                        if (q < nraw) {
-                            int slot = sb + q;
-                            int e = find_entry(epref, ne, slot);
-                            int j = ebeg[e] + slot - epref[e];
-                            float4 r = a.rel[j];
-                            sv = make_float4(r.x + eoff[e][0], r.y + eoff[e][1], r.z + eoff[e][2], r.w);
+                        if (ev[u] >= 0) {
+                            const int e = ev[u];
+                            sv = make_float4(rv[u].x + eoff[e][0], rv[u].y + eoff[e][1], rv[u].z + eoff[e][2], rv[u].w);
                             const float gx = fmaxf(0.0f, fmaxf(alo.x - sv.x, sv.x - ahi.x));
                             const float gy = fmaxf(0.0f, fmaxf(alo.y - sv.y, sv.y - ahi.y));
                             const float gz = fmaxf(0.0f, fmaxf(alo.z - sv.z, sv.z - ahi.z));
@@ -205,6 +250,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 8)
                         if (keep) src[nst + __popcll(km & lt)] = sv;
                         nst += __popcll(km);
                     }
+                    if (sb + kStage < total) fetch(sb + kStage);
                 }
                 nevald += (unsigned long long)ns * (unsigned)nst;
                 __syncthreads();
