@@ -109,64 +109,103 @@ __device__ __forceinline__ short f2bf(float x)  // round to nearest even
     return (short)(u >> 16);
 }
 
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// two FP32 values rounded to BF16 (nearest even, v_cvt_pk_bf16_f32), packed
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b)
+{
+    bf2v v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 // Logits of the 64 pairs of a wave (one per lane; lanes without a pair take part with
 // zero features).  `act` is 64 x 64 BF16 of LDS, `out` receives 8 logits per lane.
 // v_mfma_f32_16x16x16_bf16 operand layout (per lane l): A[i = l%16][k = 4(l/16)+r],
-// B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.  Row tile t holds
-// pairs 16t .. 16t+15.  Each layer first reads all its input fragments, then writes its
-// output over the same LDS rows, so every weight fragment is read once per call (the
-// weights stay in global memory: 12 KB shared by all waves, cache resident).
+// B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.  Each layer computes
+// the transposed product D = W^T act^T: the weight fragment is the A operand and the
+// activations the B operand, so a lane ends with 4 consecutive outputs of one pair and
+// writes them as one 8-byte store.  Row tile t holds pairs 16t .. 16t+15.  Each layer
+// first reads all its input fragments, then writes its output over the same LDS rows.
 __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float *fin, short *act, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lk = lane >> 4;
-    for (int k = 0; k < kFeat; ++k) act[lane * 64 + k] = f2bf((fin[k] - W.mu[k]) * W.isd[k]);
+    {
+        uint32_t pk[kFeat / 2];
+#pragma unroll
+        for (int k = 0; k < kFeat; k += 2)
+            pk[k / 2] = pack_bf16((fin[k] - W.mu[k]) * W.isd[k], (fin[k + 1] - W.mu[k + 1]) * W.isd[k + 1]);
+        uint4 *row = reinterpret_cast<uint4 *>(act + lane * 64);
+        row[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        row[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+    }
     __syncthreads();
     // layer 1: 16 -> 64
     short4v a1[4];
-    for (int t = 0; t < 4; ++t)
-        for (int r = 0; r < 4; ++r) a1[t][r] = act[(16 * t + li) * 64 + 4 * lk + r];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a1[t] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 4 * lk);
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const short4v b = W.w1[u][lane];
-        const float bias = W.b1[16 * u + li];
+        const short4v w = W.w1[u][lane];
+        const float4 bias = *reinterpret_cast<const float4 *>(W.b1 + 16 * u + 4 * lk);
+#pragma unroll
         for (int t = 0; t < 4; ++t) {
-            float4v c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[t], b, float4v{0, 0, 0, 0}, 0, 0, 0);
-            for (int r = 0; r < 4; ++r) act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[r] + bias, 0.0f));
+            const float4v c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a1[t], float4v{0, 0, 0, 0}, 0, 0, 0);
+            *reinterpret_cast<uint2 *>(act + (16 * t + li) * 64 + 16 * u + 4 * lk) =
+                make_uint2(pack_bf16(fmaxf(c[0] + bias.x, 0.0f), fmaxf(c[1] + bias.y, 0.0f)),
+                           pack_bf16(fmaxf(c[2] + bias.z, 0.0f), fmaxf(c[3] + bias.w, 0.0f)));
         }
     }
     __syncthreads();
     // layer 2: 64 -> 64
     short4v a[4][4];
+#pragma unroll
     for (int t = 0; t < 4; ++t)
+#pragma unroll
         for (int kc = 0; kc < 4; ++kc)
-            for (int r = 0; r < 4; ++r) a[t][kc][r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
+            a[t][kc] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 16 * kc + 4 * lk);
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
         float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
-            const short4v b = W.w2[kc][u][lane];
-            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t][kc], b, c[t], 0, 0, 0);
+            const short4v w = W.w2[kc][u][lane];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a[t][kc], c[t], 0, 0, 0);
         }
-        const float bias = W.b2[16 * u + li];
+        const float4 bias = *reinterpret_cast<const float4 *>(W.b2 + 16 * u + 4 * lk);
+#pragma unroll
         for (int t = 0; t < 4; ++t)
-            for (int r = 0; r < 4; ++r) act[(16 * t + 4 * lk + r) * 64 + 16 * u + li] = f2bf(fmaxf(c[t][r] + bias, 0.0f));
+            *reinterpret_cast<uint2 *>(act + (16 * t + li) * 64 + 16 * u + 4 * lk) =
+                make_uint2(pack_bf16(fmaxf(c[t][0] + bias.x, 0.0f), fmaxf(c[t][1] + bias.y, 0.0f)),
+                           pack_bf16(fmaxf(c[t][2] + bias.z, 0.0f), fmaxf(c[t][3] + bias.w, 0.0f)));
     }
     __syncthreads();
-    // layer 3: 64 -> 8 (padded to 16 columns); logits as FP32 over the first 4 KB of act
+    // layer 3: 64 -> 8 (padded to 16 outputs); logits as FP32 over the first 4 KB of act
+#pragma unroll
     for (int t = 0; t < 4; ++t)
+#pragma unroll
         for (int kc = 0; kc < 4; ++kc)
-            for (int r = 0; r < 4; ++r) a[t][kc][r] = act[(16 * t + li) * 64 + 16 * kc + 4 * lk + r];
+            a[t][kc] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 16 * kc + 4 * lk);
     float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-        const short4v b = W.w3[kc][lane];
-        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t][kc], b, c[t], 0, 0, 0);
+        const short4v w = W.w3[kc][lane];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a[t][kc], c[t], 0, 0, 0);
     }
     __syncthreads();  // every lane has read its layer-3 inputs before the logits overwrite them
     float *fout = reinterpret_cast<float *>(act);
-    const float bias = W.b3[li];
-    for (int t = 0; t < 4; ++t)
-        for (int r = 0; r < 4; ++r) fout[(16 * t + 4 * lk + r) * 16 + li] = c[t][r] + bias;
+    if (lk < 2) {  // classes 4 lk .. 4 lk + 3 of pair 16 t + li
+        const float4 bias = *reinterpret_cast<const float4 *>(W.b3 + 4 * lk);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            *reinterpret_cast<float4 *>(fout + (16 * t + li) * 8 + 4 * lk) =
+                make_float4(c[t][0] + bias.x, c[t][1] + bias.y, c[t][2] + bias.z, c[t][3] + bias.w);
+    }
     __syncthreads();
-    for (int k = 0; k < kCls; ++k) out[k] = fout[lane * 16 + k];
+#pragma unroll
+    for (int k = 0; k < kCls; ++k) out[k] = fout[lane * 8 + k];
     __syncthreads();
 }
 
