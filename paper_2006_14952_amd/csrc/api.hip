@@ -14,6 +14,7 @@ void clear_error();
 int pm_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const double *mass, double *acc,
               hipStream_t st);
 int add_into(double *acc, const double *other, int64_t n3, hipStream_t st);
+int pm_forces_tree(const fmm_params *P, int mesh, fmm_tree *t, double *acc, hipStream_t st);
 const MacModel *current_model(MacModel *host_copy);
 int run_labels(fmm_tree *t, const fmm_params *P, const double *aref_sorted, double eps, int stride, float *feats,
                int *labels, float *errs, uint64_t *pairs, int cap, int *dcounter, hipStream_t st);
@@ -420,7 +421,7 @@ int fmm_hybrid_forces_tree(fmm_tree **tree, const fmm_params *P, int mesh, int64
     if (int rc = fmm_build_tree(P, n, pos, mass, stream, tree)) return rc;
     fmm_tree *t = *tree;
     mark(t, 7, st);
-    if (int rc = pm_forces(P, mesh, n, pos, mass, acc, st)) return rc;
+    if (int rc = pm_forces_tree(P, mesh, t, acc, st)) return rc;  // deposits in Morton order
     mark(t, 8, st);
     if (int rc = run_forces(t, P, acc, st, 1)) return rc;
     if (t->timing) {

@@ -62,8 +62,25 @@ __device__ __forceinline__ void cic_weights(double x, double inv_d, int M, int &
     i0 = ((i % M) + M) % M;
 }
 
-__global__ void k_cic_deposit(const double *__restrict__ pos, const double *__restrict__ mass, int n, double box,
-                              int M, double inv_vol, double *__restrict__ rho)
+// Particle sources of the PM step: the caller's (n,3) positions and masses, or the
+// octree's Morton-ordered SoA copies (wrapped), whose output rows are perm[p].  In Morton
+// order neighbouring threads deposit into neighbouring mesh cells.
+struct CallerOrder {
+    const double *pos, *mass;
+    __device__ double x(int p, int a) const { return pos[3 * (size_t)p + a]; }
+    __device__ double m(int p) const { return mass[p]; }
+    __device__ size_t row(int p) const { return 3 * (size_t)p; }
+};
+struct MortonOrder {
+    const double *xs, *ys, *zs, *ms;
+    const int *perm;
+    __device__ double x(int p, int a) const { return a == 0 ? xs[p] : (a == 1 ? ys[p] : zs[p]); }
+    __device__ double m(int p) const { return ms[p]; }
+    __device__ size_t row(int p) const { return 3 * (size_t)perm[p]; }
+};
+
+template <class S>
+__global__ void k_cic_deposit(S src, int n, double box, int M, double inv_vol, double *__restrict__ rho)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -71,11 +88,11 @@ __global__ void k_cic_deposit(const double *__restrict__ pos, const double *__re
     int i[3];
     double w[3];
     for (int a = 0; a < 3; ++a) {
-        double x = pos[3 * (size_t)p + a];
+        double x = src.x(p, a);
         x -= box * floor(x / box);
         cic_weights(x, inv_d, M, i[a], w[a]);
     }
-    double m = mass[p] * inv_vol;
+    double m = src.m(p) * inv_vol;
     for (int c = 0; c < 8; ++c) {
         int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
         double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
@@ -115,8 +132,8 @@ __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipff
     out[t] = o;
 }
 
-__global__ void k_cic_interp(const double *__restrict__ pos, int n, double box, int M, const double *__restrict__ am,
-                             double *__restrict__ acc)
+template <class S>
+__global__ void k_cic_interp(S src, int n, double box, int M, const double *__restrict__ am, double *__restrict__ acc)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -124,7 +141,7 @@ __global__ void k_cic_interp(const double *__restrict__ pos, int n, double box, 
     int i[3];
     double w[3];
     for (int a = 0; a < 3; ++a) {
-        double x = pos[3 * (size_t)p + a];
+        double x = src.x(p, a);
         x -= box * floor(x / box);
         cic_weights(x, inv_d, M, i[a], w[a]);
     }
@@ -136,7 +153,8 @@ __global__ void k_cic_interp(const double *__restrict__ pos, int n, double box, 
         size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
         for (int a = 0; a < 3; ++a) g[a] += wt * am[a * nr + idx];
     }
-    for (int a = 0; a < 3; ++a) acc[3 * (size_t)p + a] = g[a];
+    const size_t o = src.row(p);
+    for (int a = 0; a < 3; ++a) acc[o + a] = g[a];
 }
 
 __global__ void k_add3(double *__restrict__ acc, const double *__restrict__ other, size_t n3)
@@ -151,27 +169,25 @@ __global__ void k_check_finite(const double *__restrict__ pos, size_t n3, int *b
     if (i < n3 && !isfinite(pos[i])) *bad = 1;
 }
 
-int pm_forces(const fmm_params *P, int mesh, int64_t n64, const double *pos, const double *mass, double *acc,
-              hipStream_t st)
+template <class S>
+static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos_check, double *acc, hipStream_t st)
 {
-    if (mesh < 8 || mesh > 1024) return set_error(FMM_ERR_ARG, "mesh must be in [8, 1024]");
-    if (n64 < 0 || n64 > ((int64_t)1 << 30)) return set_error(FMM_ERR_ARG, "n out of range");
-    int n = (int)n64;
-    if (n == 0) return 0;
     PMPlan *pl;
     if (int rc = pm_plan(mesh, &pl)) return rc;
     std::lock_guard<std::mutex> lk(g_pm_mu);  // plans and mesh buffers are shared per mesh size
     size_t nr = (size_t)mesh * mesh * mesh, nc = (size_t)mesh * mesh * (mesh / 2 + 1);
-    int *bad = ptr<int>(pl->amesh);  // scratch flag in the (not yet used) output mesh
-    hipMemsetAsync(bad, 0, sizeof(int), st);
-    k_check_finite<<<(unsigned)((3 * (size_t)n + 255) / 256), 256, 0, st>>>(pos, 3 * (size_t)n, bad);
-    int hbad = 0;
-    hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (hipStreamSynchronize(st) != hipSuccess) return set_error(FMM_ERR_HIP, "pm sync");
-    if (hbad) return set_error(FMM_ERR_NAN, "non-finite particle position");
+    if (pos_check) {
+        int *bad = ptr<int>(pl->amesh);  // scratch flag in the (not yet used) output mesh
+        hipMemsetAsync(bad, 0, sizeof(int), st);
+        k_check_finite<<<(unsigned)((3 * (size_t)n + 255) / 256), 256, 0, st>>>(pos_check, 3 * (size_t)n, bad);
+        int hbad = 0;
+        hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (hipStreamSynchronize(st) != hipSuccess) return set_error(FMM_ERR_HIP, "pm sync");
+        if (hbad) return set_error(FMM_ERR_NAN, "non-finite particle position");
+    }
     hipMemsetAsync(pl->rho.p, 0, nr * 8, st);
     double d = P->box / mesh;
-    k_cic_deposit<<<(n + 255) / 256, 256, 0, st>>>(pos, mass, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    k_cic_deposit<S><<<(n + 255) / 256, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
     hipfftSetStream(pl->r2c, st);
     hipfftSetStream(pl->c2r, st);
     if (hipfftExecD2Z(pl->r2c, ptr<double>(pl->rho), ptr<hipfftDoubleComplex>(pl->rhok)) != HIPFFT_SUCCESS)
@@ -184,10 +200,31 @@ int pm_forces(const fmm_params *P, int mesh, int64_t n64, const double *pos, con
             HIPFFT_SUCCESS)
             return set_error(FMM_ERR_HIP, "hipfftExecZ2D");
     }
-    k_cic_interp<<<(n + 255) / 256, 256, 0, st>>>(pos, n, P->box, mesh, ptr<double>(pl->amesh), acc);
+    k_cic_interp<S><<<(n + 255) / 256, 256, 0, st>>>(src, n, P->box, mesh, ptr<double>(pl->amesh), acc);
     int rc = hip_check(hipGetLastError(), "pm");
     if (rc == 0) rc = hip_check(hipStreamSynchronize(st), "pm");  // mesh buffers are reused by the next call
     return rc;
+}
+
+int pm_forces(const fmm_params *P, int mesh, int64_t n64, const double *pos, const double *mass, double *acc,
+              hipStream_t st)
+{
+    if (mesh < 8 || mesh > 1024) return set_error(FMM_ERR_ARG, "mesh must be in [8, 1024]");
+    if (n64 < 0 || n64 > ((int64_t)1 << 30)) return set_error(FMM_ERR_ARG, "n out of range");
+    const int n = (int)n64;
+    if (n == 0) return 0;
+    return pm_run(P, mesh, n, CallerOrder{pos, mass}, pos, acc, st);
+}
+
+// PM on the particles of a built tree (Morton order, already wrapped and checked).
+int pm_forces_tree(const fmm_params *P, int mesh, fmm_tree *t, double *acc, hipStream_t st)
+{
+    if (mesh < 8 || mesh > 1024) return set_error(FMM_ERR_ARG, "mesh must be in [8, 1024]");
+    if (t->n == 0) return 0;
+    return pm_run(P, mesh, (int)t->n,
+                  MortonOrder{ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms),
+                              ptr<int>(t->perm)},
+                  nullptr, acc, st);
 }
 
 int add_into(double *acc, const double *other, int64_t n3, hipStream_t st)
