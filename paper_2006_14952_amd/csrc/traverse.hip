@@ -221,9 +221,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         ListState Ls[kKinds];
 #pragma unroll
         for (int k = 0; k < kKinds; ++k) Ls[k] = ListState{-1, -1, 0, 0};
-        int sp = 0, ip = 0;
+        int sp = 0;
         int qhead = 0, qtail = 0;  // learned: queue of candidate pairs awaiting the selector
         bool failed = false;
+        // the inherited pairs go onto the stack first, so every step takes a full batch of
+        // 64 while that many are pending (opened sources push their children on top)
+        if (ninh > scap) {
+            if (lane == 0) atomicOr(a.err, 1);
+            continue;
+        }
+        if (root) {
+            if (lane < ninh) stk[lane] = (uint32_t)A << 5 | (uint32_t)lane;
+        } else {
+            for (int e0 = 0; e0 < ninh; e0 += kChunk) {
+                if (e0 > 0) ichunk = a.next[2][ichunk];
+                if (e0 + lane < ninh) stk[e0 + lane] = a.items[2][(size_t)ichunk * kChunk + lane];
+            }
+        }
+        sp = ninh;
+        __syncthreads();  // the copied entries are written before they are popped
 
         // Lists and stack for decided pairs of the lanes with `valid`: `m2l_ord` >= 2 puts
         // the pair on an M2L list (order m2l_ord in learned mode, else plain), `opened`
@@ -269,8 +285,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 
         for (;;) {
             // next batch: a flush of the candidate queue (learned: when 64 wait, or when
-            // nothing else is left), else up to 64 pairs from the stack, else from the
-            // list inherited from the parent
+            // nothing else is left), else up to 64 pairs from the stack
             int kk = 0, fk = 0;
             uint32_t it = 0;
             if (MODE == kModeLearned && qtail - qhead >= 64) {
@@ -279,12 +294,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 kk = sp < 64 ? sp : 64;
                 sp -= kk;
                 if (lane < kk) it = stk[sp + lane];
-            } else if (ip < ninh) {
-                kk = ninh - ip < 64 ? ninh - ip : 64;
-                if (lane < kk)
-                    it = root ? ((uint32_t)A << 5 | (uint32_t)(ip + lane)) : a.items[2][(size_t)ichunk * kChunk + lane];
-                ip += kk;
-                if (!root && ip < ninh) ichunk = a.next[2][ichunk];
             } else if (MODE == kModeLearned && qtail > qhead) {
                 fk = qtail - qhead;
             } else {
