@@ -158,11 +158,31 @@ def train(feats, labels, epochs=40, batch=8192, lr=2e-3, wd=1e-5, seed=0, val_fr
                 step=step, class_w=cw_np, history=hist, val_logits=Z, val_labels=yv)
 
 
-def choose_safety(val_logits, val_labels, max_unsafe=0.005):
-    for s in range(0, 7):
-        if unsafe_fraction(decode(val_logits, s), val_labels) <= max_unsafe:
-            return s
-    return 6
+def select_safety(pos, mass, prm: Params, params, mu, isd, theta_max, target=5e-4, max_safety=6):
+    """Smallest safety margin whose forces on a held-out box stay within `target` of the
+    library's own FP64 reference (order 8, theta 0.3) at the 99th percentile, with the
+    per-margin p99 values.  `prm` carries the box's split parameters and FP32/FP64 form."""
+    import torch
+    tree = Tree().build(pos, mass, prm)
+    ref = reference_forces(tree, prm)
+    rn = ref.norm(dim=1)
+    floor = rn[rn > 0].median()
+    run = Params.from_buffer_copy(prm)
+    run.learned = 1
+    p99 = {}
+    chosen = max_safety
+    try:
+        for sf in range(max_safety + 1):
+            set_model(params, mu, isd, theta_max, sf)
+            got = tree.short_range(run)
+            e = (got - ref).norm(dim=1) / torch.where(rn > 0, rn, floor)
+            p99[sf] = float(torch.quantile(e, 0.99).item())
+            if p99[sf] <= target:
+                chosen = sf
+                break
+    finally:
+        tree.free()
+    return chosen, p99
 
 
 def save_model(path, model, theta_max, eps, safety, config):
