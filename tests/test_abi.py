@@ -35,3 +35,27 @@ def test_bad_params_rejected_without_gpu(bad):
     rc = hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h))
     assert rc == hf.FMM_ERR_ARG
     assert hf.lib().fmm_last_error()
+
+
+def test_autotune_and_hybrid_tree_reject_bad_arguments_without_gpu():
+    L = hf.lib()
+    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
+    best = C.c_int()
+    cand = (C.c_int * 2)(16, 32)
+    # no particles / no pointers / no candidates
+    assert L.fmm_autotune(C.byref(prm), 1, None, 0, None, None, None, cand, 2, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    fake = C.c_void_p(16)  # never dereferenced: the arguments are refused first
+    assert L.fmm_autotune(C.byref(prm), 1, None, 10, fake, fake, fake, cand, 0, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    bad = (C.c_int * 2)(16, 0)
+    assert L.fmm_autotune(C.byref(prm), 1, None, 10, fake, fake, fake, bad, 2, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    off = (C.c_int64 * 3)(0, 4, 9)  # offsets[nbox] != n
+    assert L.fmm_autotune(C.byref(prm), 2, off, 10, fake, fake, fake, cand, 2, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    assert L.fmm_hybrid_forces_tree(None, C.byref(prm), 32, 10, fake, fake, fake, None) == hf.FMM_ERR_ARG
+    h = C.c_void_p()
+    assert L.fmm_hybrid_forces_tree(C.byref(h), C.byref(prm), 32, 10, None, None, None, None) == hf.FMM_ERR_ARG
+    prm.theta = 0.0
+    assert L.fmm_hybrid_forces_tree(C.byref(h), C.byref(prm), 32, 10, fake, fake, fake, None) == hf.FMM_ERR_ARG
