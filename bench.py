@@ -32,7 +32,7 @@ P2P_FLOP_PER_PAIR = 38.0
 # clustered mix).  Full (134M, lattice + clumps): the whole hybrid step, PM on a 512^3
 # mesh plus the short range, FP32 with the learned selector.
 WORKLOADS = {
-    "clustered": dict(theta=0.4, precision=1, n_crit=32, learned=False),
+    "clustered": dict(theta=0.42, precision=1, n_crit=32, learned=False),
     "uniform": dict(theta=0.5, precision=0, n_crit=32, learned=False),
     "batched": dict(theta=0.4, precision=1, n_crit=32, learned=False, autotune=True),
     "large": dict(theta=0.5, precision=1, n_crit=32, learned=False),
@@ -152,8 +152,12 @@ def main():
     achieved = flop_launch / p2p_s
     traffic = None
     tf = os.path.join(ROOT, "profiles", "p2p_traffic_%s_fp%d.json" % (args.workload, 32 if wl["precision"] else 64))
-    if os.path.exists(tf):
-        traffic = json.load(open(tf)).get("bytes_per_launch")
+    if os.path.exists(tf):  # counters taken on this workload with the same parameters, else not reported
+        rec = json.load(open(tf))
+        same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
+                                                 ("n_crit", wl["n_crit"]), ("learned", bool(wl["learned"]))))
+        if same:
+            traffic = rec.get("bytes_per_launch")
 
     out = {
         "metric": METRIC,

@@ -84,20 +84,24 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     // Dependencies: upward -> M2L; traversal -> {M2L, P2P}; M2L -> L2L; {L2L, P2P} -> L2P.
     // The plain traversal does not read multipoles, so the upward pass runs beside it on
     // the second stream; P2P runs there beside M2L and L2L.
+    // The FP32 P2P's leaf boxes depend on the tree only: they are computed on the second
+    // stream ahead of P2P.
     hipEventRecord(t->dep[0], st);
     mark(t, 0, st);
+    hipStreamWaitEvent(ax, t->dep[0], 0);
     if (P->learned) {  // the selector's features read the multipoles
         mark(t, 9, st);
         if ((rc = upward(t, &P8, st))) return rc;
         mark(t, 1, st);
         hipEventRecord(t->dep[1], st);
+        if ((rc = p2p_bbox(t, P, ax))) return rc;
         rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st);
     } else {
-        hipStreamWaitEvent(ax, t->dep[0], 0);
         mark(t, 9, ax);
         if ((rc = upward(t, &P8, ax))) return rc;
         mark(t, 1, ax);
         hipEventRecord(t->dep[1], ax);
+        if ((rc = p2p_bbox(t, P, ax))) return rc;
         rc = traverse(t, P, st);
     }
     if (rc) return rc;
@@ -457,7 +461,7 @@ void fmm_free_tree(fmm_tree *t)
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
-                      &t->m2l_off, &t->m2l_pairs, &t->bbox, &t->wstate};
+                      &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate};
     for (DevBuf *b : bufs) free_buf(*b);
     for (int k = 0; k < 11; ++k) {
         free_buf(t->litems[k]);

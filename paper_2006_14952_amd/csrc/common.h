@@ -55,8 +55,7 @@ constexpr int kChunk = 64;
 // t = 2 r^2 / r_cut^2 - 1, S a degree-10 polynomial fitted on the host.
 constexpr int kP2PPoly = 11;
 struct P2PConst {
-    float c[kP2PPoly];
-    float inv8rs3;
+    float c[kP2PPoly];  // S(t) / (8 r_s^3), coefficients of t^0 .. t^(kP2PPoly-1)
     float two_over_rc2;
     float rc2;
     double rs, rc2d;
@@ -79,5 +78,6 @@ int hip_check(hipError_t e, const char *what);
 
 // scans (int32), result is exclusive; total (device int) optional
 int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp);
+int zero_async(void *p, size_t bytes, hipStream_t st);  // p 16-byte aligned, bytes a multiple of 4
 
 }  // namespace hfmm

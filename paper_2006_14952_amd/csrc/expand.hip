@@ -22,7 +22,7 @@ int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st)
 // kind 4 + o - 2) are contracted at that order and added up.
 int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
-    hipMemsetAsync(t->Lc.p, 0, (size_t)t->ncell * ncoef(8) * (P->precision ? 4 : 8), st);
+    if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(8) * (P->precision ? 4 : 8), st)) return rc;
     for (int o = 2; o <= 8; ++o) {
         int rc = P->precision ? m2l_t<float>(t, o, P->r_s, 4 + o - 2, 8, 1, st)
                               : m2l_t<double>(t, o, P->r_s, 4 + o - 2, 8, 1, st);
@@ -31,20 +31,43 @@ int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return 0;
 }
 
-// Flattens the chunked M2L list of `kind` into (sink, item) pairs ordered by sink.
+// Flattens the chunked M2L list of `kind` into (sink, item) pairs, each sink's pairs
+// contiguous (the pair kernel reduces runs of one sink; the order of the sinks is free).
+// A wave takes 64 sinks: a wave scan of their list sizes, one atomic reservation of the
+// total in the output, then each sink's chunks are copied 64 items at a time.  `npair`
+// (the list total counted by the traversal) bounds every write.
 __global__ __launch_bounds__(64) void k_flatten_pairs(const int *__restrict__ head, const int *__restrict__ cnt,
                                                       const uint32_t *__restrict__ items, const int *__restrict__ next,
-                                                      const int *__restrict__ off, int ncell, int2 *__restrict__ out)
+                                                      int ncell, int *__restrict__ ctr, int2 *__restrict__ out,
+                                                      int npair)
 {
     const int lane = threadIdx.x;
-    for (int A = blockIdx.x; A < ncell; A += gridDim.x) {
-        const int nl = cnt[A];
-        if (nl == 0) continue;
-        int chunk = head[A];
-        const int o = off[A];
-        for (int e0 = 0; e0 < nl; e0 += kChunk) {
-            if (e0 > 0) chunk = next[chunk];
-            if (e0 + lane < nl) out[o + e0 + lane] = make_int2(A, (int)items[(size_t)chunk * kChunk + lane]);
+    for (int A0 = blockIdx.x * 64; A0 < ncell; A0 += gridDim.x * 64) {
+        const int A = A0 + lane;
+        const int nl = A < ncell ? cnt[A] : 0;
+        const int hd = nl > 0 ? head[A] : 0;
+        int incl = nl;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        const int total = __shfl(incl, 63, 64);
+        if (total == 0) continue;
+        int base = 0;
+        if (lane == 63) base = atomicAdd(ctr, total);
+        base = __shfl(base, 63, 64);
+        const int excl = incl - nl;
+        for (int j = 0; j < 64; ++j) {
+            const int nj = __shfl(nl, j, 64);
+            if (nj == 0) continue;
+            const int oj = base + __shfl(excl, j, 64);
+            int chunk = __shfl(hd, j, 64);
+            for (int e0 = 0; e0 < nj; e0 += kChunk) {
+                if (e0 > 0) chunk = next[chunk];
+                const int e = e0 + lane, o = oj + e;
+                if (e < nj && o < npair) out[o] = make_int2(A0 + j, (int)items[(size_t)chunk * kChunk + lane]);
+            }
         }
     }
 }
@@ -54,12 +77,13 @@ int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st)
     const int ncell = t->ncell;
     if (npair > 0x7fffffff) return set_error(FMM_ERR_ARG, "too many M2L pairs for one list (%lld)", (long long)npair);
     const size_t off = (size_t)kind * ncell;
-    if (int rc = grow(t->m2l_off, (size_t)ncell * 4) | grow(t->m2l_pairs, (size_t)npair * 8)) return rc;
-    if (int rc = scan_exclusive(ptr<int>(t->lcnt) + off, ptr<int>(t->m2l_off), ncell, nullptr, st, t->scan_tmp))
-        return rc;
-    const int g = ncell < 65536 ? ncell : 65536;
+    if (int rc = grow(t->m2l_ctr, 256) | grow(t->m2l_pairs, (size_t)npair * 8)) return rc;
+    if (int rc = zero_async(t->m2l_ctr.p, 4, st)) return rc;
+    const int nw = (ncell + 63) / 64;
+    const int g = nw < 16384 ? nw : 16384;
     k_flatten_pairs<<<g, 64, 0, st>>>(ptr<int>(t->lhead) + off, ptr<int>(t->lcnt) + off, ptr<uint32_t>(t->litems[kind]),
-                                      ptr<int>(t->lnext[kind]), ptr<int>(t->m2l_off), ncell, ptr<int2>(t->m2l_pairs));
+                                      ptr<int>(t->lnext[kind]), ncell, ptr<int>(t->m2l_ctr), ptr<int2>(t->m2l_pairs),
+                                      (int)npair);
     return hip_check(hipGetLastError(), "flatten pairs");
 }
 

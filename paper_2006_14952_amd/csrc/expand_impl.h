@@ -707,7 +707,8 @@ template <int P, class T> struct M2L {
     {
         if constexpr (pair_m2l<P, T>()) {
             const int64_t np = kind == 0 ? t->n_m2l : t->stats.n_m2l_by_order[kind - 4];
-            if (!accumulate) hipMemsetAsync(t->Lc.p, 0, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st);
+            if (!accumulate)
+                if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st)) return rc;
             if (np == 0) return hip_check(hipGetLastError(), "m2l");
             if (int rc = flatten_pairs(t, kind, np, st)) return rc;
             k_m2l_pairs<P, T><<<(unsigned)((np + 63) / 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int2>(t->m2l_pairs),

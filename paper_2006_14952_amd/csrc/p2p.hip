@@ -13,11 +13,11 @@
 // centre offset c_B + s box - c_A added when staging, and
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
-// degree-10 polynomial fitted on the host; the sum of each staged block is added to a
-// Kahan-compensated per-particle accumulator.  A listed source leaf whose particles'
-// bounding box lies farther than r_cut from the sink leaf's box, and any single source
-// particle farther than r_cut from that box, hold no pair inside the cutoff and are not
-// staged (the lists themselves are unchanged).
+// degree-10 polynomial fitted on the host (its coefficients carry the factor 1/(8 r_s^3));
+// the sum of each staged block is added to a Kahan-compensated per-particle accumulator.
+// A listed source leaf whose particles' bounding box lies farther than r_cut from the sink
+// leaf's box, and any single source particle farther than r_cut from that box, hold no
+// pair inside the cutoff and are not staged (the lists themselves are unchanged).
 #include <math.h>
 
 #include <type_traits>
@@ -273,24 +273,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                         }
                     } else {
                         float px = 0, py = 0, pz = 0;
-                        for (int q = g; q < nst; q += G) {
-                            const float4 s = src[q];
-                            float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-                            float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        // the leading coefficient as a vector operand: each Horner step then
+                        // reads a single scalar
+                        float clead = k.c[kP2PPoly - 1];
+                        asm volatile("" : "+v"(clead));
+                        auto pair = [&](const float4 s) __attribute__((always_inline)) {
+                            const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                             // a particle meets itself (and exact duplicates) at d = 0: the clamp
                             // keeps w finite, so w d = 0 without a separate r > 0 test
-                            float rinv = __frsqrt_rn(fmaxf(r2, 1e-20f));
-                            float t = fmaf(r2, k.two_over_rc2, -1.0f);
-                            float S = k.c[kP2PPoly - 1];
+                            const float rinv = __frsqrt_rn(fmaxf(r2, 1e-20f));
+                            const float t = fmaf(r2, k.two_over_rc2, -1.0f);
+                            float S = clead;  // S(t) / (8 r_s^3)
 #pragma unroll
                             for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
-                            float rinv2 = rinv * rinv;
-                            float f1 = fmaf(S, k.inv8rs3, -rinv2 * rinv);
-                            float w = r2 < k.rc2 ? s.w * f1 : 0.0f;
+                            const float f1 = fmaf(-rinv * rinv, rinv, S);
+                            const float w = r2 < k.rc2 ? s.w * f1 : 0.0f;
                             px = fmaf(w, dx, px);
                             py = fmaf(w, dy, py);
                             pz = fmaf(w, dz, pz);
+                        };
+                        // two sources per step, both reads in flight
+                        const float4 *sp = reinterpret_cast<const float4 *>(src) + g;
+                        const float4 *const send = reinterpret_cast<const float4 *>(src) + nst;
+                        for (; sp + G < send; sp += 2 * G) {
+                            const float4 s0 = sp[0], s1 = sp[G];
+                            pair(s0);
+                            pair(s1);
                         }
+                        if (sp < send) pair(sp[0]);
                         kahan_add(sx, cx, px);
                         kahan_add(sy, cy, py);
                         kahan_add(sz, cz, pz);
@@ -371,12 +382,23 @@ void p2p_setup(const fmm_params *P, P2PConst &k)
             for (int j = c; j <= m; ++j) Amat[r][j] -= f * Amat[c][j];
         }
     }
-    for (int j = 0; j < m; ++j) k.c[j] = (float)(Amat[j][m] / Amat[j][j]);
-    k.inv8rs3 = (float)(1.0 / (8.0 * P->r_s * P->r_s * P->r_s));
+    // the kernel evaluates S(t) / (8 r_s^3): the factor is folded into the coefficients
+    const double inv8rs3 = 1.0 / (8.0 * P->r_s * P->r_s * P->r_s);
+    for (int j = 0; j < m; ++j) k.c[j] = (float)(Amat[j][m] / Amat[j][j] * inv8rs3);
     k.two_over_rc2 = (float)(2.0 / (P->r_cut * P->r_cut));
     k.rc2 = (float)(P->r_cut * P->r_cut);
     k.rs = P->r_s;
     k.rc2d = P->r_cut * P->r_cut;
+}
+
+// The FP32 form's leaf bounding boxes (they depend on the tree only).
+int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st)
+{
+    if (t->nleaf == 0 || !P->precision) return 0;
+    if (int rc = grow(t->bbox, (size_t)t->ncell * 32)) return rc;
+    k_leaf_bbox<<<(t->nleaf + 63) / 64, 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaves), t->nleaf,
+                                                    ptr<float4>(t->rel32), ptr<float4>(t->bbox));
+    return hip_check(hipGetLastError(), "leaf boxes");
 }
 
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
@@ -404,9 +426,8 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
     a.evaluated = ptr<unsigned long long>(t->counters) + 24;
     a.bbox = nullptr;
     if (P->precision) {
-        if (int rc = grow(t->bbox, (size_t)t->ncell * 32)) return rc;
+        if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
         a.bbox = ptr<float4>(t->bbox);
-        k_leaf_bbox<<<(t->nleaf + 255) / 256, 256, 0, st>>>(a.cells, a.leaves, t->nleaf, a.rel, ptr<float4>(t->bbox));
     }
     if (P->precision) k_p2p<false><<<t->nleaf, 64, 0, st>>>(a, k);
     else k_p2p<true><<<t->nleaf, 64, 0, st>>>(a, k);

@@ -47,7 +47,7 @@ struct fmm_tree {
 
     // scratch
     hfmm::DevBuf scan_tmp, nch, flag;
-    hfmm::DevBuf m2l_off, m2l_pairs;  // flattened M2L pairs (sink, item) for the high-order kernel
+    hfmm::DevBuf m2l_ctr, m2l_pairs;  // flattened M2L pairs (sink, item) for the pair kernel; its fill counter
     hfmm::DevBuf wstate;              // per traversal wave: chunk block in use of each list kind
     hfmm::DevBuf bbox;                // per cell: float4 lo, hi of its particles relative to the centre (leaves)
     int *host = nullptr;  // pinned readback area (kHostInts ints)
@@ -76,6 +76,7 @@ int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
+int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st);  // before p2p (FP32 form): leaf boxes
 int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, int accumulate, hipStream_t st);
 uint64_t cell_key_host(int level, int ix, int iy, int iz);
 }  // namespace hfmm

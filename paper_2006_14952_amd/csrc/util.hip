@@ -59,6 +59,31 @@ int grow_keep(DevBuf &b, size_t bytes, size_t used)
 }
 
 // ---------------------------------------------------------------------------
+// Zero fill by one-wave workgroups: these find room on a GPU filled by another stream's
+// kernel, where the runtime's fill kernel (larger workgroups) waits for whole free CUs.
+
+__global__ __launch_bounds__(64) void k_zero(uint4 *__restrict__ p, size_t n16, uint32_t *__restrict__ tail, int ntail)
+{
+    const size_t stride = (size_t)gridDim.x * 64;
+    for (size_t i = (size_t)blockIdx.x * 64 + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+int zero_async(void *p, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return 0;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) || (bytes & 3))
+        return set_error(FMM_ERR_ARG, "zero fill: unaligned buffer or size");
+    const size_t n16 = bytes / 16;
+    const int ntail = (int)((bytes - n16 * 16) / 4);
+    const size_t nb = (n16 + 63) / 64;
+    const unsigned grid = (unsigned)(nb == 0 ? 1 : nb < 8192 ? nb : 8192);
+    k_zero<<<grid, 64, 0, st>>>(static_cast<uint4 *>(p), n16, reinterpret_cast<uint32_t *>(static_cast<char *>(p) + n16 * 16),
+                               ntail);
+    return hip_check(hipGetLastError(), "zero fill");
+}
+
+// ---------------------------------------------------------------------------
 // Exclusive scan of int32: block-local scans of 2048 elements, a recursive scan of
 // the block totals, then a uniform add.  Totals fit in int32 by construction of the
 // callers (list sizes are checked against 2^31 before use).
