@@ -317,16 +317,8 @@ int fmm_copy_interactions(const fmm_tree *tc, int kind, uint64_t *out, int64_t c
         *count = total;
         return 0;
     }
-    if (kind == 0 && t->trav_mode == 2) {  // learned selector: M2L pairs of every order
-        int64_t w = 0;
-        for (int k = 4; k < 11 && w < cap; ++k) {
-            int64_t c = 0;
-            if (int rc = copy_kind(t, k, out + 3 * w, cap - w, &c)) return rc;
-            w += c;
-        }
-        *count = w;
-        return 0;
-    }
+    if (kind == 0 && t->trav_mode == 2)  // learned selector: M2L pairs of every order
+        return copy_kind(t, kKindOrd, out, cap, count);
     return copy_kind(t, kind, out, cap, count);
 }
 
@@ -463,7 +455,8 @@ void fmm_free_tree(fmm_tree *t)
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
                       &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate};
     for (DevBuf *b : bufs) free_buf(*b);
-    for (int k = 0; k < 11; ++k) {
+    free_buf(t->lord);
+    for (int k = 0; k < kKinds; ++k) {
         free_buf(t->litems[k]);
         free_buf(t->lnext[k]);
     }

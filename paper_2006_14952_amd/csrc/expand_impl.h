@@ -254,10 +254,11 @@ template <int P, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 : 2))) void k_m2l(
     const Cell *__restrict__ cells, int ncell, const int *__restrict__ head, const int *__restrict__ cnt,
     const uint32_t *__restrict__ items, const int *__restrict__ next, const T *__restrict__ M, T *__restrict__ L,
-    double box, double rs, int stride, int accumulate)
+    double box, double rs, int stride, int accumulate, const unsigned char *__restrict__ ord)
 {
     // M and L hold ncoef(order of storage) coefficients per cell (stride); this kernel
     // reads and writes the first ncoef(P) of them (multi-indices are ordered by degree).
+    // ord != nullptr: a list of mixed orders, of which the entries of order P are taken.
     constexpr int NC = Tab<P>::NC;
     constexpr Tab<P> tb{};
     constexpr PairTab<P> pt{};
@@ -271,10 +272,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 :
         Cell ca = cells[A];
         int la = cell_level(ca);
         T rsh = (T)(rs / cell_h(ca, box));
-        int chunk = head[A];
+        int chunk = head[A], taken = 0;
         for (int e = 0; e < nl; ++e) {
             if (e > 0 && (e & (kChunk - 1)) == 0) chunk = next[chunk];
-            uint32_t it = items[(size_t)chunk * kChunk + (e & (kChunk - 1))];
+            const size_t at = (size_t)chunk * kChunk + (e & (kChunk - 1));
+            if (ord && ord[at] != P) continue;
+            ++taken;
+            uint32_t it = items[at];
             int B = (int)(it >> 5), s = (int)(it & 31);
             Cell cb = cells[B];
             int lb = cell_level(cb);
@@ -291,6 +295,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 :
             const T *Mb = M + (size_t)B * stride;
             m2l_contract<P, T, 0, 16>(Mb, rp, D, acc);
         }
+        if (taken == 0) nl = 0;
     }
     if (accumulate && nl == 0) return;
     T *out = L + (size_t)A * stride;
@@ -702,25 +707,29 @@ template <int P, class T> struct Upward {
 };
 
 template <int P, class T> struct M2L {
-    // list kind `kind` of the traversal; coefficient storage of order `pstore`
-    static int run(fmm_tree *t, double rs, int kind, int pstore, int accumulate, hipStream_t st)
+    // Coefficient storage of order `pstore`.  learned == 0: the plain M2L list (kind 0);
+    // learned != 0: the entries of order P of the learned selector's list, whose pairs
+    // flatten_learned has already laid out by order (the pair kernel adds to L).
+    static int run(fmm_tree *t, double rs, int learned, int pstore, int accumulate, hipStream_t st)
     {
+        const int kind = learned ? kKindOrd : 0;
         if constexpr (pair_m2l<P, T>()) {
-            const int64_t np = kind == 0 ? t->n_m2l : t->stats.n_m2l_by_order[kind - 4];
+            const int64_t np = learned ? t->stats.n_m2l_by_order[P - 2] : t->n_m2l;
             if (!accumulate)
                 if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st)) return rc;
             if (np == 0) return hip_check(hipGetLastError(), "m2l");
-            if (int rc = flatten_pairs(t, kind, np, st)) return rc;
-            k_m2l_pairs<P, T><<<(unsigned)((np + 63) / 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int2>(t->m2l_pairs),
-                                                                       np, ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs,
-                                                                       ncoef(pstore));
+            if (!learned)
+                if (int rc = flatten_pairs(t, kind, np, st)) return rc;
+            const int2 *pairs = ptr<int2>(t->m2l_pairs) + (learned ? t->lseg[P - 2] : 0);
+            k_m2l_pairs<P, T><<<(unsigned)((np + 63) / 64), 64, 0, st>>>(ptr<Cell>(t->cells), pairs, np, ptr<T>(t->Mc),
+                                                                       ptr<T>(t->Lc), t->box, rs, ncoef(pstore));
             return hip_check(hipGetLastError(), "m2l pairs");
         }
         size_t off = (size_t)kind * t->ncell;
-        k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead) + off,
-                                                       ptr<int>(t->lcnt) + off, ptr<uint32_t>(t->litems[kind]),
-                                                       ptr<int>(t->lnext[kind]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box,
-                                                       rs, ncoef(pstore), accumulate);
+        k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(
+            ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead) + off, ptr<int>(t->lcnt) + off,
+            ptr<uint32_t>(t->litems[kind]), ptr<int>(t->lnext[kind]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs,
+            ncoef(pstore), accumulate, learned ? ptr<unsigned char>(t->lord) : nullptr);
         return hip_check(hipGetLastError(), "m2l");
     }
 };
@@ -751,9 +760,9 @@ template <int P, class T> struct L2P {
 };
 
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
-template <class T> int m2l_t(fmm_tree *t, int p, double rs, int kind, int pstore, int accumulate, hipStream_t st)
+template <class T> int m2l_t(fmm_tree *t, int p, double rs, int learned, int pstore, int accumulate, hipStream_t st)
 {
-    return dispatch_p<M2L, T>(p, t, rs, kind, pstore, accumulate, st);
+    return dispatch_p<M2L, T>(p, t, rs, learned, pstore, accumulate, st);
 }
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
 template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st)

@@ -6,6 +6,12 @@
 
 namespace hfmm {
 constexpr int kHostInts = 1024;
+// Interaction list kinds: 0 M2L, 1 P2P, 2 handed to the children, 3 candidate pairs
+// (training export), 4 M2L pairs of the learned selector (all orders; the order of each
+// entry in a byte beside it).
+constexpr int kKinds = 5;
+constexpr int kKindCand = 3, kKindOrd = 4;
+constexpr int kOrders = 7;  // learned selector: M2L orders 2 .. 8
 }
 
 struct fmm_tree {
@@ -33,12 +39,14 @@ struct fmm_tree {
     hfmm::DevBuf leaves;          // int[nleaf]
     hfmm::DevBuf Mc, Lc;          // expansion coefficients, ncell x ncoef(p) (float or double)
 
-    // interaction lists: per cell and list kind (0 M2L, 1 P2P, 2 handed to the children,
-    // 3 candidate pairs, 4..10 M2L at order 2..8 of the learned selector)
-    // a chain of 64-entry chunks; head[k * ncell + c], cnt[k * ncell + c]
+    // interaction lists: per cell and list kind (hfmm::kKinds), a chain of 64-entry chunks;
+    // head[k * ncell + c], cnt[k * ncell + c].  lcnt continues with the learned selector's
+    // per-order counts, cnt[(kKinds + o - 2) * ncell + c] for order o.
     hfmm::DevBuf lhead, lcnt;
-    hfmm::DevBuf litems[11], lnext[11];
-    int lcap[11] = {0};                              // chunks (one more is allocated as overflow bin)
+    hfmm::DevBuf litems[hfmm::kKinds], lnext[hfmm::kKinds];
+    hfmm::DevBuf lord;                               // kind kKindOrd: the M2L order of each entry (byte)
+    int lcap[hfmm::kKinds] = {0};                    // chunks (one more is allocated as overflow bin)
+    int64_t lseg[hfmm::kOrders] = {0};               // learned: start of each order's pairs in m2l_pairs
     int trav_mode = 0;                               // mode of the last traversal
     hfmm::DevBuf tstack;                             // per-wave traversal stacks
     int stk_cap = 4096;                              // entries per wave (grows on overflow)

@@ -50,11 +50,6 @@ __device__ __forceinline__ int mac_decide(int4 a, int4 b, int s, const MacConst 
     return 2;
 }
 
-// List kinds: 0 M2L, 1 P2P, 2 handed to the children, 3 candidate pairs (training
-// export), 4..10 M2L at order 2..8 chosen by the learned selector.
-constexpr int kKinds = 11;
-constexpr int kKindCand = 3, kKindOrd = 4;
-
 // Traversal modes: plain MAC; plain MAC plus export of candidate pairs; learned selector.
 enum { kModePlain = 0, kModeExport = 1, kModeLearned = 2 };
 
@@ -67,6 +62,8 @@ struct TravArgs {
     int *pool;       // chunk counter of list kind k at pool[k * kPoolStride] (chunks handed out)
     int *wstate;     // per wave w: [kKinds] next chunk, [kKinds] end of its block, kept across levels
     int *head, *cnt; // [kKinds][ncell]
+    unsigned char *ord;  // kind kKindOrd: the M2L order of each entry
+    int *ocnt;           // learned: entries of order o of sink c at ocnt[(o - 2) * ncell + c]
     uint32_t *stack; // per-wave stacks when they do not fit in LDS
     int stk_cap;
     int *err;        // bit 0: stack overflow, bit 1: pool overflow
@@ -110,9 +107,11 @@ __device__ __forceinline__ int new_chunk(const TravArgs &a, int k, int *bnext, i
 }
 
 // Append `item` of every lane with `pred` to list k, in lane order.  Chunks are taken
-// only when an entry needs them, so a chain never ends in an empty chunk.
+// only when an entry needs them, so a chain never ends in an empty chunk.  ORD: the
+// byte `ob` is stored beside the entry (list kind kKindOrd).
+template <bool ORD = false>
 __device__ __forceinline__ void emit(const TravArgs &a, int k, ListState &L, int *bnext, int *bend, bool pred,
-                                     uint32_t item, uint64_t lt, int lane)
+                                     uint32_t item, uint64_t lt, int lane, unsigned char ob = 0)
 {
     uint64_t mask = __ballot(pred);
     if (mask == 0) return;
@@ -126,12 +125,20 @@ __device__ __forceinline__ void emit(const TravArgs &a, int k, ListState &L, int
         L.fill = 0;
     }
     int room = kChunk - L.fill;
-    if (pred && rank < room) a.items[k][(size_t)L.cur * kChunk + L.fill + rank] = item;
+    if (pred && rank < room) {
+        const size_t at = (size_t)L.cur * kChunk + L.fill + rank;
+        a.items[k][at] = item;
+        if (ORD) a.ord[at] = ob;
+    }
     if (m > room) {
         int c = new_chunk(a, k, bnext, bend, lane);
         if (lane == 0) a.next[k][L.cur] = c;
         L.cur = c;
-        if (pred && rank >= room) a.items[k][(size_t)c * kChunk + rank - room] = item;
+        if (pred && rank >= room) {
+            const size_t at = (size_t)c * kChunk + rank - room;
+            a.items[k][at] = item;
+            if (ORD) a.ord[at] = ob;
+        }
         L.fill = m - room;
     } else {
         L.fill += m;
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     const int scap = a.stk_cap;
     const int4 *cell4 = reinterpret_cast<const int4 *>(a.cells);  // two int4 per cell
     unsigned long long visits = 0, nm2l = 0, np2p = 0;
-    unsigned long long nord[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned nord[kOrders] = {0, 0, 0, 0, 0, 0, 0};  // learned: this wave's M2L pairs per order
     int bnext[kKinds], bend[kKinds];
     int *ws = a.wstate + (size_t)blockIdx.x * 2 * kKinds;
 #pragma unroll
@@ -221,6 +228,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         ListState Ls[kKinds];
 #pragma unroll
         for (int k = 0; k < kKinds; ++k) Ls[k] = ListState{-1, -1, 0, 0};
+        unsigned oc[kOrders] = {0, 0, 0, 0, 0, 0, 0};  // learned: this sink's M2L pairs per order
         int sp = 0;
         int qhead = 0, qtail = 0;  // learned: queue of candidate pairs awaiting the selector
         bool failed = false;
@@ -255,10 +263,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             const bool is_pd = opened && !is_p2p && !leafA && (lvA <= lvB || leafB);
             const bool open_src = opened && !is_p2p && !is_pd;
             if (MODE == kModeLearned) {
-#pragma unroll
-                for (int o = 2; o <= 8; ++o)
-                    emit(a, kKindOrd + o - 2, Ls[kKindOrd + o - 2], bnext, bend, is_m2l && m2l_ord == o, it, lt,
-                         lane);
+                emit<true>(a, kKindOrd, Ls[kKindOrd], bnext, bend, is_m2l, it, lt, lane, (unsigned char)m2l_ord);
             } else {
                 emit(a, 0, Ls[0], bnext, bend, is_m2l, it, lt, lane);
             }
@@ -326,6 +331,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                 mlp_logits_wave(a.model->w, fv, mlp_act, lg);
                 ord = valid ? decode_order(lg, a.model->safety) : 0;
                 opened = ord < 2;
+#pragma unroll
+                for (int o = 0; o < kOrders; ++o) oc[o] += __popcll(__ballot(valid && ord == o + 2));
             } else {
                 visits += kk;
                 valid = lane < kk;
@@ -370,10 +377,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             }
         }
         if (MODE == kModeLearned) {
+            nm2l += Ls[kKindOrd].tot;
 #pragma unroll
-            for (int k = kKindOrd; k < kKinds; ++k) {
-                nm2l += Ls[k].tot;
-                nord[k - kKindOrd] += Ls[k].tot;
+            for (int o = 0; o < kOrders; ++o) {
+                if (lane == 0) a.ocnt[(size_t)o * a.ncell + A] = (int)oc[o];
+                nord[o] += oc[o];
             }
         } else {
             nm2l += Ls[0].tot;
@@ -390,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         atomicAdd(&a.counters[2], nm2l);
         atomicAdd(&a.counters[3], np2p);
         if (MODE == kModeLearned)
-            for (int k = 0; k < 7; ++k) atomicAdd(&a.counters[16 + k], nord[k]);
+            for (int k = 0; k < kOrders; ++k) atomicAdd(&a.counters[16 + k], (unsigned long long)nord[k]);
     }
 }
 
@@ -454,6 +462,8 @@ static int ensure_pools(fmm_tree *t, const int *want)
         int cap = want[k] + want[k] / 4 + 64;
         if (int rc = grow(t->litems[k], (size_t)(cap + 1) * kChunk * 4) | grow(t->lnext[k], (size_t)(cap + 1) * 4))
             return rc;
+        if (k == kKindOrd)
+            if (int rc = grow(t->lord, (size_t)(cap + 1) * kChunk)) return rc;
         t->lcap[k] = cap;
     }
     return 0;
@@ -468,7 +478,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
     MacConst mc;
     mac_setup(P, mc);
     const int ncell = t->ncell;
-    int rc = grow(t->lhead, (size_t)kKinds * ncell * 4) | grow(t->lcnt, (size_t)kKinds * ncell * 4) |
+    // lcnt: kKinds list sizes, then the learned selector's per-order counts
+    const size_t ncnt = (size_t)(kKinds + (mode == kModeLearned ? kOrders : 0)) * ncell;
+    int rc = grow(t->lhead, (size_t)kKinds * ncell * 4) | grow(t->lcnt, (size_t)(kKinds + kOrders) * ncell * 4) |
              grow(t->counters, kCounterBytes);
     if (rc) return rc;
     // list kinds written in this mode get room for their expected size plus the partly
@@ -479,7 +491,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
     want[1] = slack + 8 * t->nleaf;
     want[2] = slack + 2 * ncell;
     if (mode == kModeLearned) {
-        for (int k = kKindOrd; k < kKinds; ++k) want[k] = slack + ncell / 2;
+        want[kKindOrd] = slack + 4 * ncell;
     } else {
         want[0] = slack + 2 * ncell;
         if (mode == kModeExport) want[kKindCand] = slack + 2 * ncell;
@@ -501,7 +513,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         hipMemsetAsync(cb, 0, kCounterBytes, st);
         k_wstate_init<<<(nw + 255) / 256, 256, 0, st>>>(ptr<int>(t->wstate), nw,
                                                         reinterpret_cast<int *>(cb + kPoolByte));
-        hipMemsetAsync(t->lcnt.p, 0, (size_t)kKinds * ncell * 4, st);
+        hipMemsetAsync(t->lcnt.p, 0, ncnt * 4, st);
         TravArgs a;
         a.cells = ptr<Cell>(t->cells);
         a.ncell = ncell;
@@ -516,6 +528,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         a.err = reinterpret_cast<int *>(cb + 96);
         a.head = ptr<int>(t->lhead);
         a.cnt = ptr<int>(t->lcnt);
+        a.ord = ptr<unsigned char>(t->lord);
+        a.ocnt = ptr<int>(t->lcnt) + (size_t)kKinds * ncell;
         a.stack = ptr<uint32_t>(t->tstack);
         a.stk_cap = t->stk_cap;
         a.theta_max2 = theta_max * theta_max;
@@ -544,9 +558,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             pools[k] = want[k] ? t->host[kPoolByte / 4 + k * kPoolStride] : 0;
         memcpy(&err, (char *)t->host + 96, 4);
         if (err == 0) {
-            unsigned long long ord[7];
+            unsigned long long ord[kOrders];
             memcpy(ord, (char *)t->host + 128, sizeof(ord));
-            for (int k = 0; k < 7; ++k) t->stats.n_m2l_by_order[k] = mode == kModeLearned ? (int64_t)ord[k] : 0;
+            for (int k = 0; k < kOrders; ++k) t->stats.n_m2l_by_order[k] = mode == kModeLearned ? (int64_t)ord[k] : 0;
             t->n_visit = (int64_t)c64[0];
             t->n_m2l = (int64_t)c64[2];
             t->n_p2p = (int64_t)c64[3];
