@@ -507,12 +507,14 @@ __global__ __launch_bounds__(64) void k_l2l_axis(const Cell *__restrict__ cells,
     for (int k = 0; k < NC; ++k) dst[k] += C[k] * (T)(1.0 / (double)(2 << tb.d[k]));
 }
 
-// M2L of the high orders, a lane per pair of the flattened (sink-sorted) pair array.  A
-// lane builds its pair's derivative tensor in registers and contracts it with the source
-// multipole, streamed in blocks of MB coefficients (the next block is loaded while the
-// current one is used).  The partial local expansion lives in LDS, one row per lane,
-// except for the kLo lowest outputs, which every block updates and which stay in
-// registers.  At the end the wave sums each output over the runs of lanes that share a
+// M2L of the high orders, a lane per pair of the flattened pair array (each sink's pairs
+// contiguous).  A lane builds its pair's derivative tensor in registers.  Outputs of
+// degree >= P - 2 need source coefficients of degree <= 2 only: they are summed one at a
+// time from the first ten coefficients and staged in LDS, a chunk of rows at a time, for
+// the wave reduction.  The other outputs take the whole source multipole, streamed in
+// blocks of MB coefficients (the next block is loaded while the current one is used):
+// the kLo lowest outputs (degree <= 2) in registers, the rest (degree 3 .. P - 3) in LDS,
+// one row per lane.  A reduction sums each output over the runs of lanes that share a
 // sink and adds the sums into L with one atomic per run.
 constexpr int kLo = 10;  // outputs of degree <= 2
 
@@ -520,28 +522,37 @@ constexpr int kLo = 10;  // outputs of degree <= 2
 // (an order-7/8 FP64 derivative tensor does not fit in registers).
 template <int P, class T> constexpr bool pair_m2l() { return P >= 3 && (sizeof(T) == 4 || P <= 6); }
 
-// Terms of one source block KB .. KB+MB-1 in output-major order: (output n, source k,
-// derivative index n + k), with flags marking the first and last term of each output.
-template <int P> constexpr int block_terms(int kb, int ke)
+// First output of degree >= P - 2 past the register outputs, and the LDS row counts.
+template <int P> constexpr int m2l_hi_begin() { return P >= 3 && ncoef(P - 3) > kLo ? ncoef(P - 3) : kLo; }
+template <int P> constexpr int m2l_mid_rows() { return m2l_hi_begin<P>() - kLo; }
+template <int P> constexpr int m2l_hi_chunk()
+{
+    return m2l_mid_rows<P>() > 32 ? m2l_mid_rows<P>() : (ncoef(P) - m2l_hi_begin<P>() < 32 ? ncoef(P) - m2l_hi_begin<P>() : 32);
+}
+
+// Terms of one source block KB .. KB+MB-1 for the outputs below NE, in output-major order:
+// (output n, source k, derivative index n + k), with flags marking the first and last
+// term of each output.
+template <int P> constexpr int block_terms(int kb, int ke, int ne)
 {
     Tab<P> T{};
     int c = 0;
-    for (int n = 0; n < ncoef(P); ++n)
+    for (int n = 0; n < ne; ++n)
         for (int k = kb; k < ke; ++k)
             if (T.d[k] + T.d[n] <= P) ++c;
     return c;
 }
 
-template <int P, int KB, int MB> struct BlockTab {
+template <int P, int KB, int MB, int NE> struct BlockTab {
     static constexpr int KE = KB + MB < ncoef(P) ? KB + MB : ncoef(P);
-    static constexpr int NQ = block_terms<P>(KB, KE);
+    static constexpr int NQ = block_terms<P>(KB, KE, NE);
     short n[NQ], k[NQ], nm[NQ];
     bool first[NQ], last[NQ];
     constexpr BlockTab() : n(), k(), nm(), first(), last()
     {
         Tab<P> T{};
         int q = 0;
-        for (int kn = 0; kn < ncoef(P); ++kn) {
+        for (int kn = 0; kn < NE; ++kn) {
             int q0 = q;
             for (int km = KB; km < KE; ++km)
                 if (T.d[km] + T.d[kn] <= P) {
@@ -557,14 +568,49 @@ template <int P, int KB, int MB> struct BlockTab {
     }
 };
 
-template <int P, class T, int KB, int MB>
+// Terms of the outputs N0 .. N1-1 (all of degree >= P - 2): (output n - N0, source k < 10,
+// derivative index n + k), output-major, flags as in BlockTab.
+template <int P> constexpr int hi_terms(int n0, int n1)
+{
+    Tab<P> T{};
+    int c = 0;
+    for (int n = n0; n < n1; ++n)
+        for (int k = 0; k < kLo; ++k)
+            if (T.d[k] + T.d[n] <= P) ++c;
+    return c;
+}
+
+template <int P, int N0, int N1> struct HiTab {
+    static constexpr int NQ = hi_terms<P>(N0, N1);
+    short n[NQ], k[NQ], nm[NQ];
+    bool last[NQ];
+    constexpr HiTab() : n(), k(), nm(), last()
+    {
+        Tab<P> T{};
+        int q = 0;
+        for (int kn = N0; kn < N1; ++kn) {
+            int q0 = q;
+            for (int km = 0; km < kLo; ++km)
+                if (T.d[km] + T.d[kn] <= P) {
+                    n[q] = (short)(kn - N0);
+                    k[q] = (short)km;
+                    nm[q] = (short)midx(T.x[kn] + T.x[km], T.y[kn] + T.y[km], T.z[kn] + T.z[km]);
+                    last[q] = false;
+                    ++q;
+                }
+            if (q > q0) last[q - 1] = true;
+        }
+    }
+};
+
+template <int P, class T, int KB, int MB, int NE>
 __device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T *rp, const T *D, T *lo, T *row,
                                                const T *Mcur)
 {
     constexpr Tab<P> tb{};
-    constexpr BlockTab<P, KB, MB> bt{};
+    constexpr BlockTab<P, KB, MB, NE> bt{};
     constexpr int NC = ncoef(P);
-    constexpr int KE = BlockTab<P, KB, MB>::KE;
+    constexpr int KE = BlockTab<P, KB, MB, NE>::KE;
     constexpr int KE2 = KE + MB < NC ? KE + MB : NC;
     T Mnext[MB];
     if constexpr (KE < NC) {
@@ -576,7 +622,7 @@ __device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T
     for (int k = KB; k < KE; ++k) Ms[k - KB] = Mcur[k - KB] * rp[tb.d[k]];
     T a = 0;
 #pragma unroll
-    for (int q = 0; q < BlockTab<P, KB, MB>::NQ; ++q) {
+    for (int q = 0; q < BlockTab<P, KB, MB, NE>::NQ; ++q) {
         const int n = bt.n[q];
         if (bt.first[q]) a = n < kLo ? lo[n] : row[n - kLo];
         a += Ms[bt.k[q]] * D[bt.nm[q]];
@@ -585,82 +631,121 @@ __device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T
             else row[n - kLo] = a;
         }
     }
-    if constexpr (KE < NC) m2l_pair_block<P, T, KE, MB>(Mb, rp, D, lo, row, Mnext);
+    if constexpr (KE < NC) m2l_pair_block<P, T, KE, MB, NE>(Mb, rp, D, lo, row, Mnext);
+}
+
+// Sum the staged rows 0 .. nrows-1 (lane j's values at buf[j * STR + r]) over the runs of
+// lanes with the same sink sid[j] and add each sum to output `out0 + r` of that sink.
+template <class T, int STR>
+__device__ __forceinline__ void m2l_reduce_rows(const T *buf, const int *sid, int nrows, int out0, T *L, int stride)
+{
+    for (int r = threadIdx.x; r < nrows; r += 64) {
+        T sum = 0;
+        int cur = sid[0];
+        for (int j = 0; j < 64; ++j) {
+            const int a = sid[j];
+            if (a != cur) {
+                if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + out0 + r], sum);
+                sum = 0;
+                cur = a;
+            }
+            sum += buf[j * STR + r];
+        }
+        if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + out0 + r], sum);
+    }
+}
+
+// The outputs N0 .. NC-1 in chunks of HC: each output of a chunk summed in a register,
+// staged, reduced.
+template <int P, class T, int N0, int HC, int STR>
+__device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, const int *sid, T *L, int stride)
+{
+    constexpr int NC = ncoef(P);
+    constexpr int N1 = N0 + HC < NC ? N0 + HC : NC;
+    constexpr HiTab<P, N0, N1> ht{};
+    T *row = buf + threadIdx.x * STR;
+    T a = 0;
+#pragma unroll
+    for (int q = 0; q < HiTab<P, N0, N1>::NQ; ++q) {
+        a += Ms[ht.k[q]] * D[ht.nm[q]];
+        if (ht.last[q]) {
+            row[ht.n[q]] = a;
+            a = 0;
+        }
+    }
+    __syncthreads();
+    m2l_reduce_rows<T, STR>(buf, sid, N1 - N0, N0, L, stride);
+    __syncthreads();
+    if constexpr (N1 < NC) m2l_hi_outputs<P, T, N1, HC, STR>(Ms, D, buf, sid, L, stride);
 }
 
 template <int P, class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_m2l_pairs(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : P >= 7 ? 2 : 3))) void k_m2l_pairs(
     const Cell *__restrict__ cells, const int2 *__restrict__ pairs, int64_t npair, const T *__restrict__ M,
     T *__restrict__ L, double box, double rs, int stride)
 {
-    constexpr int NC = ncoef(P), NHI = NC - kLo, STR = NHI | 1;  // odd row stride: no bank conflicts
+    constexpr int NC = ncoef(P), NHB = m2l_hi_begin<P>(), NMID = m2l_mid_rows<P>(), HC = m2l_hi_chunk<P>();
+    constexpr int STR = (NMID > HC ? NMID : HC) | 1;  // odd row stride: no bank conflicts
     constexpr int MB = 16;
-    __shared__ T accs[64 * STR];
+    __shared__ T buf[64 * STR];
     __shared__ int sid[64];
     const int lane = threadIdx.x;
     const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
-    T *row = accs + lane * STR;
-    for (int k = 0; k < NHI; ++k) row[k] = 0;
-    T lo[kLo];
+    T D[NC], rp[P + 1], M0[MB];
 #pragma unroll
-    for (int k = 0; k < kLo; ++k) lo[k] = 0;
+    for (int k = 0; k < NC; ++k) D[k] = 0;
+#pragma unroll
+    for (int k = 0; k < MB; ++k) M0[k] = 0;
+#pragma unroll
+    for (int k = 0; k <= P; ++k) rp[k] = 0;
     int A = -1;
+    const T *Mb = M;
     if (idx < npair) {
         const int2 pr = pairs[idx];
         A = pr.x;
         const uint32_t it = (uint32_t)pr.y;
         const int B = (int)(it >> 5), s = (int)(it & 31);
         const Cell ca = cells[A], cb = cells[B];
-        const T *Mb = M + (size_t)B * stride;
-        T M0[MB];
+        Mb = M + (size_t)B * stride;
 #pragma unroll
         for (int k = 0; k < MB; ++k) M0[k] = Mb[k];
         T Rx, Ry, Rz;
         pair_sep<T>(ca, cb, s, Rx, Ry, Rz);
-        T f[P + 1], D[NC];
+        T f[P + 1];
         prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, (T)(rs / cell_h(ca, box)), f);
         dtensor<P, T>(Rx, Ry, Rz, f, D);
         const T rho = (T)ldexp(1.0, cell_level(ca) - cell_level(cb));
-        T rp[P + 1];
         rp[0] = 1;
 #pragma unroll
         for (int k = 1; k <= P; ++k) rp[k] = rp[k - 1] * rho;
-        m2l_pair_block<P, T, 0, MB>(Mb, rp, D, lo, row, M0);
     }
     sid[lane] = A;
-    __syncthreads();
-    for (int r = kLo + lane; r < NC; r += 64) {
-        T sum = 0;
-        int cur = sid[0];
-        for (int j = 0; j < 64; ++j) {
-            const int a = sid[j];
-            if (a != cur) {
-                if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + r], sum);
-                sum = 0;
-                cur = a;
-            }
-            sum += accs[j * STR + (r - kLo)];
-        }
-        if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + r], sum);
+    // outputs of degree >= P - 2 from the source coefficients of degree <= 2
+    {
+        constexpr Tab<P> tb{};
+        T Ms[kLo];
+#pragma unroll
+        for (int k = 0; k < kLo; ++k) Ms[k] = M0[k] * rp[tb.d[k]];
+        __syncthreads();
+        m2l_hi_outputs<P, T, NHB, HC, STR>(Ms, D, buf, sid, L, stride);
     }
+    // the other outputs from the whole source multipole
+    T *row = buf + lane * STR;
+#pragma unroll
+    for (int k = 0; k < NMID; ++k) row[k] = 0;
+    T lo[kLo];
+#pragma unroll
+    for (int k = 0; k < kLo; ++k) lo[k] = 0;
+    if (idx < npair) m2l_pair_block<P, T, 0, MB, NHB>(Mb, rp, D, lo, row, M0);
     __syncthreads();
+    if constexpr (NMID > 0) {
+        m2l_reduce_rows<T, STR>(buf, sid, NMID, kLo, L, stride);
+        __syncthreads();
+    }
 #pragma unroll
     for (int k = 0; k < kLo; ++k) row[k] = lo[k];
     __syncthreads();
-    if (lane < kLo) {
-        T sum = 0;
-        int cur = sid[0];
-        for (int j = 0; j < 64; ++j) {
-            const int a = sid[j];
-            if (a != cur) {
-                if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + lane], sum);
-                sum = 0;
-                cur = a;
-            }
-            sum += accs[j * STR + lane];
-        }
-        if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + lane], sum);
-    }
+    m2l_reduce_rows<T, STR>(buf, sid, kLo, 0, L, stride);
 }
 
 int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st);
