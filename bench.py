@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
                     help="1: per-pair acceptance and order from the trained selector (packaged model file)")
     ap.add_argument("--cpu-sample", type=int, default=None,
-                    help="oracle targets for cpu_baseline (0: skip; default 60000, 0 for large and full)")
+                    help="oracle targets for cpu_baseline (0: skip; default 100000, 0 for large and full)")
     ap.add_argument("--accuracy-sample", type=int, default=20000,
                     help="particles checked against the brute-force sum (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -191,7 +191,7 @@ def main():
     }
 
     cpu_sample = args.cpu_sample if args.cpu_sample is not None else (
-        0 if args.workload in ("large", "full") else 60000)
+        0 if args.workload in ("large", "full") else 100000)
     if cpu_sample > 0 or args.accuracy_sample > 0:
         import oracle
         if batched:  # sampled particles of the largest box (the oracle runs on that box alone)
