@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64) void k_labels(LabelArgs a)
             const int4 gbv = reinterpret_cast<const int4 *>(a.cells)[2 * B];
             PairGeo g = pair_geo(ga, gbv, s);
             float f[kFeat];
-            pair_features<double>(g, la, lb, a.box, a.rs, a.rcut, mA0, a.M + (size_t)B * NC, f);
+            pair_features(g, la, lb, a.box, a.rs, a.rcut, mA0, cell_features<double>(a.M + (size_t)B * NC), f);
             // expansion in units of h_A: Rh = R / h_A, split scale r_s / h_A, rho = h_B / h_A
             double inv2wa = 0.5 / g.wa;
             double Rx = g.R[0] * inv2wa, Ry = g.R[1] * inv2wa, Rz = g.R[2] * inv2wa;

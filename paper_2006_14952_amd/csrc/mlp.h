@@ -62,13 +62,26 @@ __device__ __forceinline__ PairGeo pair_geo(int4 a, int4 b, int s)
     return g;
 }
 
-// Features of a candidate pair (see the learned-selector notes in the design notes):
-// size/separation ratios, separations in units of r_s, level difference, direction,
-// scale of the sink, and the low-order shape of the source multipole (scaled Mh_m,
-// first 20 coefficients) relative to its mass.
-template <class T>
+// Per-cell part of the features: the mass term of the (scaled) multipole and the norms of
+// its degree-1, -2 and -3 parts (first 20 coefficients) relative to |mass|.
+template <class T> __device__ __forceinline__ float4 cell_features(const T *MB)
+{
+    const float m0 = (float)MB[0];
+    const float am0 = fabsf(m0) > 0.0f ? fabsf(m0) : 1e-30f;
+    float n1 = 0, n2 = 0, n3 = 0;
+    for (int k = 1; k < 4; ++k) n1 += (float)MB[k] * (float)MB[k];
+    for (int k = 4; k < 10; ++k) n2 += (float)MB[k] * (float)MB[k];
+    for (int k = 10; k < 20; ++k) n3 += (float)MB[k] * (float)MB[k];
+    const float ia = 1.0f / am0;
+    return make_float4(m0, sqrtf(n1) * ia, sqrtf(n2) * ia, sqrtf(n3) * ia);
+}
+
+// Features of a candidate pair (sink A, source B): size/separation ratios, separations in
+// units of r_s, level difference, direction, scale of the sink, the low-order shape of the
+// source multipole (cell_features of B) and the log of the mass ratio B : A.  mA0 is the
+// mass term of A's multipole.
 __device__ __forceinline__ void pair_features(const PairGeo &g, int la, int lb, double box, double rs, double rcut,
-                                              double mA0, const T *MB, float *f)
+                                              double mA0, float4 cB, float *f)
 {
     // geometry is exact in units u; the ratios are formed in FP32
     const float u = (float)ldexp(box, -(g.l + 1));
@@ -87,16 +100,10 @@ __device__ __forceinline__ void pair_features(const PairGeo &g, int la, int lb, 
     f[7] = (float)(la - lb);
     f[8] = Rm * iSc;
     f[9] = log2f(hA * irs);
-    const float m0 = (float)MB[0];
-    const float am0 = fabsf(m0) > 0.0f ? fabsf(m0) : 1e-30f;
-    float n1 = 0, n2 = 0, n3 = 0;
-    for (int k = 1; k < 4; ++k) n1 += (float)MB[k] * (float)MB[k];
-    for (int k = 4; k < 10; ++k) n2 += (float)MB[k] * (float)MB[k];
-    for (int k = 10; k < 20; ++k) n3 += (float)MB[k] * (float)MB[k];
-    const float ia = 1.0f / am0;
-    f[10] = sqrtf(n1) * ia;
-    f[11] = sqrtf(n2) * ia;
-    f[12] = sqrtf(n3) * ia;
+    const float am0 = fabsf(cB.x) > 0.0f ? fabsf(cB.x) : 1e-30f;
+    f[10] = cB.y;
+    f[11] = cB.z;
+    f[12] = cB.w;
     f[13] = logf(am0 / fmaxf((float)mA0, 1e-30f));
     f[14] = 0.0f;
     f[15] = 0.0f;

@@ -58,6 +58,7 @@ struct fmm_tree {
     hfmm::DevBuf m2l_ctr, m2l_pairs;  // flattened M2L pairs (sink, item) for the pair kernel; its fill counter
     hfmm::DevBuf wstate;              // per traversal wave: chunk block in use of each list kind
     hfmm::DevBuf bbox;                // per cell: float4 lo, hi of its particles relative to the centre (leaves)
+    hfmm::DevBuf cfeat;               // learned selector: per-cell part of the features (float4)
     int *host = nullptr;  // pinned readback area (kHostInts ints)
     int last_p = -1, last_prec = -1;
 

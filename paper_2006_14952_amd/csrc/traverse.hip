@@ -71,8 +71,7 @@ struct TravArgs {
     // candidate pairs / learned selector
     double theta_max2;             // candidates have (L/S_c)^2 <= theta_max2
     double box, rs, rcut;
-    const void *M;                 // scaled multipoles (features), stride mstride
-    int mstride, mprec;            // mprec 0: double, 1: float
+    const float4 *cf;              // learned: per-cell part of the features (cell_features)
     const MacModel *model;
 };
 
@@ -222,9 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             ichunk = a.head[2 * a.ncell + parentA];
         }
         double mA0 = 0.0;
-        if (MODE == kModeLearned)
-            mA0 = a.mprec ? (double)static_cast<const float *>(a.M)[(size_t)A * a.mstride]
-                          : static_cast<const double *>(a.M)[(size_t)A * a.mstride];
+        if (MODE == kModeLearned) mA0 = a.cf[A].x;
         ListState Ls[kKinds];
 #pragma unroll
         for (int k = 0; k < kKinds; ++k) Ls[k] = ListState{-1, -1, 0, 0};
@@ -320,12 +317,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 if (valid) {
                     gb = cell4[2 * B];
                     PairGeo g = pair_geo(ga, gb, s);
-                    if (a.mprec)
-                        pair_features<float>(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0,
-                                             static_cast<const float *>(a.M) + (size_t)B * a.mstride, fv);
-                    else
-                        pair_features<double>(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0,
-                                              static_cast<const double *>(a.M) + (size_t)B * a.mstride, fv);
+                    pair_features(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0, a.cf[B], fv);
                 }
                 float lg[kCls];
                 mlp_logits_wave(a.model->w, fv, mlp_act, lg);
@@ -437,6 +429,14 @@ static int resident_waves(int mode)
     return resident_waves<kModeLearned>();
 }
 
+// Per-cell part of the selector's features, from the scaled multipoles (stride `stride`).
+template <class T>
+__global__ void k_cell_features(const T *__restrict__ M, int stride, int ncell, float4 *__restrict__ cf)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) cf[c] = cell_features<T>(M + (size_t)c * stride);
+}
+
 constexpr int kPoolByte = 256;
 constexpr int kCounterBytes = kPoolByte + kKinds * kPoolStride * 4;
 static_assert(kCounterBytes <= kHostInts * 4, "counter readback exceeds the pinned area");
@@ -497,6 +497,16 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         if (mode == kModeExport) want[kKindCand] = slack + 2 * ncell;
     }
     if ((rc = ensure_pools(t, want))) return rc;
+    if (mode == kModeLearned) {
+        if (!M || mstride < 20) return set_error(FMM_ERR_ARG, "learned traversal: multipoles of order >= 3 needed");
+        if ((rc = grow(t->cfeat, (size_t)ncell * sizeof(float4)))) return rc;
+        if (mprec)
+            k_cell_features<float><<<(ncell + 63) / 64, 64, 0, st>>>(static_cast<const float *>(M), mstride, ncell,
+                                                                    ptr<float4>(t->cfeat));
+        else
+            k_cell_features<double><<<(ncell + 63) / 64, 64, 0, st>>>(static_cast<const double *>(M), mstride, ncell,
+                                                                     ptr<float4>(t->cfeat));
+    }
     for (int attempt = 0; attempt < 4; ++attempt) {
         int nw = 1;
         for (int l = 0; l < t->nlevel; ++l) {
@@ -536,9 +546,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         a.box = P->box;
         a.rs = P->r_s;
         a.rcut = P->r_cut;
-        a.M = M;
-        a.mstride = mstride;
-        a.mprec = mprec;
+        a.cf = ptr<float4>(t->cfeat);
         a.model = model;
         for (int l = 0; l < t->nlevel; ++l) {
             a.lbeg = t->lvl_beg[l];
