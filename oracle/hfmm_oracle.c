@@ -30,6 +30,8 @@
  *     takes the literal S_c > r_cut > S_m test.
  *   - theta = L / S_c, accepted at equality; L is the larger side of the two cells by
  *     default (mac_mode bit 1 takes the source side only, as worded in Sec. 2.3).
+ *   - mac_mode bit 2: the conventional MAC the cost comparison of Sec. 3 measures against:
+ *     item 2 alone decides (no neglect beyond r_cut, no forced opening across it).
  *   - Periodicity: 27 root images; r_cut < box/2 makes the image of any pair unique.
  *   - A pair contributes iff 0 < r^2 < r_cut^2 (hard cut, no softening).
  */
@@ -279,7 +281,8 @@ double orc_f1(double r, double rs)
 
 typedef struct {
     double box, rs, rcut, theta, G;
-    int p, ncrit, mac_mode; /* bit 0: literal item 3 (S_c); bit 1: source-only size in item 2 */
+    int p, ncrit, mac_mode; /* bit 0: literal item 3 (S_c); bit 1: source-only size in item 2;
+                               bit 2: conventional MAC (item 2 alone) */
 } orc_params;
 
 typedef struct {
@@ -428,6 +431,7 @@ static void build_tree(orc_state *S)
  * item 2: L <= theta S_c                 -> M2L, with L = max(h_A, h_B) by default and
  *         L = h_B (source side only) with mac_mode bit 1
  * otherwise open the larger cell (sink on ties); two leaves -> P2P.
+ * mac_mode bit 2 (conventional MAC): items 1 and 3 are skipped, item 2 alone decides.
  *
  * Why L = max(h_A, h_B) by default: the traversal keeps the two sides within a factor
  * two of each other except when the sink is a leaf, where it keeps opening the source.
@@ -476,9 +480,11 @@ static int mac_decide(const orc_state *S, const orc_mac *mac, int A, int B, int 
         sc2 += R * R; sm2 += g * g; sM2 += G * G;
     }
     double cut2 = mac->cut2[l];
-    if ((double)sm2 > cut2) return 0;                               /* item 1 */
-    int straddle = (S->P.mac_mode & 1) ? ((double)sc2 > cut2) : ((double)sM2 > cut2);
-    if (straddle) { if (nforce) (*nforce)++; return 2; }            /* item 3 */
+    if (!(S->P.mac_mode & 4)) {                                     /* truncated MAC */
+        if ((double)sm2 > cut2) return 0;                           /* item 1 */
+        int straddle = (S->P.mac_mode & 1) ? ((double)sc2 > cut2) : ((double)sM2 > cut2);
+        if (straddle) { if (nforce) (*nforce)++; return 2; }        /* item 3 */
+    }
     /* item 2: size L = larger side of the pair (default) or the source side alone
      * (mac_mode bit 1, the literal Sec. 2.3 wording) */
     int64_t w = (S->P.mac_mode & 2) ? wb : (wa > wb ? wa : wb);

@@ -349,3 +349,55 @@ def test_interaction_lists_partition_pairs():
             assert cover.get((i, int(j), int(s)), 0) == 1, (i, j, s)
             need += 1
     assert need > 1000
+
+
+# ---- conventional MAC (mac_mode bit 2), the baseline of the cost comparison of Sec. 3 --
+
+def test_conventional_mac_tiny_theta_lists_every_leaf_pair():
+    """Conventional MAC, theta -> 0: nothing is accepted or neglected, so every pair of
+    leaves in every one of the 27 root images becomes a P2P pair (27 nleaf^2 of them) and
+    the forces are the hard-cut sum."""
+    rng = np.random.default_rng(41)
+    pos, m = inputs.clustered(300, 2, rng)
+    P = oracle.make_params(rs=0.03, rcut=0.135, theta=1e-3, p=2, ncrit=8, mac_mode=4)
+    res = oracle.fmm(pos, m, P)
+    nleaf = res.stats["nleaf"]
+    assert res.stats["n_m2l"] == 0
+    assert res.stats["n_p2p"] == 27 * nleaf * nleaf
+    bf = oracle.bruteforce(pos, m, P)
+    np.testing.assert_allclose(res.acc, bf, rtol=1e-10, atol=1e-12 * np.abs(bf).max())
+
+
+def test_conventional_mac_covers_every_pair_of_every_image_once():
+    """Without the neglect rule the lists cover all particle pairs of all 27 images (not
+    only those inside r_cut), each exactly once, by P2P or by M2L."""
+    rng = np.random.default_rng(42)
+    pos, m = inputs.clustered(150, 2, rng)
+    P = oracle.make_params(rs=0.03, rcut=0.135, theta=0.5, p=3, ncrit=4, mac_mode=4)
+    res = oracle.fmm(pos, m, P)
+    assert res.stats["n_m2l"] > 0
+    rng_of = {int(k): (int(b), int(e)) for k, _, b, e, _ in res.cells()}
+    seen = np.zeros((len(pos), len(pos), 27), np.int64)
+    for kind in ("p2p", "m2l"):
+        for a, b, s in res.lists(kind):
+            ba, ea = rng_of[int(a)]
+            bb, eb = rng_of[int(b)]
+            seen[ba:ea, bb:eb, int(s)] += 1
+    assert seen.min() == 1 and seen.max() == 1
+
+
+def test_uniform_m2l_vanishes_only_with_the_truncated_mac():
+    """Uniform 32^3 box, r_s = 1.25 mesh cells, leaves of up to 32 particles (Sec. 3): the
+    truncated MAC leaves no M2L at all (every surviving pair is handled by P2P, as in P3M),
+    the conventional MAC needs many.  Here every leaf lies on one level, so the
+    conventional MAC opens exactly the 27 adjacent leaves of each leaf (L / S_c = 1) and
+    accepts every pair two cells apart (L / S_c = 1/2 = theta)."""
+    pos, m = inputs.make("uniform")
+    pr = inputs.split_params("uniform")
+    kw = dict(rs=pr["rs"], rcut=pr["rcut"], theta=0.5, p=2, ncrit=32)
+    tr = oracle.fmm(pos, m, oracle.make_params(**kw)).stats
+    cv = oracle.fmm(pos, m, oracle.make_params(mac_mode=4, **kw)).stats
+    assert tr["n_m2l"] == 0 and tr["n_p2p"] > 0
+    assert cv["n_m2l"] > 1000
+    assert cv["nleaf"] == 16 ** 3 and cv["maxlevel"] == 4
+    assert cv["n_p2p"] == 27 * cv["nleaf"]
