@@ -54,7 +54,9 @@ extern "C" {
  *   n_crit    leaf limit: a cell is split while it holds more than n_crit particles (Sec. 2.1), >= 1
  *   mac_mode  bit 0: literal item 3 (open when S_c > r_cut > S_m) instead of the strict
  *             reading (open when S_M > r_cut >= S_m); bit 1: item 2 uses the source side
- *             alone instead of the larger side of the pair
+ *             alone instead of the larger side of the pair; bit 2: conventional MAC, the
+ *             baseline of the cost comparison of Sec. 3 (item 2 alone: no neglect beyond
+ *             r_cut, no forced opening across it; forces stay correct, at higher cost)
  *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
  *             compensated per-particle sums, FP64 positions, cell offsets and final sum
  *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see

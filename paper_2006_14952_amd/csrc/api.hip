@@ -33,7 +33,7 @@ static int check_params(const fmm_params *P)
     if (!isfinite(P->G)) return set_error(FMM_ERR_ARG, "G must be finite");
     if (P->p < 0 || P->p > FMM_PMAX) return set_error(FMM_ERR_ARG, "p must be in [0, %d]", FMM_PMAX);
     if (P->n_crit < 1) return set_error(FMM_ERR_ARG, "n_crit must be >= 1");
-    if (P->mac_mode < 0 || P->mac_mode > 3) return set_error(FMM_ERR_ARG, "mac_mode must be in [0, 3]");
+    if (P->mac_mode < 0 || P->mac_mode > 7) return set_error(FMM_ERR_ARG, "mac_mode must be in [0, 7]");
     if (P->precision != 0 && P->precision != 1) return set_error(FMM_ERR_ARG, "precision must be 0 or 1");
     if (P->learned != 0 && P->learned != 1) return set_error(FMM_ERR_ARG, "learned must be 0 or 1");
     return 0;

@@ -39,12 +39,14 @@ __device__ __forceinline__ int mac_decide(int4 a, int4 b, int s, const MacConst 
     double g0 = fmax(A0 - half, 0.0), g1 = fmax(A1 - half, 0.0), g2 = fmax(A2 - half, 0.0);
     double sm2 = g0 * g0 + g1 * g1 + g2 * g2;
     double cut2 = ldexp(mc.cut2[0], 2 * l);  // equals (r_cut / u_l)^2 exactly
-    if (sm2 > cut2) return 0;
     double sc2 = R0 * R0 + R1 * R1 + R2 * R2;
-    double G0 = A0 + half, G1 = A1 + half, G2 = A2 + half;
-    double sM2 = G0 * G0 + G1 * G1 + G2 * G2;
-    bool straddle = (mc.mode & 1) ? (sc2 > cut2) : (sM2 > cut2);
-    if (straddle) return 2;
+    if (!(mc.mode & 4)) {  // truncated MAC; mode bit 2: conventional MAC, item 2 alone
+        if (sm2 > cut2) return 0;
+        double G0 = A0 + half, G1 = A1 + half, G2 = A2 + half;
+        double sM2 = G0 * G0 + G1 * G1 + G2 * G2;
+        bool straddle = (mc.mode & 1) ? (sc2 > cut2) : (sM2 > cut2);
+        if (straddle) return 2;
+    }
     double w = (mc.mode & 2) ? wb : fmax(wa, wb);
     if (4.0 * w * w <= mc.theta2 * sc2) return 1;
     return 2;
@@ -171,14 +173,16 @@ __device__ __forceinline__ MacEval mac_eval(int4 a, int4 b, int s, const MacCons
     double w = (mc.mode & 2) ? g.wb : fmax(g.wa, g.wb);
     r.q2 = 4.0 * w * w / g.sc2;
     r.straddle = false;
-    if (g.sm2 > cut2) {
-        r.code = 0;
-        return r;
-    }
-    r.straddle = (mc.mode & 1) ? (g.sc2 > cut2) : (g.sM2 > cut2);
-    if (r.straddle) {
-        r.code = 2;
-        return r;
+    if (!(mc.mode & 4)) {  // truncated MAC; mode bit 2: conventional MAC, item 2 alone
+        if (g.sm2 > cut2) {
+            r.code = 0;
+            return r;
+        }
+        r.straddle = (mc.mode & 1) ? (g.sc2 > cut2) : (g.sM2 > cut2);
+        if (r.straddle) {
+            r.code = 2;
+            return r;
+        }
     }
     r.code = (4.0 * w * w <= mc.theta2 * g.sc2) ? 1 : 2;
     return r;

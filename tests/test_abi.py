@@ -26,7 +26,7 @@ def test_version_and_error_string():
 
 
 @pytest.mark.parametrize("bad", [dict(theta=0.0), dict(p=9), dict(p=-1), dict(n_crit=0), dict(r_cut=0.6),
-                                 dict(r_s=-1.0), dict(precision=2), dict(mac_mode=4), dict(box=0.0)])
+                                 dict(r_s=-1.0), dict(precision=2), dict(mac_mode=8), dict(box=0.0)])
 def test_bad_params_rejected_without_gpu(bad):
     kw = dict(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
     kw.update(bad)

@@ -76,8 +76,9 @@ def test_fp32_every_order_clustered(p):
     t.free()
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_mac_modes_lists_identical(mode):
+    """Every MAC reading, and the conventional MAC (bit 2), on the GPU and the oracle."""
     rng = inputs.rng_for(102, mode)
     pos, m = inputs.clustered(6000, 5, rng)
     prm = hf.params(r_s=0.015, r_cut=0.0675, theta=0.5, p=4, n_crit=16, mac_mode=mode)
