@@ -49,13 +49,13 @@ static void free_buf(DevBuf &b)
 static float ev_ms(fmm_tree *t, int a, int b)
 {
     float ms = 0;
-    hipEventElapsedTime(&ms, t->ev[a], t->ev[b]);
+    (void)hipEventElapsedTime(&ms, t->ev[a], t->ev[b]);  // timing only: 0 if unavailable
     return ms;
 }
 
 static void mark(fmm_tree *t, int k, hipStream_t st)
 {
-    if (t->timing) hipEventRecord(t->ev[k], st);
+    if (t->timing) (void)hipEventRecord(t->ev[k], st);  // a failure shows in the stage's error check
 }
 
 // The stages of one short-range evaluation on a built tree (or forest of boxes).
@@ -86,38 +86,38 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     // the second stream; P2P runs there beside M2L and L2L.
     // The FP32 P2P's leaf boxes depend on the tree only: they are computed on the second
     // stream ahead of P2P.
-    hipEventRecord(t->dep[0], st);
+    if ((rc = hip_check(hipEventRecord(t->dep[0], st), "event")) || (rc = hip_check(hipStreamWaitEvent(ax, t->dep[0], 0), "event wait")))
+        return rc;
     mark(t, 0, st);
-    hipStreamWaitEvent(ax, t->dep[0], 0);
     if (P->learned) {  // the selector's features read the multipoles
         mark(t, 9, st);
         if ((rc = upward(t, &P8, st))) return rc;
         mark(t, 1, st);
-        hipEventRecord(t->dep[1], st);
+        if ((rc = hip_check(hipEventRecord(t->dep[1], st), "event"))) return rc;
         if ((rc = p2p_bbox(t, P, ax))) return rc;
         rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st);
     } else {
         mark(t, 9, ax);
         if ((rc = upward(t, &P8, ax))) return rc;
         mark(t, 1, ax);
-        hipEventRecord(t->dep[1], ax);
+        if ((rc = hip_check(hipEventRecord(t->dep[1], ax), "event"))) return rc;
         if ((rc = p2p_bbox(t, P, ax))) return rc;
         rc = traverse(t, P, st);
     }
     if (rc) return rc;
     mark(t, 2, st);
-    hipEventRecord(t->dep[2], st);
-    hipStreamWaitEvent(ax, t->dep[2], 0);
+    if ((rc = hip_check(hipEventRecord(t->dep[2], st), "event")) || (rc = hip_check(hipStreamWaitEvent(ax, t->dep[2], 0), "event wait")))
+        return rc;
     mark(t, 5, ax);
     if ((rc = p2p(t, P, ax))) return rc;
     mark(t, 6, ax);
-    hipEventRecord(t->dep[3], ax);
-    hipStreamWaitEvent(st, t->dep[1], 0);
+    if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[1], 0), "event wait")))
+        return rc;
     if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
     mark(t, 3, st);
     if ((rc = downward_l2l(t, &P8, st))) return rc;
     mark(t, 4, st);
-    hipStreamWaitEvent(st, t->dep[3], 0);
+    if ((rc = hip_check(hipStreamWaitEvent(st, t->dep[3], 0), "event wait"))) return rc;
     mark(t, 10, st);
     if ((rc = l2p_combine(t, &P8, acc, accumulate, st))) return rc;
     mark(t, 11, st);
@@ -129,7 +129,7 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     S.n_visit = t->n_visit;
     S.levels_traversed = t->nlevel;
     if (t->timing) {  // stages overlap across the two streams; each time is its own span
-        hipEventSynchronize(t->ev[11]);
+        if ((rc = hip_check(hipEventSynchronize(t->ev[11]), "timing event"))) return rc;
         S.t_upward_ms = ev_ms(t, 9, 1);
         S.t_traverse_ms = P->learned ? ev_ms(t, 1, 2) : ev_ms(t, 0, 2);
         S.t_m2l_ms = ev_ms(t, 2, 3);
@@ -159,15 +159,15 @@ static int build_common(const fmm_params *P, int64_t n, const double *pos, const
         if (!t) return set_error(FMM_ERR_NOMEM, "tree allocation");
         fresh = true;
     }
-    if (t->timing) hipEventRecord(t->ev[14], st);
+    if (t->timing) (void)hipEventRecord(t->ev[14], st);  // timing only
     int rc = tree_build(t, P, n, pos, mass, nbox, offsets, st);
     if (rc) {
         if (fresh) fmm_free_tree(t);
         return rc;
     }
     if (t->timing) {
-        hipEventRecord(t->ev[15], st);
-        hipEventSynchronize(t->ev[15]);
+        (void)hipEventRecord(t->ev[15], st);  // timing only
+        (void)hipEventSynchronize(t->ev[15]);
         t->stats.t_build_ms = ev_ms(t, 14, 15);
     }
     t->stats.n = n;
@@ -270,13 +270,13 @@ int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t 
         if (!rc) rc = run_forces(t, &Q, acc, st);
         float total = 0.0f;
         for (int r = 0; r < (reps > 0 ? reps : 1) && !rc; ++r) {
-            hipEventRecord(e0, st);
+            (void)hipEventRecord(e0, st);  // timing events; failures surface in the step's own checks
             rc = build();
             if (!rc) rc = run_forces(t, &Q, acc, st);
-            hipEventRecord(e1, st);
+            (void)hipEventRecord(e1, st);
             if (!rc) rc = hip_check(hipEventSynchronize(e1), "autotune");
             float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
             total += ms;
         }
         const double ms = total / (reps > 0 ? reps : 1);
@@ -331,11 +331,14 @@ static int copy_kind(fmm_tree *t, int kind, uint64_t *out, int64_t cap, int64_t 
     std::vector<uint32_t> items((size_t)nchunk * kChunk);
     std::vector<int> next(nchunk);
     if (hipDeviceSynchronize() != hipSuccess) return set_error(FMM_ERR_HIP, "sync");
-    hipMemcpy(cells.data(), t->cells.p, (size_t)nc * sizeof(Cell), hipMemcpyDeviceToHost);
-    hipMemcpy(head.data(), ptr<int>(t->lhead) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost);
-    hipMemcpy(cnt.data(), ptr<int>(t->lcnt) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost);
-    hipMemcpy(items.data(), t->litems[kind].p, items.size() * 4, hipMemcpyDeviceToHost);
-    hipMemcpy(next.data(), t->lnext[kind].p, next.size() * 4, hipMemcpyDeviceToHost);
+    if (hipMemcpy(cells.data(), t->cells.p, (size_t)nc * sizeof(Cell), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(head.data(), ptr<int>(t->lhead) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(cnt.data(), ptr<int>(t->lcnt) + (size_t)kind * nc, (size_t)nc * 4, hipMemcpyDeviceToHost) !=
+            hipSuccess ||
+        hipMemcpy(items.data(), t->litems[kind].p, items.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(next.data(), t->lnext[kind].p, next.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(FMM_ERR_HIP, "copying interaction lists");
     std::vector<uint64_t> key(nc);
     for (int c = 0; c < nc; ++c)
         key[c] = cell_key_host(cell_level(cells[c]), cell_ix(cells[c]), cells[c].iy, cells[c].iz);
@@ -380,13 +383,13 @@ int fmm_mac_training_data(fmm_tree *t, const fmm_params *P, double theta_max, co
     rc = grow(aref, (size_t)t->n * 24) | grow(ctr, 16);
     if (!rc) rc = sort_soa(t, acc_ref, ptr<double>(aref), st);
     if (!rc) {
-        hipMemsetAsync(ctr.p, 0, 4, st);
-        rc = run_labels(t, P, ptr<double>(aref), eps, stride, feats, labels, errs, pairs, (int)cap, ptr<int>(ctr), st);
+        rc = hip_check(hipMemsetAsync(ctr.p, 0, 4, st), "training data");
+        if (!rc) rc = run_labels(t, P, ptr<double>(aref), eps, stride, feats, labels, errs, pairs, (int)cap, ptr<int>(ctr), st);
     }
     int n = 0;
     if (!rc) {
-        hipMemcpyAsync(&n, ctr.p, 4, hipMemcpyDeviceToHost, st);
-        rc = hip_check(hipStreamSynchronize(st), "training data");
+        rc = hip_check(hipMemcpyAsync(&n, ctr.p, 4, hipMemcpyDeviceToHost, st), "training data");
+        if (!rc) rc = hip_check(hipStreamSynchronize(st), "training data");
     }
     if (aref.p) (void)hipFree(aref.p);
     if (ctr.p) (void)hipFree(ctr.p);
@@ -421,7 +424,7 @@ int fmm_hybrid_forces_tree(fmm_tree **tree, const fmm_params *P, int mesh, int64
     mark(t, 8, st);
     if (int rc = run_forces(t, P, acc, st, 1)) return rc;
     if (t->timing) {
-        hipEventSynchronize(t->ev[8]);
+        (void)hipEventSynchronize(t->ev[8]);  // timing only
         t->stats.t_pm_ms = ev_ms(t, 7, 8);
     }
     return hip_check(hipGetLastError(), "hybrid");

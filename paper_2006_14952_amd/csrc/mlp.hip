@@ -298,7 +298,7 @@ int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const f
     float wsum = 0.0f;
     for (int s = 0; s < B; ++s) wsum += cw[hy[s]];
     if (!(wsum > 0)) return set_error(FMM_ERR_ARG, "class weights sum to zero");
-    hipMemsetAsync(loss, 0, 4, st);
+    if (int rc = hip_check(hipMemsetAsync(loss, 0, 4, st), "mlp loss")) return rc;
     unsigned nb = (unsigned)((B + 127) / 128);
     k_mlp_fwd<<<nb, 128, 0, st>>>(params, mu, isd, X, B, ptr<float>(g_ts.xn), ptr<float>(g_ts.h1), ptr<float>(g_ts.h2),
                                   ptr<float>(g_ts.z));

@@ -182,9 +182,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
             // starts at (the largest entry wins, so entries left empty by the box test are
             // skipped), and a max-scan over the slots carries the marks forward.  Lane l
             // owns slots kPer l .. kPer l + kPer - 1.
+            // ecarry: the entry holding the last slot fetched so far (it holds slot sbase
+            // unless an entry starts there, which the marks then supply)
+            int ecarry = 0;
             auto fetch = [&](int sbase) __attribute__((always_inline)) {
                 const int nraw = min(kStage, total - sbase);
-                const int efirst = find_entry(epref, ne, sbase);
+                const int efirst = ecarry;
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) smark[kPer * lane + u] = 0;
                 __syncthreads();
@@ -218,6 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                         rv[u] = a.rel[ebeg[e] + sbase + q - epref[e]];
                     }
                 }
+                ecarry = __builtin_amdgcn_readlane(ev[kPer - 1], 63);
             };
             if (!F64 && total > 0) fetch(0);
             for (int sb = 0; sb < total; sb += kStage) {

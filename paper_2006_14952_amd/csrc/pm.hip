@@ -178,18 +178,19 @@ static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos
     size_t nr = (size_t)mesh * mesh * mesh, nc = (size_t)mesh * mesh * (mesh / 2 + 1);
     if (pos_check) {
         int *bad = ptr<int>(pl->amesh);  // scratch flag in the (not yet used) output mesh
-        hipMemsetAsync(bad, 0, sizeof(int), st);
+        if (int rc = hip_check(hipMemsetAsync(bad, 0, sizeof(int), st), "pm check")) return rc;
         k_check_finite<<<(unsigned)((3 * (size_t)n + 255) / 256), 256, 0, st>>>(pos_check, 3 * (size_t)n, bad);
         int hbad = 0;
-        hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st);
-        if (hipStreamSynchronize(st) != hipSuccess) return set_error(FMM_ERR_HIP, "pm sync");
+        if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return set_error(FMM_ERR_HIP, "pm sync");
         if (hbad) return set_error(FMM_ERR_NAN, "non-finite particle position");
     }
-    hipMemsetAsync(pl->rho.p, 0, nr * 8, st);
+    if (int rc = hip_check(hipMemsetAsync(pl->rho.p, 0, nr * 8, st), "pm mesh")) return rc;
     double d = P->box / mesh;
     k_cic_deposit<S><<<(n + 255) / 256, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
-    hipfftSetStream(pl->r2c, st);
-    hipfftSetStream(pl->c2r, st);
+    if (hipfftSetStream(pl->r2c, st) != HIPFFT_SUCCESS || hipfftSetStream(pl->c2r, st) != HIPFFT_SUCCESS)
+        return set_error(FMM_ERR_HIP, "hipfftSetStream");
     if (hipfftExecD2Z(pl->r2c, ptr<double>(pl->rho), ptr<hipfftDoubleComplex>(pl->rhok)) != HIPFFT_SUCCESS)
         return set_error(FMM_ERR_HIP, "hipfftExecD2Z");
     for (int axis = 0; axis < 3; ++axis) {

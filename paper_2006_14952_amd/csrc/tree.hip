@@ -341,13 +341,15 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     t->nbox = nbox;
     t->hboxoff.resize(nbox + 1);
     for (int b = 0; b <= nbox; ++b) t->hboxoff[b] = hoff ? (int)hoff[b] : (b ? n : 0);
-    hipMemcpyAsync(t->boxoff.p, t->hboxoff.data(), (size_t)(nbox + 1) * 4, hipMemcpyHostToDevice, st);
+    if ((rc = hip_check(hipMemcpyAsync(t->boxoff.p, t->hboxoff.data(), (size_t)(nbox + 1) * 4, hipMemcpyHostToDevice, st),
+                        "box offsets")))
+        return rc;
     if (!t->host) {
         if (hipHostMalloc((void **)&t->host, kHostInts * sizeof(int), hipHostMallocDefault) != hipSuccess)
             return set_error(FMM_ERR_NOMEM, "pinned host buffer");
     }
     int *bad = ptr<int>(t->flag);
-    hipMemsetAsync(bad, 0, sizeof(int), st);
+    if ((rc = hip_check(hipMemsetAsync(bad, 0, sizeof(int), st), "tree flags"))) return rc;
     if (n > 0) {
         k_keys<<<blocks(n, 256), 256, 0, st>>>(pos, n, P->box, ptr<uint64_t>(t->keys[0]), ptr<uint32_t>(t->idx[0]), bad);
         if ((rc = radix_sort(t, n, nbox, st))) return rc;
@@ -368,7 +370,8 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
         int *nch = ptr<int>(t->nch), *off = nch + ln;
         k_count_children<<<blocks(ln, 256), 256, 0, st>>>(ptr<Cell>(t->cells), lb, ln, l, P->n_crit, keys, nch);
         if ((rc = scan_exclusive(nch, off, ln, bad + 1, st, t->scan_tmp))) return rc;
-        hipMemcpyAsync(t->host, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+        if ((rc = hip_check(hipMemcpyAsync(t->host, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "level size")))
+            return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "tree level sync"))) return rc;
         if (t->host[0]) return set_error(FMM_ERR_NAN, "non-finite particle position");
         int nnext = t->host[1];
@@ -389,7 +392,8 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     int *flag = ptr<int>(t->nch), *off = flag + t->ncell;
     k_leaf_flag<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag);
     if ((rc = scan_exclusive(flag, off, t->ncell, bad + 1, st, t->scan_tmp))) return rc;
-    hipMemcpyAsync(t->host, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(hipMemcpyAsync(t->host, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st), "leaf count")))
+        return rc;
     if ((rc = hip_check(hipStreamSynchronize(st), "leaf count"))) return rc;
     t->nleaf = t->host[0];
     if ((rc = grow(t->leaves, (size_t)t->nleaf * 4 + 4))) return rc;

@@ -150,8 +150,7 @@ static int scan_rec(const int *in, int *out, int n, hipStream_t st, int *tmp)
 int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp)
 {
     if (n <= 0) {
-        if (total) hipMemsetAsync(total, 0, sizeof(int), st);
-        return 0;
+        return total ? hip_check(hipMemsetAsync(total, 0, sizeof(int), st), "scan total") : 0;
     }
     size_t need = 0;
     for (int m = n; m > 1; m = (m + kScanTile - 1) / kScanTile) need += 2 * ((m + kScanTile - 1) / kScanTile);
