@@ -466,6 +466,8 @@ void fmm_free_tree(fmm_tree *t)
     if (t->host) (void)hipHostFree(t->host);
     if (t->events_ready)
         for (auto &e : t->ev) (void)hipEventDestroy(e);
+    if (t->bev_ready)
+        for (auto &e : t->bev) (void)hipEventDestroy(e);
     if (t->aux) {
         (void)hipStreamSynchronize(t->aux);
         for (auto &e : t->dep) (void)hipEventDestroy(e);

@@ -78,6 +78,9 @@ int hip_check(hipError_t e, const char *what);
 
 // scans (int32), result is exclusive; total (device int) optional
 int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp);
-int zero_async(void *p, size_t bytes, hipStream_t st);  // p 16-byte aligned, bytes a multiple of 4
+int zero_async(void *p, size_t bytes, hipStream_t st);
+// scan_exclusive of in[0 .. n), n = *hi - *lo read on the device, n <= n_max
+int scan_exclusive_dn(const int *in, int *out, const int *lo, const int *hi, int n_max, int *total, hipStream_t st,
+                      DevBuf &tmp);  // p 16-byte aligned, bytes a multiple of 4
 
 }  // namespace hfmm

@@ -6,6 +6,7 @@
 
 namespace hfmm {
 constexpr int kHostInts = 1024;
+constexpr int kHostLevels = 512;  // tree build: level sizes mirrored at host[kHostLevels ...]
 // Interaction list kinds: 0 M2L, 1 P2P, 2 handed to the children, 3 candidate pairs
 // (training export), 4 M2L pairs of the learned selector (all orders; the order of each
 // entry in a byte beside it).
@@ -65,6 +66,8 @@ struct fmm_tree {
     // second stream (default priority) for stages independent of the caller's stream
     hipStream_t aux = nullptr;
     hipEvent_t dep[4]{};
+    hipEvent_t bev[hfmm::kMaxLevel + 1]{};  // tree build: one per level launch
+    bool bev_ready = false;
 
     // timing
     int timing = 0;

@@ -244,49 +244,87 @@ __device__ inline void octant_bounds(const uint64_t *keys, const Cell &c, int l,
     b[8] = c.end;
 }
 
-__global__ void k_count_children(const Cell *__restrict__ cells, int lbeg, int ln, int l, int ncrit,
-                                 const uint64_t *__restrict__ keys, int *__restrict__ nch)
+// Level by level without host round trips: the cells of level l are lv[l] .. lv[l+1]-1
+// in device memory, the cell array has room for `cap` cells, and *ovf is set (and every
+// later level left empty) when a level would not fit; the host then rebuilds with room.
+__global__ void k_level_init(int *__restrict__ lv, int nbox, int *__restrict__ ovf)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ln) return;
-    Cell c = cells[lbeg + t];
-    int k = 0;
-    if (c.end - c.beg > ncrit && l < kMaxLevel) {
-        int b[9];
-        octant_bounds(keys, c, l, b);
-        for (int o = 0; o < 8; ++o) k += b[o + 1] > b[o];
+    if (threadIdx.x == 0) {
+        lv[0] = 0;
+        lv[1] = nbox;
+        *ovf = 0;
     }
-    nch[t] = k;
 }
 
-__global__ void k_make_children(Cell *__restrict__ cells, int lbeg, int ln, int l, int ncrit,
-                                const uint64_t *__restrict__ keys, const int *__restrict__ off, int nbeg)
+__global__ void k_count_children_dev(const Cell *__restrict__ cells, const int *__restrict__ lv, int l, int ncrit,
+                                     const uint64_t *__restrict__ keys, int *__restrict__ nch,
+                                     const int *__restrict__ ovf)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ln) return;
-    int ci = lbeg + t;
-    Cell c = cells[ci];
-    if (!(c.end - c.beg > ncrit && l < kMaxLevel)) return;
-    int b[9];
-    octant_bounds(keys, c, l, b);
-    int first = nbeg + off[t], k = 0;
-    for (int o = 0; o < 8; ++o) {
-        if (b[o + 1] == b[o]) continue;
-        Cell ch;
-        ch.xln = pack_xln(2 * cell_ix(c) + ((o >> 2) & 1), l + 1, 0);
-        ch.iy = 2 * c.iy + ((o >> 1) & 1);
-        ch.iz = 2 * c.iz + (o & 1);
-        ch.pad = 0;
-        ch.beg = b[o];
-        ch.end = b[o + 1];
-        ch.child = -1;
-        ch.parent = ci;
-        cells[first + k] = ch;
-        ++k;
+    if (*ovf) return;
+    const int lbeg = lv[l], ln = lv[l + 1] - lbeg;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ln; t += gridDim.x * blockDim.x) {
+        Cell c = cells[lbeg + t];
+        int k = 0;
+        if (c.end - c.beg > ncrit && l < kMaxLevel) {
+            int b[9];
+            octant_bounds(keys, c, l, b);
+            for (int o = 0; o < 8; ++o) k += b[o + 1] > b[o];
+        }
+        nch[t] = k;
     }
-    c.child = first;
-    c.xln = pack_xln(cell_ix(c), l, k);
-    cells[ci] = c;
+}
+
+__global__ void k_make_children_dev(Cell *__restrict__ cells, const int *__restrict__ lv, int l, int ncrit,
+                                    const uint64_t *__restrict__ keys, const int *__restrict__ off, int cap,
+                                    int *__restrict__ ovf)
+{
+    if (*ovf) return;
+    const int lbeg = lv[l], ln = lv[l + 1] - lbeg, nbeg = lv[l + 1];
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ln; t += gridDim.x * blockDim.x) {
+        const int ci = lbeg + t;
+        Cell c = cells[ci];
+        if (!(c.end - c.beg > ncrit && l < kMaxLevel)) continue;
+        int b[9];
+        octant_bounds(keys, c, l, b);
+        int nk = 0;
+        for (int o = 0; o < 8; ++o) nk += b[o + 1] > b[o];
+        const int first = nbeg + off[t];
+        if (first + nk > cap) {  // no room: the level is dropped and the tree rebuilt
+            atomicOr(ovf, 1);
+            continue;
+        }
+        int k = 0;
+        for (int o = 0; o < 8; ++o) {
+            if (b[o + 1] == b[o]) continue;
+            Cell ch;
+            ch.xln = pack_xln(2 * cell_ix(c) + ((o >> 2) & 1), l + 1, 0);
+            ch.iy = 2 * c.iy + ((o >> 1) & 1);
+            ch.iz = 2 * c.iz + (o & 1);
+            ch.pad = 0;
+            ch.beg = b[o];
+            ch.end = b[o + 1];
+            ch.child = -1;
+            ch.parent = ci;
+            cells[first + k] = ch;
+            ++k;
+        }
+        c.child = first;
+        c.xln = pack_xln(cell_ix(c), l, k);
+        cells[ci] = c;
+    }
+}
+
+// lv[l+2] = end of the next level; an overflowing level leaves the next one empty
+__global__ void k_level_end(int *__restrict__ lv, int l, const int *__restrict__ total, int cap, int *__restrict__ ovf)
+{
+    if (threadIdx.x != 0) return;
+    int e = lv[l + 1] + (*ovf ? 0 : *total);
+    if (e > cap) {
+        *ovf = 1;
+        e = lv[l + 1];
+    }
+    if (*ovf) e = lv[l + 1];
+    lv[l + 2] = e;
 }
 
 __global__ void k_leaf_flag(const Cell *__restrict__ cells, int ncell, int *__restrict__ flag)
@@ -336,7 +374,7 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     if (!rc) rc = grow(t->xs, nn * 8) | grow(t->ys, nn * 8) | grow(t->zs, nn * 8) | grow(t->ms, nn * 8);
     if (!rc) rc = grow(t->perm, nn * 4) | grow(t->leaf_of, nn * 4) | grow(t->rel32, nn * 16) | grow(t->nearf, nn * 24);
     if (!rc) rc = grow(t->flag, 64 * sizeof(int));
-    if (!rc) rc = grow(t->cells, sizeof(Cell) * (1024 + (size_t)nbox)) | grow(t->boxoff, (size_t)(nbox + 1) * 4);
+    if (!rc) rc = grow(t->boxoff, (size_t)(nbox + 1) * 4);
     if (rc) return rc;
     t->nbox = nbox;
     t->hboxoff.resize(nbox + 1);
@@ -357,30 +395,63 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
                                                  ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms),
                                                  ptr<int>(t->perm));
     }
-    k_roots<<<blocks(nbox, 64), 64, 0, st>>>(ptr<Cell>(t->cells), nbox, ptr<int>(t->boxoff));
     if ((rc = hip_check(hipGetLastError(), "tree keys"))) return rc;
 
-    t->lvl_beg.assign(1, 0);
-    t->lvl_beg.push_back(nbox);
-    const uint64_t *keys = ptr<uint64_t>(t->keys[t->sorted]);
-    int l = 0;
-    for (; l < kMaxLevel && n > 0; ++l) {
-        int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
-        if ((rc = grow(t->nch, (size_t)ln * 2 * sizeof(int) + 64))) return rc;
-        int *nch = ptr<int>(t->nch), *off = nch + ln;
-        k_count_children<<<blocks(ln, 256), 256, 0, st>>>(ptr<Cell>(t->cells), lb, ln, l, P->n_crit, keys, nch);
-        if ((rc = scan_exclusive(nch, off, ln, bad + 1, st, t->scan_tmp))) return rc;
-        if ((rc = hip_check(hipMemcpyAsync(t->host, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st), "level size")))
-            return rc;
-        if ((rc = hip_check(hipStreamSynchronize(st), "tree level sync"))) return rc;
-        if (t->host[0]) return set_error(FMM_ERR_NAN, "non-finite particle position");
-        int nnext = t->host[1];
-        if (nnext == 0) break;
-        int nbeg = t->lvl_beg[l + 1];
-        if ((rc = grow_keep(t->cells, (size_t)(nbeg + nnext) * sizeof(Cell), (size_t)nbeg * sizeof(Cell)))) return rc;
-        k_make_children<<<blocks(ln, 256), 256, 0, st>>>(ptr<Cell>(t->cells), lb, ln, l, P->n_crit, keys, off, nbeg);
-        t->lvl_beg.push_back(nbeg + nnext);
+    // Cells level by level.  The level sizes stay on the device (lv); the host reads each
+    // one back a level late through an event, only to stop the loop, so the GPU never
+    // waits for it.  Room for `cap` cells: the previous tree's count or 8 n / n_crit,
+    // four times more after an overflow.
+    if (!t->bev_ready) {
+        for (auto &e : t->bev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return set_error(FMM_ERR_HIP, "hipEventCreateWithFlags");
+        t->bev_ready = true;
     }
+    int *lv = bad + 8, *ovf = bad + 2;  // flag area: [0] non-finite, [1] scan total, [2] overflow, [8..] lv
+    int *hl = t->host + kHostLevels;    // pinned mirror of lv
+    const uint64_t *keys = ptr<uint64_t>(t->keys[t->sorted]);
+    const int nc_ = P->n_crit > 0 ? P->n_crit : 1;
+    int64_t cap64 = (nc_ >= 2 ? 8 * (int64_t)n / nc_ : 4 * (int64_t)n) + 64 * (int64_t)nbox + 1024;
+    if (t->ncell > 0) cap64 = cap64 > (int64_t)t->ncell * 5 / 4 + 1024 ? cap64 : (int64_t)t->ncell * 5 / 4 + 1024;
+    int launched = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (cap64 > 0x7fffffff || attempt > 3) return set_error(FMM_ERR_NOMEM, "octree does not fit");
+        const int cap = (int)cap64;
+        if ((rc = grow(t->cells, sizeof(Cell) * (size_t)cap) | grow(t->nch, (size_t)cap * 2 * sizeof(int) + 64)))
+            return rc;
+        int *nch = ptr<int>(t->nch), *off = nch + cap;
+        k_roots<<<blocks(nbox, 64), 64, 0, st>>>(ptr<Cell>(t->cells), nbox, ptr<int>(t->boxoff));
+        k_level_init<<<1, 64, 0, st>>>(lv, nbox, ovf);
+        hl[0] = 0;
+        hl[1] = nbox;
+        int64_t bound = nbox;  // the cells of level l are at most 8^l nbox (and cap)
+        launched = 0;
+        for (int l = 0; l < kMaxLevel && n > 0; ++l) {
+            const int b = (int)bound, g = blocks(b, 256) < 4096 ? blocks(b, 256) : 4096;
+            k_count_children_dev<<<g, 256, 0, st>>>(ptr<Cell>(t->cells), lv, l, P->n_crit, keys, nch, ovf);
+            if ((rc = scan_exclusive_dn(nch, off, lv + l, lv + l + 1, b, bad + 1, st, t->scan_tmp))) return rc;
+            k_make_children_dev<<<g, 256, 0, st>>>(ptr<Cell>(t->cells), lv, l, P->n_crit, keys, off, cap, ovf);
+            k_level_end<<<1, 64, 0, st>>>(lv, l, bad + 1, cap, ovf);
+            if ((rc = hip_check(hipMemcpyAsync(hl + l + 2, lv + l + 2, sizeof(int), hipMemcpyDeviceToHost, st),
+                                "level size")) ||
+                (rc = hip_check(hipEventRecord(t->bev[l], st), "event")))
+                return rc;
+            launched = l + 1;
+            bound = bound * 8 < cap ? bound * 8 : cap;
+            if (l >= 1) {  // the previous level's result: is level l (launched already) empty?
+                if ((rc = hip_check(hipEventSynchronize(t->bev[l - 1]), "tree level"))) return rc;
+                if (hl[l + 1] == hl[l]) break;
+            }
+        }
+        if ((rc = hip_check(hipMemcpyAsync(t->host, bad, 3 * sizeof(int), hipMemcpyDeviceToHost, st), "tree flags")) ||
+            (rc = hip_check(hipStreamSynchronize(st), "tree")))
+            return rc;
+        if (t->host[0]) return set_error(FMM_ERR_NAN, "non-finite particle position");
+        if (!t->host[2]) break;
+        cap64 *= 4;  // a level did not fit: rebuild with more room
+    }
+    t->lvl_beg.assign(1, 0);
+    for (int l = 0; l <= launched && hl[l + 1] > hl[l]; ++l) t->lvl_beg.push_back(hl[l + 1]);
     t->nlevel = (int)t->lvl_beg.size() - 1;
     t->ncell = t->lvl_beg.back();
     if (n == 0) {

@@ -92,8 +92,8 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int *__restrict__ in, int *__restrict__ out, int n,
-                                                            int *__restrict__ tile_sum)
+__device__ __forceinline__ void scan_tile_body(const int *__restrict__ in, int *__restrict__ out, int n,
+                                               int *__restrict__ tile_sum)
 {
     __shared__ int lds[kScanThreads];
     const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
@@ -123,6 +123,41 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int *__restric
     if (threadIdx.x == kScanThreads - 1) tile_sum[blockIdx.x] = lds[threadIdx.x];
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int *__restrict__ in, int *__restrict__ out, int n,
+                                                            int *__restrict__ tile_sum)
+{
+    scan_tile_body(in, out, n, tile_sum);
+}
+
+// The same with n = *hi - *lo read on the device (grids sized for an upper bound of n);
+// tiles past n report an empty sum.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile_dn(const int *__restrict__ in, int *__restrict__ out,
+                                                               const int *__restrict__ lo, const int *__restrict__ hi,
+                                                               int *__restrict__ tile_sum)
+{
+    const int n = *hi - *lo;
+    if ((int64_t)blockIdx.x * kScanTile >= n) {
+        if (threadIdx.x == 0) tile_sum[blockIdx.x] = 0;
+        return;
+    }
+    scan_tile_body(in, out, n, tile_sum);
+}
+
+__global__ void k_scan_add_dn(int *__restrict__ out, const int *__restrict__ lo, const int *__restrict__ hi,
+                              const int *__restrict__ tile_off)
+{
+    const int n = *hi - *lo;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_off[i / kScanTile];
+}
+
+__global__ void k_scan_total_dn(const int *__restrict__ in, const int *__restrict__ out, const int *__restrict__ lo,
+                                const int *__restrict__ hi, int *__restrict__ total)
+{
+    const int n = *hi - *lo;
+    *total = n > 0 ? out[n - 1] + in[n - 1] : 0;
+}
+
 __global__ void k_scan_add(int *__restrict__ out, int n, const int *__restrict__ tile_off)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,6 +180,29 @@ static int scan_rec(const int *in, int *out, int n, hipStream_t st, int *tmp)
         k_scan_add<<<(n + 255) / 256, 256, 0, st>>>(out, n, offs);
     }
     return 0;
+}
+
+static size_t scan_tmp_ints(int n)
+{
+    size_t need = 4;
+    for (int m = n; m > 1; m = (m + kScanTile - 1) / kScanTile) need += 2 * ((m + kScanTile - 1) / kScanTile);
+    return need;
+}
+
+int scan_exclusive_dn(const int *in, int *out, const int *lo, const int *hi, int n_max, int *total, hipStream_t st,
+                      DevBuf &tmp)
+{
+    if (n_max <= 0) return 0;
+    if (int rc = grow(tmp, scan_tmp_ints(n_max) * sizeof(int))) return rc;
+    const int nt = (n_max + kScanTile - 1) / kScanTile;
+    int *sums = static_cast<int *>(tmp.p), *offs = sums + nt;
+    k_scan_tile_dn<<<nt, kScanThreads, 0, st>>>(in, out, lo, hi, sums);
+    if (nt > 1) {
+        if (int rc = scan_rec(sums, offs, nt, st, sums + 2 * nt)) return rc;
+        k_scan_add_dn<<<(n_max + 255) / 256, 256, 0, st>>>(out, lo, hi, offs);
+    }
+    if (total) k_scan_total_dn<<<1, 1, 0, st>>>(in, out, lo, hi, total);
+    return hip_check(hipGetLastError(), "scan");
 }
 
 int scan_exclusive(const int *in, int *out, int n, int *total, hipStream_t st, DevBuf &tmp)

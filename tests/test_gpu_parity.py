@@ -199,3 +199,24 @@ def test_tree_reuse_shrink_and_grow():
         ref = oracle.fmm(pos, m, opar(prm)).acc
         assert rel_err(got, ref).max() < 1e-9
     t.free()
+
+
+def test_deep_chains_outgrow_the_first_cell_estimate():
+    """1000 pairs of particles 2e-6 apart with leaves of one particle: each pair hangs
+    from a chain of single-child cells down to about level 19, about 11 cells per
+    particle, more than the build's first room (4 n + 1088 cells for n_crit = 1).  The
+    build must detect the overflow, rebuild with more room, and match the oracle's tree
+    and lists."""
+    rng = inputs.rng_for(130)
+    c = rng.uniform(0.0, 1.0, (1000, 3))
+    d = rng.normal(size=(1000, 3))
+    d *= 1e-6 / np.linalg.norm(d, axis=1, keepdims=True)
+    pos = np.mod(np.concatenate([c + d, c - d]), 1.0)
+    m = np.full(len(pos), 1.0 / len(pos))
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.5, p=2, n_crit=1)
+    got, ref, e = check_fp64(pos, m, prm)
+    t = hf.Tree().build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+    st = t.stats()
+    t.free()
+    assert st["n_cells"] > 4 * len(pos) + 1088
+    assert st["max_level"] >= 18
