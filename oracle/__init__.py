@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 
 class Params(C.Structure):
     _fields_ = [("box", C.c_double), ("rs", C.c_double), ("rcut", C.c_double), ("theta", C.c_double),
-                ("G", C.c_double), ("p", C.c_int), ("ncrit", C.c_int), ("mac_mode", C.c_int)]
+                ("G", C.c_double), ("p", C.c_int), ("ncrit", C.c_int), ("mac_mode", C.c_int), ("split", C.c_int)]
 
 
 STAT_NAMES = ["ncell", "nleaf", "maxlevel", "n_m2l", "n_p2p", "p2p_pairs", "p2p_incut", "n_prune",
@@ -55,16 +55,18 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         L.orc_ncoef.argtypes = [C.c_int]; L.orc_ncoef.restype = C.c_int
         L.orc_multi_indices.argtypes = [C.c_int, _ip]
-        for nm in ("orc_prefactors_closed", "orc_prefactors_recur"):
+        for nm in ("orc_prefactors_closed", "orc_prefactors_recur", "orc_prefactors_poly"):
             getattr(L, nm).argtypes = [C.c_int, C.c_double, C.c_double, _dp]
         L.orc_prefactors_newton.argtypes = [C.c_int, C.c_double, _dp]
         L.orc_dtensor.argtypes = [C.c_int, _dp, C.c_double, _dp]
+        L.orc_dtensor_split.argtypes = [C.c_int, _dp, C.c_double, C.c_double, C.c_int, _dp]
         L.orc_p2m.argtypes = [C.c_int, C.c_long, _dp, _dp, _dp, _dp]
         L.orc_m2m.argtypes = [C.c_int, _dp, _dp, _dp]
         L.orc_m2l.argtypes = [C.c_int, _dp, _dp, C.c_double, _dp]
         L.orc_l2l.argtypes = [C.c_int, _dp, _dp, _dp]
         L.orc_l2p.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
         L.orc_f1.argtypes = [C.c_double, C.c_double]; L.orc_f1.restype = C.c_double
+        L.orc_f1_poly.argtypes = [C.c_double, C.c_double]; L.orc_f1_poly.restype = C.c_double
         L.orc_fmm.argtypes = [C.POINTER(Params), C.c_long, _dp, _dp, C.c_long, C.c_void_p, _dp, C.c_int]
         L.orc_fmm.restype = C.c_void_p
         L.orc_free.argtypes = [C.c_void_p]
@@ -82,8 +84,10 @@ def lib():
     return _lib
 
 
-def make_params(box=1.0, rs=0.0390625, rcut=0.17578125, theta=0.5, G=1.0, p=4, ncrit=32, mac_mode=0):
-    return Params(float(box), float(rs), float(rcut), float(theta), float(G), int(p), int(ncrit), int(mac_mode))
+def make_params(box=1.0, rs=0.0390625, rcut=0.17578125, theta=0.5, G=1.0, p=4, ncrit=32, mac_mode=0, split=0):
+    """split 0: Gaussian (erfc) split of Sec. 2.2 (r_s); 1: polynomial split (r_cut alone)."""
+    return Params(float(box), float(rs), float(rcut), float(theta), float(G), int(p), int(ncrit), int(mac_mode),
+                  int(split))
 
 
 def ncoef(p):
@@ -96,11 +100,14 @@ def multi_indices(p):
     return out
 
 
-def prefactors(p, r, rs, method="recur"):
+def prefactors(p, r, rs, method="recur", rc=None):
     """f_(0..p)(r) of Sec. 2.2; method: 'recur' (corrected recurrence), 'closed'
-    (general closed form), 'newton' (Eq. (4), rs ignored)."""
+    (general closed form), 'newton' (Eq. (4), rs ignored), 'poly' (polynomial split with
+    cutoff rc, rs ignored)."""
     f = np.zeros(p + 1)
-    if method == "recur":
+    if method == "poly":
+        lib().orc_prefactors_poly(int(p), float(r), float(rc), f)
+    elif method == "recur":
         lib().orc_prefactors_recur(int(p), float(r), float(rs), f)
     elif method == "closed":
         lib().orc_prefactors_closed(int(p), float(r), float(rs), f)
@@ -109,10 +116,10 @@ def prefactors(p, r, rs, method="recur"):
     return f
 
 
-def dtensor(p, R, rs):
-    """D_n(R) for |n| <= p; rs <= 0 gives the Newtonian kernel."""
+def dtensor(p, R, rs, split=0, rc=0.0):
+    """D_n(R) for |n| <= p; rs <= 0 gives the Newtonian kernel, split 1 the polynomial split."""
     D = np.zeros(ncoef(p))
-    lib().orc_dtensor(int(p), np.ascontiguousarray(R, np.float64), float(rs), D)
+    lib().orc_dtensor_split(int(p), np.ascontiguousarray(R, np.float64), float(rs), float(rc), int(split), D)
     return D
 
 
@@ -150,6 +157,10 @@ def l2p(p, L, y):
 
 def f1(r, rs):
     return lib().orc_f1(float(r), float(rs))
+
+
+def f1_poly(r, rc):
+    return lib().orc_f1_poly(float(r), float(rc))
 
 
 class FMMResult:

@@ -138,6 +138,36 @@ void orc_prefactors_recur(int p, double r, double rs, double *f)
     }
 }
 
+/* Polynomial split (the alternative truncation function of Sec. 5): with x = r / r_cut,
+ *   phi_s(r) = g(x) / r,  g(x) = 1 - 15/8 x + 5/4 x^3 - 3/8 x^5  (x < 1),  0 beyond.
+ * Reading: the paper names no polynomial; this one is the lowest-degree g whose
+ * complement (1 - g)/r holds only even powers of r (a smooth long range) and that
+ * vanishes with its first two derivatives at r_cut.  Then
+ *   phi_s = 1/r + sum_m c_m r^(2m) / r_cut^(2m+1),  c = (-15/8, 5/4, -3/8),
+ * and the same operator gives the prefactors in closed form:
+ *   f_(p) = (-1)^p (2p-1)!!/r^(2p+1) + sum_{m >= p} c_m 2^p m!/(m-p)! r^(2m-2p) / r_cut^(2m+1)
+ * (valid for r < r_cut, where every expansion of the method is used). */
+static const double kPolyC[3] = {-15.0 / 8.0, 5.0 / 4.0, -3.0 / 8.0};
+
+void orc_prefactors_poly(int p, double r, double rc, double *f)
+{
+    for (int k = 0; k <= p; ++k) {
+        double s = ((k & 1) ? -1.0 : 1.0) * dfact_odd(2 * k - 1) / ipow(r, 2 * k + 1);
+        for (int m = k; m < 3; ++m) {
+            double fall = 1.0; /* m! / (m-k)! */
+            for (int i = 0; i < k; ++i) fall *= (double)(m - i);
+            s += kPolyC[m] * ldexp(fall, k) * ipow(r, 2 * m - 2 * k) / ipow(rc, 2 * m + 1);
+        }
+        f[k] = s;
+    }
+}
+
+/* Force factor of the polynomial split: f_(1) = -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5). */
+double orc_f1_poly(double r, double rc)
+{
+    return -1.0 / (r * r * r) + 2.5 / (rc * rc * rc) - 1.5 * r * r / (rc * rc * rc * rc * rc);
+}
+
 /* Newtonian prefactor, Sec. 2.1 Eq. (4): (-1)^n (2n-1)!!/r^(2n+1). */
 void orc_prefactors_newton(int p, double r, double *f)
 {
@@ -149,12 +179,13 @@ void orc_prefactors_newton(int p, double r, double *f)
  * psi(r) = F(r^2/2) one has F^(k) = f_(k), and the n-th derivative is
  *   D_n = sum_{k <= n/2} f_(|n|-|k|) prod_i n_i! / (2^k_i k_i! (n_i-2k_i)!) R_i^(n_i-2k_i).
  * rs <= 0 selects the Newtonian kernel 1/r (Eq. (4)). */
-void orc_dtensor(int p, const double R[3], double rs, double *D)
+void orc_dtensor_split(int p, const double R[3], double rs, double rc, int split, double *D)
 {
     init_tables();
     double r = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
     double f[ORC_PMAX + 1];
-    if (rs > 0) orc_prefactors_recur(p, r, rs, f);
+    if (split == 1) orc_prefactors_poly(p, r, rc, f);
+    else if (rs > 0) orc_prefactors_recur(p, r, rs, f);
     else orc_prefactors_newton(p, r, f);
     for (int k = 0; k < orc_ncoef(p); ++k) {
         const int *n = g_mi[k];
@@ -209,12 +240,14 @@ void orc_m2m(int p, const double *Mold, const double x[3], double *Mnew)
     }
 }
 
+void orc_dtensor(int p, const double R[3], double rs, double *D) { orc_dtensor_split(p, R, rs, 0.0, 0, D); }
+
 /* Eq. (3): L_n(z_sink) += sum_{|m| <= p-|n|} M_m(z_src) D_{n+m}(z_sink - z_src) */
-void orc_m2l(int p, const double *M, const double R[3], double rs, double *L)
+void orc_m2l_split(int p, const double *M, const double R[3], double rs, double rc, int split, double *L)
 {
     init_tables();
     double D[ORC_NCOEF_MAX];
-    orc_dtensor(p, R, rs, D);
+    orc_dtensor_split(p, R, rs, rc, split, D);
     for (int k = 0; k < orc_ncoef(p); ++k) {
         const int *n = g_mi[k];
         int dn = n[0] + n[1] + n[2];
@@ -225,6 +258,11 @@ void orc_m2l(int p, const double *M, const double R[3], double rs, double *L)
         }
         L[k] += s;
     }
+}
+
+void orc_m2l(int p, const double *M, const double R[3], double rs, double *L)
+{
+    orc_m2l_split(p, M, R, rs, 0.0, 0, L);
 }
 
 /* Eq. (5): L_n(z + x) += sum_{|m| <= p-|n|} x^m / m! L_{m+n}(z)   (x = new centre - old centre) */
@@ -283,7 +321,15 @@ typedef struct {
     double box, rs, rcut, theta, G;
     int p, ncrit, mac_mode; /* bit 0: literal item 3 (S_c); bit 1: source-only size in item 2;
                                bit 2: conventional MAC (item 2 alone) */
+    int split;              /* 0: Gaussian (erfc) split of Sec. 2.2; 1: polynomial split */
 } orc_params;
+
+/* pair force factor f_(1)(r) of the split in use */
+static double f1_of(const orc_params *P, double r)
+{
+    if (P->split == 1) return r < P->rcut ? orc_f1_poly(r, P->rcut) : 0.0; /* compact support */
+    return orc_f1(r, P->rs);
+}
 
 typedef struct {
     int level, ix, iy, iz;   /* cube [i h, (i+1) h) per axis, h = box / 2^level */
@@ -526,7 +572,7 @@ static int cmp_pair(const void *x, const void *y)
 static void p2p_leaf_pair(const orc_state *S, int A, int B, int s, double *acc, long *npairs, long *nin)
 {
     int sh[3]; image_of(s, sh);
-    double L = S->P.box, rc2 = S->P.rcut * S->P.rcut, rs = S->P.rs;
+    double L = S->P.box, rc2 = S->P.rcut * S->P.rcut;
     const ocell *a = &S->cell[A], *b = &S->cell[B];
     for (long i = a->beg; i < a->end; ++i) {
         double ax = 0, ay = 0, az = 0;
@@ -538,7 +584,7 @@ static void p2p_leaf_pair(const orc_state *S, int A, int B, int s, double *acc, 
             (*npairs)++;
             if (!(r2 > 0.0 && r2 < rc2)) continue;
             (*nin)++;
-            double w = S->m[j] * orc_f1(sqrt(r2), rs);
+            double w = S->m[j] * f1_of(&S->P, sqrt(r2));
             ax += w * dx; ay += w * dy; az += w * dz;
         }
         acc[3 * i] += ax; acc[3 * i + 1] += ay; acc[3 * i + 2] += az;
@@ -561,7 +607,9 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
               const long *targets, double *acc, int nthreads)
 {
     init_tables();
-    if (P->p < 0 || P->p > ORC_PMAX || P->ncrit < 1 || !(P->theta > 0) || !(P->rcut < 0.5 * P->box)) return NULL;
+    if (P->p < 0 || P->p > ORC_PMAX || P->ncrit < 1 || !(P->theta > 0) || !(P->rcut < 0.5 * P->box) ||
+        P->split < 0 || P->split > 1)
+        return NULL;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -651,7 +699,7 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
                 double zb[3]; cell_centre(S, B, zb);
                 double R[3] = {za[0] - (zb[0] + sh[0] * P->box), za[1] - (zb[1] + sh[1] * P->box),
                                za[2] - (zb[2] + sh[2] * P->box)};
-                orc_m2l(P->p, S->M + (size_t)B * np, R, P->rs, S->L + (size_t)c * np);
+                orc_m2l_split(P->p, S->M + (size_t)B * np, R, P->rs, P->rcut, P->split, S->L + (size_t)c * np);
             }
         }
         free(start);
@@ -775,7 +823,7 @@ void orc_copy_cells(const void *h, int64_t *out /* ncell x 5 */, long *orig /* n
 int orc_bruteforce(const orc_params *P, double rc, long n, const double *pos, const double *mass, long ntarget,
                    const long *targets, double *acc_out /* ntarget x 3 */, int nthreads)
 {
-    if (!(rc < 0.5 * P->box) || !(rc > 0)) return -1;
+    if (!(rc < 0.5 * P->box) || !(rc > 0) || P->split < 0 || P->split > 1) return -1;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
@@ -833,7 +881,7 @@ int orc_bruteforce(const orc_params *P, double rc, long n, const double *pos, co
                         }
                         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                         if (!(r2 > 0.0 && r2 < rc2)) continue;
-                        double w = mass[j] * orc_f1(sqrt(r2), P->rs);
+                        double w = mass[j] * f1_of(P, sqrt(r2));
                         ax += w * d[0]; ay += w * d[1]; az += w * d[2];
                     }
                 }

@@ -25,7 +25,25 @@ def _cic(pos, box, M):
     return i0, w1
 
 
-def pm_forces(pos, mass, box, rs, M, G=1.0):
+def long_range_window(k, rs=None, split=0, rcut=None):
+    """Fourier factor of the long-range Green function: exp(-k^2 r_s^2) for the Gaussian
+    split; for the polynomial split the transform of its smoothing density
+    15/(8 pi r_c^3) (1 - r^2/r_c^2) (r < r_c), 15 (3 sin u - 3 u cos u - u^2 sin u)/u^5
+    with u = k r_c (a series below u = 0.1)."""
+    k = np.asarray(k, np.float64)
+    if split == 0:
+        return np.exp(-k * k * rs * rs)
+    u = k * rcut
+    out = np.empty_like(u)
+    small = u < 0.1
+    us = u[small]
+    out[small] = 1.0 - us ** 2 / 14.0 + us ** 4 / 504.0 - us ** 6 / 33264.0
+    ul = u[~small]
+    out[~small] = 15.0 * (3 * np.sin(ul) - 3 * ul * np.cos(ul) - ul ** 2 * np.sin(ul)) / ul ** 5
+    return out
+
+
+def pm_forces(pos, mass, box, rs, M, G=1.0, split=0, rcut=None):
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
     i0, w1 = _cic(pos, box, M)
     d = box / M
@@ -47,7 +65,7 @@ def pm_forces(pos, mass, box, rs, M, G=1.0):
         nyq |= (np.abs(nx_i) == M // 2)[:, :, None] | (np.abs(ny_i) == M // 2)[:, :, None]
         nyq[:, :, M // 2] = True
     with np.errstate(divide="ignore", invalid="ignore"):
-        phi = -4 * np.pi * G * np.exp(-k2 * rs * rs) / (k2 * W * W)
+        phi = -4 * np.pi * G * long_range_window(np.sqrt(k2), rs, split, rcut) / (k2 * W * W)
     phi[0, 0, 0] = 0.0
     phi[nyq] = 0.0
     out = np.zeros_like(pos)

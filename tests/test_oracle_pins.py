@@ -401,3 +401,79 @@ def test_uniform_m2l_vanishes_only_with_the_truncated_mac():
     assert cv["n_m2l"] > 1000
     assert cv["nleaf"] == 16 ** 3 and cv["maxlevel"] == 4
     assert cv["n_p2p"] == 27 * cv["nleaf"]
+
+
+# ---- polynomial split (the alternative truncation function of Sec. 5) ------------------
+
+def _poly_g_symbolic():
+    """g(x) = 1 - x h(x^2) of lowest degree with g(1) = g'(1) = g''(1) = 0, solved by sympy
+    from those conditions (so the coefficients are not retyped)."""
+    x, a0, a1, a2 = sp.symbols("x a0 a1 a2")
+    g = 1 - x * (a0 + a1 * x ** 2 + a2 * x ** 4)
+    sol = sp.solve([g.subs(x, 1), sp.diff(g, x).subs(x, 1), sp.diff(g, x, 2).subs(x, 1)], [a0, a1, a2])
+    return x, g.subs(sol)
+
+
+def test_poly_split_prefactors_match_symbolic_derivatives():
+    x, g = _poly_g_symbolic()
+    r, rc = sp.symbols("r rc", positive=True)
+    f = g.subs(x, r / rc) / r
+    for rv, rcv in [("1/10", "1"), ("1/2", "1"), ("9/10", "1"), ("3/100", "1/20"), ("7/5", "2")]:
+        got = oracle.prefactors(8, float(sp.Rational(rv)), 0.0, "poly", rc=float(sp.Rational(rcv)))
+        e = f
+        for k in range(9):
+            ref = float(sp.N(e.subs({r: sp.Rational(rv), rc: sp.Rational(rcv)}), 40))
+            assert abs(got[k] - ref) <= 1e-11 * max(abs(ref), 1e-300), (k, rv, got[k], ref)
+            e = sp.diff(e, r) / r
+
+
+def test_poly_split_vanishes_smoothly_and_long_range_is_regular():
+    """phi_s and its force vanish at r_cut; the long range (1 - g)/r is even in r (finite,
+    with zero slope, at r = 0)."""
+    x, g = _poly_g_symbolic()
+    assert sp.simplify(g.subs(x, 1)) == 0 and sp.simplify(sp.diff(g, x).subs(x, 1)) == 0
+    lr = sp.expand((1 - g) / x)
+    assert all(int(t.as_poly(x).degree()) % 2 == 0 for t in lr.as_ordered_terms())
+    rc = 0.3
+    for r in (rc * (1 - 1e-7),):
+        f = oracle.prefactors(1, r, 0.0, "poly", rc=rc)
+        assert abs(f[0]) * r < 1e-12 and abs(oracle.f1_poly(r, rc)) * r ** 3 < 1e-12
+    np.testing.assert_allclose(oracle.f1_poly(0.1, rc), oracle.prefactors(1, 0.1, 0.0, "poly", rc=rc)[1], rtol=1e-14)
+
+
+def test_poly_split_dtensor_matches_symbolic_gradient():
+    xs, g = _poly_g_symbolic()
+    X, Y, Z = sp.symbols("X Y Z", real=True)
+    rc = sp.Rational(3, 2)
+    rr = sp.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    psi = g.subs(xs, rr / rc) / rr
+    R = (sp.Rational(3, 10), sp.Rational(-7, 10), sp.Rational(1, 2))
+    p = 5
+    D = oracle.dtensor(p, np.array([float(v) for v in R]), 0.0, split=1, rc=float(rc))
+    mi = oracle.multi_indices(p)
+    for k in [0, 1, 2, 3, 4, 5, 9, 13, 19, 24, 34, 40, 55]:
+        n = mi[k]
+        e = psi
+        for var, cnt in zip((X, Y, Z), n):
+            if cnt:
+                e = sp.diff(e, var, int(cnt))
+        ref = float(sp.N(e.subs({X: R[0], Y: R[1], Z: R[2]}), 30))
+        assert abs(D[k] - ref) <= 1e-11 * max(1.0, abs(ref)), (tuple(n), D[k], ref)
+
+
+def test_poly_split_fmm_tiny_theta_equals_bruteforce_and_error_falls_with_order():
+    rng = np.random.default_rng(44)
+    pos, m = inputs.clustered(3000, 4, rng)
+    P = oracle.make_params(rs=0.0, rcut=0.09, theta=1e-3, p=2, ncrit=8, split=1)
+    res = oracle.fmm(pos, m, P)
+    assert res.stats["n_m2l"] == 0
+    bf = oracle.bruteforce(pos, m, P)
+    np.testing.assert_allclose(res.acc, bf, rtol=1e-10, atol=1e-12 * np.abs(bf).max())
+    pos, m = inputs.clustered(20000, 12, np.random.default_rng(45))
+    bf = oracle.bruteforce(pos, m, oracle.make_params(rs=0.0, rcut=0.045, split=1))
+    e = []
+    for p in (2, 4, 6):
+        res = oracle.fmm(pos, m, oracle.make_params(rs=0.0, rcut=0.045, theta=0.5, p=p, ncrit=16, split=1))
+        assert res.stats["n_m2l"] > 0
+        e.append(np.percentile(_rel_err(res.acc, bf), 99))
+    assert e[0] > e[1] > e[2]
