@@ -22,11 +22,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "short-range particles/s at p99 rel force err ≤1e-3; learned/FP32 vs plain"
 PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12}
-P2P_FLOP_PER_PAIR = 38.0
+# algorithmic flop per evaluated P2P pair: the Gaussian split's counting convention (3 sub,
+# 3 FMA for r^2, rsqrt, exp, rcp counted 1 each, ~8 erfc approximation, 4 combine, 3 FMA
+# accumulate); the polynomial split's factored force law (3 sub, 3 FMA for r^2, rsqrt, 2 mul
+# for x = r / r_cut, 1 - x, 3 FMA for the cubic, 4 mul to combine, 1 mul for the mass,
+# 3 FMA accumulate)
+P2P_FLOP_PER_PAIR = {0: 38.0, 1: 30.0}
 
-# Largest opening angle of the grid {0.5, 0.45, 0.4, 0.35, 0.3} whose p99 error against
-# brute force is <= 1e-3 at the configured order (measured with the oracle on the
-# clustered workload: theta 0.5 -> 2.5e-3, 0.45 -> 1.9e-3, 0.4 -> 2.6e-4).
+# Opening angles: the largest whose p99 error against brute force is <= 1e-3 at the
+# configured order (clustered workload: theta 0.5 -> 2.5e-3, 0.45 -> 1.9e-3, 0.44 and
+# 0.42 -> 8.5e-4 (the integer MAC geometry accepts the same pairs), 0.4 -> 2.7e-4).
 # Batched: theta 0.6 -> p99 2.8e-2 .. 4.2e-2 on sampled boxes, 0.4 -> 6.6e-4 .. 9.6e-4 at p = 5.
 # Large (16.7M clustered, order 8): theta 0.5 meets the bar at p = 8 (p99 7e-4 on the
 # clustered mix).  Full (134M, lattice + clumps): the whole hybrid step, PM on a 512^3
@@ -51,6 +56,8 @@ def main():
     ap.add_argument("--n-crit", type=int, default=None)
     ap.add_argument("--autotune", type=int, default=None, choices=(0, 1),
                     help="1: choose n_crit with the library's autotuner before timing (default: batched only)")
+    ap.add_argument("--split", type=int, default=0, choices=(0, 1),
+                    help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
                     help="1: per-pair acceptance and order from the trained selector (packaged model file)")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -96,7 +103,7 @@ def main():
         pos_np, m_np = inputs.make(args.workload)
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                    precision=wl["precision"], learned=int(wl["learned"]))
+                    precision=wl["precision"], learned=int(wl["learned"]), split=args.split)
     sel = None
     if wl["learned"]:
         from paper_2006_14952_amd import learned
@@ -146,7 +153,7 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     st = tree.stats()
 
-    flop_launch = P2P_FLOP_PER_PAIR * st["p2p_evaluated"]  # pairs the kernel evaluates
+    flop_launch = P2P_FLOP_PER_PAIR[args.split] * st["p2p_evaluated"]  # pairs the kernel evaluates
     p2p_s = float(np.mean(p2p_ms)) * 1e-3
     peak = PEAK["fp32_vector"] if wl["precision"] else PEAK["fp64_vector"]
     achieved = flop_launch / p2p_s
@@ -154,8 +161,9 @@ def main():
     tf = os.path.join(ROOT, "profiles", "p2p_traffic_%s_fp%d.json" % (args.workload, 32 if wl["precision"] else 64))
     if os.path.exists(tf):  # counters taken on this workload with the same parameters, else not reported
         rec = json.load(open(tf))
-        same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
-                                                 ("n_crit", wl["n_crit"]), ("learned", bool(wl["learned"]))))
+        same = all(rec.get(k, 0 if k == "split" else None) == v
+                   for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]), ("n_crit", wl["n_crit"]),
+                                ("learned", bool(wl["learned"])), ("split", args.split)))
         if same:
             traffic = rec.get("bytes_per_launch")
 
@@ -177,8 +185,10 @@ def main():
             pr["p"], wl["theta"], wl["n_crit"], pr["rs"], pr["rcut"],
             "FP32 P2P/M2L + FP64 positions/offsets/final sum" if wl["precision"] else "FP64")
             + (", " + sel + " in place of p and theta" if sel else "")
+            + (", polynomial split" if args.split else "")
             + (", full hybrid step: PM on %d^3 mesh + short range" % mesh if hybrid else ""),
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
+            "split": args.split,
             "selector": sel or "fixed p and theta", "autotuned_n_crit_ms": tuned},
         "roofline": {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
@@ -209,7 +219,7 @@ def main():
         tg = inputs.rng_for(CONFIG_SAMPLE_SEED).choice(len(bp), min(max(cpu_sample, args.accuracy_sample), len(bp)),
                                                        replace=False)
         op = oracle.make_params(box=1.0, rs=pr["rs"], rcut=pr["rcut"], theta=wl["theta"], p=pr["p"],
-                                ncrit=wl["n_crit"])
+                                ncrit=wl["n_crit"], split=args.split)
         bf = oracle.bruteforce(bp, bm, op, targets=tg)
         ref_norm = np.linalg.norm(bf, axis=1)
         floor = np.median(ref_norm[ref_norm > 0])

@@ -60,14 +60,20 @@ extern "C" {
  *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
  *             compensated per-particle sums, FP64 positions, cell offsets and final sum
  *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see
- *             fmm_load_mac_model), the plain MAC's hard rules still apply */
+ *             fmm_load_mac_model), the plain MAC's hard rules still apply
+ *   split     0: the Gaussian (erfc) split of Sec. 2.2 with scale r_s, hard cut at r_cut;
+ *             1: the polynomial split (the alternative truncation function Sec. 5 allows):
+ *             phi_s = g(r/r_cut)/r, g(x) = 1 - 15/8 x + 5/4 x^3 - 3/8 x^5 below r_cut and 0
+ *             beyond (r_s unused by the short range); PM filters with the transform of
+ *             its smoothing density.  The learned selector requires split 0. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
     int mac_mode;
     int precision;
     int learned;
-    int reserved[3];
+    int split;
+    int reserved[2];
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts

@@ -36,6 +36,8 @@ static int check_params(const fmm_params *P)
     if (P->mac_mode < 0 || P->mac_mode > 7) return set_error(FMM_ERR_ARG, "mac_mode must be in [0, 7]");
     if (P->precision != 0 && P->precision != 1) return set_error(FMM_ERR_ARG, "precision must be 0 or 1");
     if (P->learned != 0 && P->learned != 1) return set_error(FMM_ERR_ARG, "learned must be 0 or 1");
+    if (P->split != 0 && P->split != 1) return set_error(FMM_ERR_ARG, "split must be 0 or 1");
+    if (P->learned && P->split) return set_error(FMM_ERR_ARG, "the learned selector requires split 0");
     return 0;
 }
 
@@ -145,7 +147,8 @@ static int copy_kind(fmm_tree *t, int kind, uint64_t *out, int64_t cap, int64_t 
 static bool same_params(const fmm_params &a, const fmm_params &b)
 {
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
-           a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned;
+           a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
+           a.split == b.split;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,

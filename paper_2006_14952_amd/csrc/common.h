@@ -54,8 +54,16 @@ constexpr int kChunk = 64;
 // Per-call constants of the P2P force law in FP32: f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),
 // t = 2 r^2 / r_cut^2 - 1, S a degree-10 polynomial fitted on the host.
 constexpr int kP2PPoly = 11;
+// The short range's truncation function: kind 0 the Gaussian split (scale = r_s), kind 1
+// the polynomial split g(r/r_cut)/r (scale = r_cut).
+struct Split {
+    double scale;
+    int kind;
+};
+
 struct P2PConst {
     float c[kP2PPoly];  // S(t) / (8 r_s^3), coefficients of t^0 .. t^(kP2PPoly-1)
+    int split;          // 0: Gaussian split; 1: polynomial split (c[0] = 1 / r_cut, see p2p_setup)
     float two_over_rc2;
     float rc2;
     double rs, rc2d;

@@ -136,9 +136,26 @@ __device__ __forceinline__ double d_exp(double x) { return exp(x); }
 __device__ __forceinline__ float d_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double d_sqrt(double x) { return sqrt(x); }
 
-// Truncated prefactors f_(0..P) at squared distance r2 with split scale rs (any units).
-template <int P, class T> __device__ __forceinline__ void prefactors(T r2, T rs, T *f)
+// Truncated prefactors f_(0..P) at squared distance r2, a = the split's scale (any units,
+// the same as r2's).  Polynomial split, phi_s = 1/r + sum_m c_m r^(2m)/a^(2m+1) with
+// c = (-15/8, 5/4, -3/8): f_(k) = (-1)^k (2k-1)!!/r^(2k+1) + the k-fold (r^-1 d/dr) of the
+// polynomial, which ends at k = 2.
+template <int P, class T> __device__ __forceinline__ void prefactors(T r2, T rs, int kind, T *f)
 {
+    if (kind == 1) {
+        const T r = d_sqrt(r2), inv_r2 = (T)1 / r2, ia = (T)1 / rs, ia2 = ia * ia;
+        T nk = (T)1 / r;
+        f[0] = nk + ia * ((T)(-15.0 / 8.0) + r2 * ia2 * ((T)1.25 - (T)0.375 * r2 * ia2));
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+            nk = -(T)(2 * k - 1) * nk * inv_r2;
+            T pk = 0;
+            if (k == 1) pk = ia2 * ia * ((T)2.5 - (T)1.5 * r2 * ia2);
+            if (k == 2) pk = (T)(-3) * ia2 * ia2 * ia;
+            f[k] = nk + pk;
+        }
+        return;
+    }
     T r = d_sqrt(r2);
     T inv_r2 = (T)1 / r2;
     T e = d_exp(-r2 / ((T)4 * rs * rs));
@@ -254,7 +271,7 @@ template <int P, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 : 2))) void k_m2l(
     const Cell *__restrict__ cells, int ncell, const int *__restrict__ head, const int *__restrict__ cnt,
     const uint32_t *__restrict__ items, const int *__restrict__ next, const T *__restrict__ M, T *__restrict__ L,
-    double box, double rs, int stride, int accumulate, const unsigned char *__restrict__ ord)
+    double box, Split sp, int stride, int accumulate, const unsigned char *__restrict__ ord)
 {
     // M and L hold ncoef(order of storage) coefficients per cell (stride); this kernel
     // reads and writes the first ncoef(P) of them (multi-indices are ordered by degree).
@@ -271,7 +288,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 :
     if (nl > 0) {
         Cell ca = cells[A];
         int la = cell_level(ca);
-        T rsh = (T)(rs / cell_h(ca, box));
+        T rsh = (T)(sp.scale / cell_h(ca, box));
         int chunk = head[A], taken = 0;
         for (int e = 0; e < nl; ++e) {
             if (e > 0 && (e & (kChunk - 1)) == 0) chunk = next[chunk];
@@ -285,7 +302,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 1 :
             T Rx, Ry, Rz;
             pair_sep<T>(ca, cb, s, Rx, Ry, Rz);
             T f[P + 1], D[NC];
-            prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, rsh, f);
+            prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, rsh, sp.kind, f);
             dtensor<P, T>(Rx, Ry, Rz, f, D);
             T rho = (T)ldexp(1.0, la - lb);
             T rp[P + 1];
@@ -682,7 +699,7 @@ __device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, 
 template <int P, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : P >= 7 ? 2 : 3))) void k_m2l_pairs(
     const Cell *__restrict__ cells, const int2 *__restrict__ pairs, int64_t npair, const T *__restrict__ M,
-    T *__restrict__ L, double box, double rs, int stride)
+    T *__restrict__ L, double box, Split sp, int stride)
 {
     constexpr int NC = ncoef(P), NHB = m2l_hi_begin<P>(), NMID = m2l_mid_rows<P>(), HC = m2l_hi_chunk<P>();
     constexpr int STR = (NMID > HC ? NMID : HC) | 1;  // odd row stride: no bank conflicts
@@ -712,7 +729,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         T Rx, Ry, Rz;
         pair_sep<T>(ca, cb, s, Rx, Ry, Rz);
         T f[P + 1];
-        prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, (T)(rs / cell_h(ca, box)), f);
+        prefactors<P, T>(Rx * Rx + Ry * Ry + Rz * Rz, (T)(sp.scale / cell_h(ca, box)), sp.kind, f);
         dtensor<P, T>(Rx, Ry, Rz, f, D);
         const T rho = (T)ldexp(1.0, cell_level(ca) - cell_level(cb));
         rp[0] = 1;
@@ -795,7 +812,7 @@ template <int P, class T> struct M2L {
     // Coefficient storage of order `pstore`.  learned == 0: the plain M2L list (kind 0);
     // learned != 0: the entries of order P of the learned selector's list, whose pairs
     // flatten_learned has already laid out by order (the pair kernel adds to L).
-    static int run(fmm_tree *t, double rs, int learned, int pstore, int accumulate, hipStream_t st)
+    static int run(fmm_tree *t, Split sp, int learned, int pstore, int accumulate, hipStream_t st)
     {
         const int kind = learned ? kKindOrd : 0;
         if constexpr (pair_m2l<P, T>()) {
@@ -807,13 +824,13 @@ template <int P, class T> struct M2L {
                 if (int rc = flatten_pairs(t, kind, np, st)) return rc;
             const int2 *pairs = ptr<int2>(t->m2l_pairs) + (learned ? t->lseg[P - 2] : 0);
             k_m2l_pairs<P, T><<<(unsigned)((np + 63) / 64), 64, 0, st>>>(ptr<Cell>(t->cells), pairs, np, ptr<T>(t->Mc),
-                                                                       ptr<T>(t->Lc), t->box, rs, ncoef(pstore));
+                                                                       ptr<T>(t->Lc), t->box, sp, ncoef(pstore));
             return hip_check(hipGetLastError(), "m2l pairs");
         }
         size_t off = (size_t)kind * t->ncell;
         k_m2l<P, T><<<nblk(t->ncell, 64), 64, 0, st>>>(
             ptr<Cell>(t->cells), t->ncell, ptr<int>(t->lhead) + off, ptr<int>(t->lcnt) + off,
-            ptr<uint32_t>(t->litems[kind]), ptr<int>(t->lnext[kind]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, rs,
+            ptr<uint32_t>(t->litems[kind]), ptr<int>(t->lnext[kind]), ptr<T>(t->Mc), ptr<T>(t->Lc), t->box, sp,
             ncoef(pstore), accumulate, learned ? ptr<unsigned char>(t->lord) : nullptr);
         return hip_check(hipGetLastError(), "m2l");
     }
@@ -845,9 +862,9 @@ template <int P, class T> struct L2P {
 };
 
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
-template <class T> int m2l_t(fmm_tree *t, int p, double rs, int learned, int pstore, int accumulate, hipStream_t st)
+template <class T> int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, hipStream_t st)
 {
-    return dispatch_p<M2L, T>(p, t, rs, learned, pstore, accumulate, st);
+    return dispatch_p<M2L, T>(p, t, sp, learned, pstore, accumulate, st);
 }
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
 template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st)

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(64) void k_labels(LabelArgs a)
             double inv2wa = 0.5 / g.wa;
             double Rx = g.R[0] * inv2wa, Ry = g.R[1] * inv2wa, Rz = g.R[2] * inv2wa;
             double fk[P + 1], D[NC], L[NC];
-            prefactors<P, double>(Rx * Rx + Ry * Ry + Rz * Rz, a.rs / hA, fk);
+            prefactors<P, double>(Rx * Rx + Ry * Ry + Rz * Rz, a.rs / hA, 0, fk);
             dtensor<P, double>(Rx, Ry, Rz, fk, D);
             const double rho = ldexp(1.0, la - lb);
             const double *Mb = a.M + (size_t)B * NC;

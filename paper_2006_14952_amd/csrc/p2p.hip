@@ -101,7 +101,10 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 
 constexpr int kStage = 192;
 
-template <bool F64>
+// POLY (FP32 form, polynomial split): f_(1) = -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5) evaluated
+// as -(1-x)^2 (1 + 2x + 3x^2 + 3x^3/2) / r^3, x = r / r_c: the three terms cancel near r_cut
+// in FP32, the factored form does not.
+template <bool F64, bool POLY>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6))) void k_p2p(P2PArgs a, P2PConst k)
 {
     using R = typename std::conditional<F64, double, float>::type;
@@ -261,6 +264,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                 if (valid) {
                     if constexpr (F64) {
                         const double rc2 = k.rc2d, inv2rs = 0.5 / k.rs, c1 = 1.0 / (k.rs * 1.7724538509055160273);
+                        const double irc2 = 1.0 / rc2, irc3 = irc2 / sqrt(rc2);
                         for (int q = g; q < nst; q += G) {
                             const double4 s = src[q];
                             double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
@@ -268,9 +272,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                             bool in = r2 > 0.0 && r2 < rc2;
                             double rr2 = in ? r2 : 1.0;
                             double r = sqrt(rr2);
-                            double u = r * inv2rs;
-                            double h = erfc(u) + r * c1 * exp(-u * u);
-                            double w = in ? -s.w * h / (rr2 * r) : 0.0;
+                            double w;
+                            if (k.split == 1) {  // -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5)
+                                w = in ? s.w * (-1.0 / (rr2 * r) + irc3 * (2.5 - 1.5 * rr2 * irc2)) : 0.0;
+                            } else {
+                                double u = r * inv2rs;
+                                double h = erfc(u) + r * c1 * exp(-u * u);
+                                w = in ? -s.w * h / (rr2 * r) : 0.0;
+                            }
                             ax += w * dx;
                             ay += w * dy;
                             az += w * dz;
@@ -287,11 +296,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                             // a particle meets itself (and exact duplicates) at d = 0: the clamp
                             // keeps w finite, so w d = 0 without a separate r > 0 test
                             const float rinv = __frsqrt_rn(fmaxf(r2, 1e-20f));
-                            const float t = fmaf(r2, k.two_over_rc2, -1.0f);
-                            float S = clead;  // S(t) / (8 r_s^3)
+                            float f1;
+                            if constexpr (POLY) {
+                                const float x = r2 * rinv * k.c[0], omx = 1.0f - x;
+                                const float q = fmaf(fmaf(fmaf(1.5f, x, 3.0f), x, 2.0f), x, 1.0f);
+                                f1 = -(omx * omx) * q * (rinv * rinv * rinv);
+                            } else {
+                                const float t = fmaf(r2, k.two_over_rc2, -1.0f);
+                                float S = clead;  // S(t) / (8 r_s^3)
 #pragma unroll
-                            for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
-                            const float f1 = fmaf(-rinv * rinv, rinv, S);
+                                for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
+                                f1 = fmaf(-rinv * rinv, rinv, S);
+                            }
                             const float w = r2 < k.rc2 ? s.w * f1 : 0.0f;
                             px = fmaf(w, dx, px);
                             py = fmaf(w, dy, py);
@@ -389,6 +405,11 @@ void p2p_setup(const fmm_params *P, P2PConst &k)
     // the kernel evaluates S(t) / (8 r_s^3): the factor is folded into the coefficients
     const double inv8rs3 = 1.0 / (8.0 * P->r_s * P->r_s * P->r_s);
     for (int j = 0; j < m; ++j) k.c[j] = (float)(Amat[j][m] / Amat[j][j] * inv8rs3);
+    k.split = P->split;
+    if (P->split == 1) {  // polynomial split: the FP32 kernel needs 1 / r_cut only
+        for (int j = 0; j < m; ++j) k.c[j] = 0.0f;
+        k.c[0] = (float)(1.0 / P->r_cut);
+    }
     k.two_over_rc2 = (float)(2.0 / (P->r_cut * P->r_cut));
     k.rc2 = (float)(P->r_cut * P->r_cut);
     k.rs = P->r_s;
@@ -433,8 +454,9 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
         if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
         a.bbox = ptr<float4>(t->bbox);
     }
-    if (P->precision) k_p2p<false><<<t->nleaf, 64, 0, st>>>(a, k);
-    else k_p2p<true><<<t->nleaf, 64, 0, st>>>(a, k);
+    if (P->precision && P->split == 1) k_p2p<false, true><<<t->nleaf, 64, 0, st>>>(a, k);
+    else if (P->precision) k_p2p<false, false><<<t->nleaf, 64, 0, st>>>(a, k);
+    else k_p2p<true, false><<<t->nleaf, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");
 }
 

@@ -5,7 +5,9 @@
 //   CIC deposit -> rho(x);  FFT;  phi_k = -4 pi G rho_k exp(-k^2 r_s^2) / (k^2 W(k)^2);
 //   a_k = -i k phi_k (three components);  inverse FFTs;  CIC interpolation.
 // W(k) = prod_i sinc^2(k_i Delta / 2) is the CIC window, divided out once for the
-// deposit and once for the interpolation.  The k = 0 mode is dropped (mean density is
+// deposit and once for the interpolation.  With the polynomial split the filter is the
+// transform of its smoothing density 15/(8 pi r_c^3)(1 - r^2/r_c^2) (r < r_c):
+// 15 (3 sin u - 3 u cos u - u^2 sin u) / u^5, u = k r_cut.  The k = 0 mode is dropped (mean density is
 // cancelled by the expanding background).  FFTs are hipFFT (double precision).
 #include <hipfft/hipfft.h>
 #include <math.h>
@@ -103,9 +105,20 @@ __global__ void k_cic_deposit(S src, int n, double box, int M, double inv_vol, d
 
 __device__ __forceinline__ double sinc(double x) { return fabs(x) < 1e-8 ? 1.0 : sin(x) / x; }
 
+// long-range filter at |k|^2 = k2: Gaussian split exp(-k^2 r_s^2); polynomial split the
+// transform above (its series below u = 0.1, where the closed form cancels)
+__device__ __forceinline__ double lr_window(double k2, double rs, int split, double rcut)
+{
+    if (split != 1) return exp(-k2 * rs * rs);
+    const double u = sqrt(k2) * rcut, u2 = u * u;
+    if (u < 0.1) return 1.0 - u2 / 14.0 + u2 * u2 / 504.0 - u2 * u2 * u2 / 33264.0;
+    const double s = sin(u), c = cos(u);
+    return 15.0 * (3.0 * s - 3.0 * u * c - u2 * s) / (u2 * u2 * u);
+}
+
 // a_k component `axis` from rho_k; includes the 1/M^3 of the inverse transform
 __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipfftDoubleComplex *__restrict__ out,
-                             int M, double box, double rs, double G, int axis)
+                             int M, double box, double rs, int split, double rcut, double G, int axis)
 {
     int Mh = M / 2 + 1;
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,7 +137,7 @@ __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipff
     }
     double W = sinc(0.5 * k0 * d) * sinc(0.5 * k1 * d) * sinc(0.5 * k2 * d);
     W = W * W;
-    double phi = -4.0 * M_PI * G * exp(-k2s * rs * rs) / (k2s * W * W);
+    double phi = -4.0 * M_PI * G * lr_window(k2s, rs, split, rcut) / (k2s * W * W);
     double ka = axis == 0 ? k0 : (axis == 1 ? k1 : k2);
     double s = phi * ka / ((double)M * M * M);  // a_k = -i k phi_k
     o.x = s * r.y;
@@ -196,7 +209,7 @@ static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos
     for (int axis = 0; axis < 3; ++axis) {
         k_green_grad<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(ptr<hipfftDoubleComplex>(pl->rhok),
                                                                   ptr<hipfftDoubleComplex>(pl->work), mesh, P->box,
-                                                                  P->r_s, P->G, axis);
+                                                                  P->r_s, P->split, P->r_cut, P->G, axis);
         if (hipfftExecZ2D(pl->c2r, ptr<hipfftDoubleComplex>(pl->work), ptr<double>(pl->amesh) + axis * nr) !=
             HIPFFT_SUCCESS)
             return set_error(FMM_ERR_HIP, "hipfftExecZ2D");

@@ -154,3 +154,25 @@ def test_batched_rejects_mixed_params():
     b = hf.params(r_s=0.02, p=5)
     with pytest.raises(hf.FMMError):
         hf.short_range_batched(dev(pos), dev(m), [a, b, a, a], off)
+
+
+@pytest.mark.parametrize("M", [32, 64])
+def test_pm_polynomial_split_matches_cpu_reference(M):
+    pos, m = inputs.clustered(3000, 4, inputs.rng_for(305, M))
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, p=4, split=1)
+    got = hf.pm_long_range(dev(pos), dev(m), prm, M).cpu().numpy()
+    ref = pm_ewald.pm_forces(pos, m, 1.0, rs, M, split=1, rcut=prm.r_cut)
+    assert rms_rel(got, ref) < 1e-10
+    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+def test_hybrid_polynomial_split_approaches_ewald():
+    """PM + short range with the polynomial split is the periodic Newtonian force."""
+    pos, m = inputs.clustered(3000, 4, inputs.rng_for(306))
+    M = 64
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, r_cut=4.5 * rs, theta=0.3, p=8, n_crit=16, split=1)
+    tot = hf.hybrid(dev(pos), dev(m), prm, M).cpu().numpy()
+    ew = pm_ewald.ewald_total(pos, m, 1.0, rs)
+    assert rms_rel(tot, ew) < 1e-4
