@@ -292,10 +292,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                         asm volatile("" : "+v"(clead));
                         auto pair = [&](const float4 s) __attribute__((always_inline)) {
                             const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                            // a particle meets itself (and exact duplicates) at d = 0: the clamp
-                            // keeps w finite, so w d = 0 without a separate r > 0 test
-                            const float rinv = __frsqrt_rn(fmaxf(r2, 1e-20f));
+                            // a particle meets itself (and exact duplicates) at d = 0: the 1e-20
+                            // added to r^2 keeps w finite, so w d = 0 without a separate r > 0
+                            // test; for any other pair it is far below r^2's rounding
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, 1e-20f)));
+                            const float rinv = __frsqrt_rn(r2);
                             float f1;
                             if constexpr (POLY) {
                                 const float x = r2 * rinv * k.c[0], omx = 1.0f - x;
@@ -313,15 +314,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                             py = fmaf(w, dy, py);
                             pz = fmaf(w, dz, pz);
                         };
-                        // two sources per step, both reads in flight
+                        // four sources per step, read two at a time
                         const float4 *sp = reinterpret_cast<const float4 *>(src) + g;
                         const float4 *const send = reinterpret_cast<const float4 *>(src) + nst;
-                        for (; sp + G < send; sp += 2 * G) {
+                        for (; sp + 3 * G < send; sp += 4 * G) {
                             const float4 s0 = sp[0], s1 = sp[G];
                             pair(s0);
                             pair(s1);
+                            const float4 s2 = sp[2 * G], s3 = sp[3 * G];
+                            pair(s2);
+                            pair(s3);
                         }
-                        if (sp < send) pair(sp[0]);
+                        for (; sp < send; sp += G) pair(sp[0]);
                         kahan_add(sx, cx, px);
                         kahan_add(sy, cy, py);
                         kahan_add(sz, cz, pz);

@@ -223,24 +223,32 @@ __global__ void k_roots(Cell *cells, int nbox, const int *__restrict__ boxoff)
     cells[b] = c;
 }
 
-// first index in [lo, hi) whose key is >= v
-__device__ inline int lower_bound_key(const uint64_t *keys, int lo, int hi, uint64_t v)
-{
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (keys[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // Octant boundaries of a cell at level l: b[o] = first particle of octant o, b[8] = end.
+// The seven lower bounds each search the whole particle range in lockstep (the interval
+// length sequence depends on the range only), so their loads are in flight together:
+// log2(n) dependent steps instead of seven times that.  Invariant per search: keys before
+// base are below the target and the answer lies in [base, base + n].
 __device__ inline void octant_bounds(const uint64_t *keys, const Cell &c, int l, int b[9])
 {
-    int shift = 3 * (kMaxLevel - 1 - l);
-    uint64_t prefix = keys[c.beg] >> (shift + 3) << (shift + 3);
+    const int shift = 3 * (kMaxLevel - 1 - l);
+    const uint64_t prefix = keys[c.beg] >> (shift + 3) << (shift + 3);
+    int base[7];
+    uint64_t tgt[7];
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+        base[o] = c.beg;
+        tgt[o] = prefix | ((uint64_t)(o + 1) << shift);
+    }
+    int n = c.end - c.beg;  // >= 1: only cells with more than n_crit particles are split
+    while (n > 1) {
+        const int half = n >> 1;
+#pragma unroll
+        for (int o = 0; o < 7; ++o) base[o] = keys[base[o] + half] < tgt[o] ? base[o] + half : base[o];
+        n -= half;
+    }
     b[0] = c.beg;
-    for (int o = 1; o < 8; ++o) b[o] = lower_bound_key(keys, b[o - 1], c.end, prefix | ((uint64_t)o << shift));
+#pragma unroll
+    for (int o = 0; o < 7; ++o) b[o + 1] = base[o] + (keys[base[o]] < tgt[o] ? 1 : 0);
     b[8] = c.end;
 }
 
