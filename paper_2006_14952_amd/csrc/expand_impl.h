@@ -653,13 +653,20 @@ __device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T
 
 // Sum the staged rows 0 .. nrows-1 (lane j's values at buf[j * STR + r]) over the runs of
 // lanes with the same sink sid[j] and add each sum to output `out0 + r` of that sink.
+// With fewer than 64 rows, 64 / nrows threads share a row, each summing a contiguous
+// range of lanes (a run cut by a range boundary is added in two parts).
 template <class T, int STR>
 __device__ __forceinline__ void m2l_reduce_rows(const T *buf, const int *sid, int nrows, int out0, T *L, int stride)
 {
-    for (int r = threadIdx.x; r < nrows; r += 64) {
+    const int nparts = nrows < 64 ? 64 / nrows : 1;
+    const int span = (64 + nparts - 1) / nparts;
+    for (int t = threadIdx.x; t < nrows * nparts; t += 64) {
+        const int r = t % nrows, part = t / nrows;
+        const int j0 = part * span, j1 = j0 + span < 64 ? j0 + span : 64;
+        if (j0 >= j1) continue;
         T sum = 0;
-        int cur = sid[0];
-        for (int j = 0; j < 64; ++j) {
+        int cur = sid[j0];
+        for (int j = j0; j < j1; ++j) {
             const int a = sid[j];
             if (a != cur) {
                 if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + out0 + r], sum);
