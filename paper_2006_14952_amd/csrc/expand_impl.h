@@ -651,22 +651,32 @@ __device__ __forceinline__ void m2l_pair_block(const T *__restrict__ Mb, const T
     if constexpr (KE < NC) m2l_pair_block<P, T, KE, MB, NE>(Mb, rp, D, lo, row, Mnext);
 }
 
-// Sum the staged rows 0 .. nrows-1 (lane j's values at buf[j * STR + r]) over the runs of
+// Sum the staged rows 0 .. NROWS-1 (lane j's values at buf[j * STR + r]) over the runs of
 // lanes with the same sink sid[j] and add each sum to output `out0 + r` of that sink.
-// With fewer than 64 rows, 64 / nrows threads share a row, each summing a contiguous
-// range of lanes (a run cut by a range boundary is added in two parts).
-template <class T, int STR>
-__device__ __forceinline__ void m2l_reduce_rows(const T *buf, const int *sid, int nrows, int out0, T *L, int stride)
+// With fewer than 64 rows, a power of two of threads share a row, each summing a
+// contiguous range of lanes (a run cut by a range boundary is added in two parts).  When
+// the whole wave holds one sink (`one`, wave-uniform; the pairs of a sink are contiguous),
+// the sums take no run tests and their loads are independent.
+template <class T, int STR, int NROWS>
+__device__ __forceinline__ void m2l_reduce_rows(const T *buf, const int *sid, bool one, int out0, T *L, int stride)
 {
-    const int nparts = nrows < 64 ? 64 / nrows : 1;
-    const int span = (64 + nparts - 1) / nparts;
-    for (int t = threadIdx.x; t < nrows * nparts; t += 64) {
-        const int r = t % nrows, part = t / nrows;
-        const int j0 = part * span, j1 = j0 + span < 64 ? j0 + span : 64;
-        if (j0 >= j1) continue;
+    constexpr int NP = NROWS > 32 ? 1 : NROWS > 16 ? 2 : NROWS > 8 ? 4 : NROWS > 4 ? 8 : NROWS > 2 ? 16 : NROWS > 1 ? 32 : 64;
+    constexpr int SPAN = 64 / NP;
+    for (int t = threadIdx.x; t < NROWS * NP; t += 64) {
+        const int r = t % NROWS, j0 = (t / NROWS) * SPAN;
+        if (one) {
+            T s0 = 0, s1 = 0;
+#pragma unroll
+            for (int k = 0; k < SPAN; k += 2) {
+                s0 += buf[(j0 + k) * STR + r];
+                if (k + 1 < SPAN) s1 += buf[(j0 + k + 1) * STR + r];
+            }
+            atomicAdd(&L[(size_t)sid[j0] * stride + out0 + r], s0 + s1);
+            continue;
+        }
         T sum = 0;
         int cur = sid[j0];
-        for (int j = j0; j < j1; ++j) {
+        for (int j = j0; j < j0 + SPAN; ++j) {
             const int a = sid[j];
             if (a != cur) {
                 if (cur >= 0) atomicAdd(&L[(size_t)cur * stride + out0 + r], sum);
@@ -682,7 +692,8 @@ __device__ __forceinline__ void m2l_reduce_rows(const T *buf, const int *sid, in
 // The outputs N0 .. NC-1 in chunks of HC: each output of a chunk summed in a register,
 // staged, reduced.
 template <int P, class T, int N0, int HC, int STR>
-__device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, const int *sid, T *L, int stride)
+__device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, const int *sid, bool one, T *L,
+                                               int stride)
 {
     constexpr int NC = ncoef(P);
     constexpr int N1 = N0 + HC < NC ? N0 + HC : NC;
@@ -698,9 +709,9 @@ __device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, 
         }
     }
     __syncthreads();
-    m2l_reduce_rows<T, STR>(buf, sid, N1 - N0, N0, L, stride);
+    m2l_reduce_rows<T, STR, N1 - N0>(buf, sid, one, N0, L, stride);
     __syncthreads();
-    if constexpr (N1 < NC) m2l_hi_outputs<P, T, N1, HC, STR>(Ms, D, buf, sid, L, stride);
+    if constexpr (N1 < NC) m2l_hi_outputs<P, T, N1, HC, STR>(Ms, D, buf, sid, one, L, stride);
 }
 
 template <int P, class T>
@@ -744,6 +755,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         for (int k = 1; k <= P; ++k) rp[k] = rp[k - 1] * rho;
     }
     sid[lane] = A;
+    // every lane holds the same sink: the pairs of a sink are contiguous, so equal ends suffice
+    const int A0 = __builtin_amdgcn_readlane(A, 0);
+    const bool one = A0 >= 0 && A0 == __builtin_amdgcn_readlane(A, 63);
     // outputs of degree >= P - 2 from the source coefficients of degree <= 2
     {
         constexpr Tab<P> tb{};
@@ -751,7 +765,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
 #pragma unroll
         for (int k = 0; k < kLo; ++k) Ms[k] = M0[k] * rp[tb.d[k]];
         __syncthreads();
-        m2l_hi_outputs<P, T, NHB, HC, STR>(Ms, D, buf, sid, L, stride);
+        m2l_hi_outputs<P, T, NHB, HC, STR>(Ms, D, buf, sid, one, L, stride);
     }
     // the other outputs from the whole source multipole
     T *row = buf + lane * STR;
@@ -763,13 +777,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     if (idx < npair) m2l_pair_block<P, T, 0, MB, NHB>(Mb, rp, D, lo, row, M0);
     __syncthreads();
     if constexpr (NMID > 0) {
-        m2l_reduce_rows<T, STR>(buf, sid, NMID, kLo, L, stride);
+        m2l_reduce_rows<T, STR, NMID>(buf, sid, one, kLo, L, stride);
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < kLo; ++k) row[k] = lo[k];
     __syncthreads();
-    m2l_reduce_rows<T, STR>(buf, sid, kLo, 0, L, stride);
+    m2l_reduce_rows<T, STR, kLo>(buf, sid, one, 0, L, stride);
 }
 
 int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st);

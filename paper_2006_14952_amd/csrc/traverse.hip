@@ -7,7 +7,8 @@
 // Each sink emits its M2L sources, its P2P sources (both leaves) and the pairs it hands
 // to its children.  The set of pairs is exactly that of the recursive traversal.
 //
-// GPU form: one 64-lane wave per sink (persistent waves pull sinks from a counter).
+// GPU form: one 64-lane wave per sink; a level's sinks are dealt round robin to a grid of
+// as many waves as fit on the device at once.
 // The wave takes up to 64 pending pairs at a time, decides them in parallel, appends
 // the emitted pairs with ballots, and pushes opened sources' children on a per-wave
 // stack (last in, first out).  Lists are chains of 64-entry chunks taken from pools
