@@ -27,15 +27,32 @@
 
 namespace hfmm {
 
-__device__ __forceinline__ int wave_incl_scan(int v)
+// Inclusive sum over the wave by DPP (same lane pattern as wave_incl_max_dpp below).
+__device__ __forceinline__ int wave_incl_scan(int vi)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
+    unsigned v = (unsigned)vi;
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (int)v;
+}
+
+// Inclusive max-scan of non-negative values over the wave by DPP: shifts by 1, 2, 4, 8
+// within each row of 16 lanes, then the last lane of row 0 (2) into row 1 (3), then lane 31
+// into rows 2 and 3.  Lanes without a source lane keep the identity 0.
+__device__ __forceinline__ int wave_incl_max_dpp(int vi)
+{
+    unsigned v = (unsigned)vi;  // unsigned max: 0 is its identity, so each step fuses into one DPP max
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (int)v;
 }
 
 // largest e in [0, ne) with pref[e] <= slot (pref non-decreasing, pref[0] = 0)
@@ -205,14 +222,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                     m = max(m, smark[kPer * lane + u]);
                     mrun[u] = m;
                 }
-                int incl = m;
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int v = __shfl_up(incl, o, 64);
-                    if (lane >= o) incl = max(incl, v);
-                }
-                int prev = __shfl_up(incl, 1, 64);
-                if (lane == 0) prev = 0;
+                const int incl = wave_incl_max_dpp(m);
+                const int prev = __builtin_amdgcn_update_dpp(0, incl, 0x138, 0xf, 0xf, false);  // wave_shr:1
                 const int base = max(prev, efirst + 1);
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {

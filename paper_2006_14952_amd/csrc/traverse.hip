@@ -148,14 +148,19 @@ __device__ __forceinline__ void emit(const TravArgs &a, int k, ListState &L, int
     L.tot += m;
 }
 
-__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+// Inclusive sum over the wave by DPP: shifts by 1, 2, 4, 8 within each row of 16 lanes,
+// then the last lane of row 0 (2) into row 1 (3), then lane 31 into rows 2 and 3; lanes
+// without a source lane add 0.  No LDS round trips on the traversal's dependent path.
+__device__ __forceinline__ int wave_incl_scan(int vi, int)
 {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
+    unsigned v = (unsigned)vi;
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (int)v;
 }
 
 // Full MAC evaluation for the candidate logic: code as mac_decide, plus whether item 3
