@@ -196,7 +196,7 @@ __device__ __forceinline__ MacEval mac_eval(int4 a, int4 b, int s, const MacCons
 
 // Sinks t = blockIdx.x, blockIdx.x + gridDim.x, ... of one level.
 template <int MODE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_traverse(TravArgs a, MacConst mc)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kModeLearned ? 3 : 4))) void k_traverse(TravArgs a, MacConst mc)
 {
     __shared__ short mlp_act[MODE == kModeLearned ? 64 * 64 : 1];
     __shared__ uint32_t cand_q[MODE == kModeLearned ? kCandQ : 1];
