@@ -91,4 +91,36 @@ int zero_async(void *p, size_t bytes, hipStream_t st);
 int scan_exclusive_dn(const int *in, int *out, const int *lo, const int *hi, int n_max, int *total, hipStream_t st,
                       DevBuf &tmp);  // p 16-byte aligned, bytes a multiple of 4
 
+// ---------------------------------------------------------------------------
+// Inclusive scans over one 64-lane wave by DPP: shifts by 1, 2, 4 and 8 lanes within each
+// row of 16, then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31 into rows 2
+// and 3.  Lanes without a source lane take 0, the identity of both operations (the max
+// is over non-negative values).  No LDS round trips.
+__device__ __forceinline__ int wave_incl_sum(int vi)
+{
+    unsigned v = (unsigned)vi;
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (int)v;
+}
+
+__device__ __forceinline__ int wave_incl_max(int vi)
+{
+    unsigned v = (unsigned)vi;  // unsigned: 0 is the identity, so each step fuses into one DPP max
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (int)v;
+}
+
+// The value of the previous lane (0 in lane 0): DPP wave_shr:1.
+__device__ __forceinline__ int wave_shift_up1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+
 }  // namespace hfmm

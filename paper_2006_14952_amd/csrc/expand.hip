@@ -50,13 +50,8 @@ __global__ __launch_bounds__(64) void k_flatten_pairs(const int *__restrict__ he
         const int A = A0 + lane;
         const int nl = A < ncell ? cnt[A] : 0;
         const int hd = nl > 0 ? head[A] : 0;
-        int incl = nl;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += u;
-        }
-        const int total = __shfl(incl, 63, 64);
+        const int incl = wave_incl_sum(nl);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         if (total == 0) continue;
         int base = 0;
         if (lane == 63) base = atomicAdd(ctr, total);
@@ -103,14 +98,9 @@ __global__ __launch_bounds__(64) void k_flatten_learned(const int *__restrict__ 
 #pragma unroll
         for (int o = 0; o < kOrders; ++o) {
             const int c = nl > 0 ? ocnt[(size_t)o * ncell + A] : 0;
-            int incl = c;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int u = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += u;
-            }
+            const int incl = wave_incl_sum(c);
             excl[o] = incl - c;
-            const int total = __shfl(incl, 63, 64);
+            const int total = __builtin_amdgcn_readlane(incl, 63);
             int b = 0;
             if (lane == 63 && total > 0) b = atomicAdd(&ctr[o], total);
             base[o] = __shfl(b, 63, 64);

@@ -27,34 +27,6 @@
 
 namespace hfmm {
 
-// Inclusive sum over the wave by DPP (same lane pattern as wave_incl_max_dpp below).
-__device__ __forceinline__ int wave_incl_scan(int vi)
-{
-    unsigned v = (unsigned)vi;
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return (int)v;
-}
-
-// Inclusive max-scan of non-negative values over the wave by DPP: shifts by 1, 2, 4, 8
-// within each row of 16 lanes, then the last lane of row 0 (2) into row 1 (3), then lane 31
-// into rows 2 and 3.  Lanes without a source lane keep the identity 0.
-__device__ __forceinline__ int wave_incl_max_dpp(int vi)
-{
-    unsigned v = (unsigned)vi;  // unsigned max: 0 is its identity, so each step fuses into one DPP max
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
-    return (int)v;
-}
-
 // largest e in [0, ne) with pref[e] <= slot (pref non-decreasing, pref[0] = 0)
 __device__ __forceinline__ int find_entry(const int *pref, int ne, int slot)
 {
@@ -187,10 +159,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                     if (gx * gx + gy * gy + gz * gz > k.rc2 * 1.0001f) cntj = 0;
                 }
             }
-            const int incl = wave_incl_scan(cntj);
+            const int incl = wave_incl_sum(cntj);
             if (lane < ne) epref[lane] = incl - cntj;
             const int total = __builtin_amdgcn_readlane(incl, 63);
-            const int ltot = F64 ? total : __builtin_amdgcn_readlane(wave_incl_scan(listed), 63);
+            const int ltot = F64 ? total : __builtin_amdgcn_readlane(wave_incl_sum(listed), 63);
             npairs += (unsigned long long)ns * (unsigned)ltot;
             __syncthreads();
             // FP32: the source records of a stage are loaded into registers one stage
@@ -222,8 +194,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6)
                     m = max(m, smark[kPer * lane + u]);
                     mrun[u] = m;
                 }
-                const int incl = wave_incl_max_dpp(m);
-                const int prev = __builtin_amdgcn_update_dpp(0, incl, 0x138, 0xf, 0xf, false);  // wave_shr:1
+                const int incl = wave_incl_max(m);
+                const int prev = wave_shift_up1(incl);
                 const int base = max(prev, efirst + 1);
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {

@@ -148,21 +148,6 @@ __device__ __forceinline__ void emit(const TravArgs &a, int k, ListState &L, int
     L.tot += m;
 }
 
-// Inclusive sum over the wave by DPP: shifts by 1, 2, 4, 8 within each row of 16 lanes,
-// then the last lane of row 0 (2) into row 1 (3), then lane 31 into rows 2 and 3; lanes
-// without a source lane add 0.  No LDS round trips on the traversal's dependent path.
-__device__ __forceinline__ int wave_incl_scan(int vi, int)
-{
-    unsigned v = (unsigned)vi;
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return (int)v;
-}
-
 // Full MAC evaluation for the candidate logic: code as mac_decide, plus whether item 3
 // forced the opening and (L / S_c)^2.
 struct MacEval {
@@ -277,7 +262,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
             emit(a, 1, Ls[1], bnext, bend, is_p2p, it, lt, lane);
             emit(a, 2, Ls[2], bnext, bend, is_pd, it, lt, lane);
             const int nch = open_src ? xln_nchild(gb.x) : 0;
-            const int incl = wave_incl_scan(nch, lane);
+            const int incl = wave_incl_sum(nch);
             const int tot = __builtin_amdgcn_readlane(incl, 63);
             if (tot > 0) {
                 if (sp + tot > scap) {
