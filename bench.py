@@ -237,6 +237,10 @@ def main():
                                    "kind": "oracle",
                                    "sample": "%d %s: its full tree and upward pass, then traversal/M2L/P2P/downward"
                                              " for their sink cells only; %.1f s" % (len(tgc), what, t_or)}
+            # the share of listed P2P pairs that lie inside r_cut, from the oracle's own lists
+            # of the sampled sink leaves (the GPU counts listed and evaluated pairs only)
+            if res.stats.get("p2p_pairs"):
+                out["counts"]["p2p_incut_fraction_sampled"] = res.stats["p2p_incut"] / res.stats["p2p_pairs"]
             out["accuracy"].update({"oracle_form": "plain p=%d theta=%.2f" % (pr["p"], wl["theta"]),
                                     "median_vs_oracle": float(np.median(e_or)),
                                     "p99_vs_oracle": float(np.percentile(e_or, 99)), "max_vs_oracle": float(e_or.max())})
