@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "short-range particles/s at p99 rel force err ≤1e-3; learned/FP32 vs plain"
-PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12}
+PEAK = {"fp32_vector": 157.3e12, "fp64_vector": 78.6e12, "hbm": 8.0e12}
 # algorithmic flop per evaluated P2P pair: the Gaussian split's counting convention (3 sub,
 # 3 FMA for r^2, rsqrt, exp, rcp counted 1 each, ~8 erfc approximation, 4 combine, 3 FMA
 # accumulate); the polynomial split's factored force law (3 sub, 3 FMA for r^2, rsqrt, 2 mul
@@ -194,6 +194,8 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_launch, "p2p_ms_per_launch": p2p_s * 1e3},
         "stages_ms": {k: float(np.mean(v)) for k, v in stage.items()},
+        "roofline_step": stage_rooflines(st, {k: float(np.mean(v)) for k, v in stage.items()}, float(np.mean(build_ms)),
+                                         dt * 1e3, n, pr["p"], bool(wl["learned"]), wl["precision"], args.split),
         "build_ms": float(np.mean(build_ms)),
         "pm_ms": float(np.mean(pm_ms)) if hybrid else None,
         "counts": {k: st[k] for k in ("n_cells", "n_leaves", "max_level", "n_m2l", "n_p2p", "p2p_pairs", "n_visit",
@@ -249,6 +251,42 @@ def main():
 
 
 CONFIG_SAMPLE_SEED = 777
+
+
+def _binom(n, k):
+    from math import comb
+    return comb(n, k)
+
+
+def stage_rooflines(counts, stages, build_ms, step_ms, n, p, learned, precision, split):
+    """Per-stage work at its own peak against the stage's measured span, and the whole step:
+    sum of the stages' times at peak / ms per step.  Work per unit: tree 250 B per particle
+    (HBM); P2M 2 n_p per particle and M2M, L2L 2 C(p+6,6) per cell; traversal ~40 FP64
+    operations per visited pair; M2L 2 C(p+6,6) per accepted pair (at each pair's order for
+    the learned selector); P2P 38 flop per evaluated pair (30 with the polynomial split);
+    L2P 6 C(p+2,3) per particle.  Stages on the two streams overlap, so their spans do too."""
+    pe = 8 if learned else p  # expansions are kept at order 8 under the selector
+    fp = PEAK["fp32_vector"] if precision else PEAK["fp64_vector"]
+    if learned:
+        m2l = sum(2 * _binom(o + 6, 6) * c for o, c in zip(range(2, 9), counts["n_m2l_by_order"]))
+    else:
+        m2l = 2 * _binom(p + 6, 6) * counts["n_m2l"]
+    rows = {
+        "build": (250.0 * n, "B", PEAK["hbm"], build_ms),
+        "upward": (2.0 * _binom(pe + 3, 3) * n + 2.0 * _binom(pe + 6, 6) * counts["n_cells"], "flop", fp,
+                   stages["t_upward_ms"]),
+        "traversal": (40.0 * counts["n_visit"], "op", PEAK["fp64_vector"], stages["t_traverse_ms"]),
+        "m2l": (float(m2l), "flop", fp, stages["t_m2l_ms"]),
+        "p2p": (P2P_FLOP_PER_PAIR[split] * counts["p2p_evaluated"], "flop", fp, stages["t_p2p_ms"]),
+        "downward": (2.0 * _binom(pe + 6, 6) * counts["n_cells"] + 6.0 * _binom(pe + 2, 3) * n, "flop", fp,
+                     stages["t_downward_ms"]),
+    }
+    out, at_peak = {}, 0.0
+    for k, (w, unit, peak, ms) in rows.items():
+        t = w / peak * 1e3
+        at_peak += t
+        out[k] = {"work": w, "unit": unit, "ms_at_peak": t, "ms": ms, "frac": t / ms if ms > 0 else None}
+    return {"stages": out, "ms_at_peak": at_peak, "frac": at_peak / step_ms}
 
 
 def copy_calibration(nbytes):
