@@ -1,0 +1,61 @@
+"""Host-side arithmetic of bench.py's report (no GPU): the step roofline adds every
+stage's algorithmic work at its own peak and sets it against the measured spans."""
+import importlib.util
+import math
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _counts(**kw):
+    c = {"n_cells": 1000, "n_m2l": 5000, "n_visit": 20000, "p2p_evaluated": 10 ** 7,
+         "n_m2l_by_order": [0] * 7}
+    c.update(kw)
+    return c
+
+
+STAGES = {"t_upward_ms": 1.0, "t_traverse_ms": 2.0, "t_m2l_ms": 3.0, "t_p2p_ms": 4.0, "t_downward_ms": 0.5}
+
+
+def test_stage_work_follows_the_counting_rules(bench):
+    n, p = 4096, 6
+    r = bench.stage_rooflines(_counts(), STAGES, 0.25, 10.0, n, p, False, 1, 0)
+    s = r["stages"]
+    assert s["build"]["work"] == 250 * n and s["build"]["unit"] == "B"
+    assert s["p2p"]["work"] == 38 * 10 ** 7
+    assert s["m2l"]["work"] == 2 * math.comb(p + 6, 6) * 5000 == 2 * 924 * 5000
+    assert s["traversal"]["work"] == 40 * 20000
+    assert s["upward"]["work"] == 2 * math.comb(p + 3, 3) * n + 2 * math.comb(p + 6, 6) * 1000
+    assert s["downward"]["work"] == 2 * math.comb(p + 6, 6) * 1000 + 6 * math.comb(p + 2, 3) * n
+    # times at peak: FP32 form against the FP32 vector peak, traversal against FP64, build against HBM
+    assert s["p2p"]["ms_at_peak"] == pytest.approx(38e7 / 157.3e12 * 1e3)
+    assert s["traversal"]["ms_at_peak"] == pytest.approx(8e5 / 78.6e12 * 1e3)
+    assert s["build"]["ms_at_peak"] == pytest.approx(250 * n / 8e12 * 1e3)
+    assert s["p2p"]["frac"] == pytest.approx(s["p2p"]["ms_at_peak"] / 4.0)
+    assert r["ms_at_peak"] == pytest.approx(sum(v["ms_at_peak"] for v in s.values()))
+    assert r["frac"] == pytest.approx(r["ms_at_peak"] / 10.0)
+
+
+def test_learned_counts_each_order_and_fp64_uses_its_peak(bench):
+    by_order = [1, 2, 3, 4, 5, 6, 7]  # orders 2..8
+    r = bench.stage_rooflines(_counts(n_m2l_by_order=by_order), STAGES, 0.25, 10.0, 100, 4, True, 0, 0)
+    want = sum(2 * math.comb(o + 6, 6) * c for o, c in zip(range(2, 9), by_order))
+    assert r["stages"]["m2l"]["work"] == want
+    # expansions at order 8 under the selector, FP64 peak for the FP64 form
+    assert r["stages"]["downward"]["work"] == 2 * math.comb(14, 6) * 1000 + 6 * math.comb(10, 3) * 100
+    assert r["stages"]["m2l"]["ms_at_peak"] == pytest.approx(want / 78.6e12 * 1e3)
+
+
+def test_polynomial_split_counts_thirty_flop_per_pair(bench):
+    r = bench.stage_rooflines(_counts(), STAGES, 0.25, 10.0, 10, 4, False, 1, 1)
+    assert r["stages"]["p2p"]["work"] == 30 * 10 ** 7
