@@ -459,7 +459,7 @@ void fmm_free_tree(fmm_tree *t)
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
-                      &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate, &t->cfeat};
+                      &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate, &t->cfeat, &t->cellc};
     for (DevBuf *b : bufs) free_buf(*b);
     free_buf(t->lord);
     for (int k = 0; k < kKinds; ++k) {

@@ -50,6 +50,7 @@ struct fmm_tree {
     int64_t lseg[hfmm::kOrders] = {0};               // learned: start of each order's pairs in m2l_pairs
     int trav_mode = 0;                               // mode of the last traversal
     hfmm::DevBuf tstack;                             // per-wave traversal stacks
+    hfmm::DevBuf cellc;                              // packed 16-byte cell view for the traversal
     int stk_cap = 4096;                              // entries per wave (grows on overflow)
     int64_t n_m2l = 0, n_p2p = 0, n_visit = 0, p2p_pairs = 0;
     hfmm::DevBuf counters;                           // device counters

@@ -76,6 +76,7 @@ struct TravArgs {
     double box, rs, rcut;
     const float4 *cf;              // learned: per-cell part of the features (cell_features)
     const MacModel *model;
+    const int4 *cellc;  // the first 16 bytes of every cell, packed (what the traversal reads)
 };
 
 constexpr int kChunkBlock = 32;   // chunks taken from a pool per atomic
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
     // fast as an LDS stack, and it leaves the LDS to the learned selector
     uint32_t *stk = a.stack + (size_t)blockIdx.x * a.stk_cap;
     const int scap = a.stk_cap;
-    const int4 *cell4 = reinterpret_cast<const int4 *>(a.cells);  // two int4 per cell
+    const int4 *cellc = a.cellc;
     unsigned long long visits = 0, nm2l = 0, np2p = 0;
     unsigned nord[kOrders] = {0, 0, 0, 0, 0, 0, 0};  // learned: this wave's M2L pairs per order
     int bnext[kKinds], bend[kKinds];
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
     }
     for (int t = blockIdx.x; t < a.ln; t += gridDim.x) {
         const int A = a.lbeg + t;
-        const int4 ga = cell4[2 * A];
+        const int4 ga = cellc[A];
         const int parentA = a.cells[A].parent;
         const bool leafA = xln_nchild(ga.x) == 0;
         const int lvA = xln_level(ga.x);
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
                 float fv[kFeat];
                 for (int q = 0; q < kFeat; ++q) fv[q] = 0.0f;
                 if (valid) {
-                    gb = cell4[2 * B];
+                    gb = cellc[B];
                     PairGeo g = pair_geo(ga, gb, s);
                     pair_features(g, lvA, xln_level(gb.x), a.box, a.rs, a.rcut, mA0, a.cf[B], fv);
                 }
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
                 bool cand = false;
                 const int B = (int)(it >> 5), s = (int)(it & 31);
                 if (valid) {
-                    gb = cell4[2 * B];
+                    gb = cellc[B];
                     if (MODE == kModePlain) {
                         d = mac_decide(ga, gb, s, mc);
                     } else {
@@ -424,6 +425,14 @@ static int resident_waves(int mode)
     return resident_waves<kModeLearned>();
 }
 
+// The traversal's 16-byte view of each cell, packed: the random cell reads of the traversal
+// then touch half as many cache lines (8 sibling cells per 128-byte line).
+__global__ void k_pack_cells(const Cell *__restrict__ cells, int ncell, int4 *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) out[c] = reinterpret_cast<const int4 *>(cells)[2 * (size_t)c];
+}
+
 // Per-cell part of the selector's features, from the scaled multipoles (stride `stride`).
 template <class T>
 __global__ void k_cell_features(const T *__restrict__ M, int stride, int ncell, float4 *__restrict__ cf)
@@ -492,6 +501,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         if (mode == kModeExport) want[kKindCand] = slack + 2 * ncell;
     }
     if ((rc = ensure_pools(t, want))) return rc;
+    if ((rc = grow(t->cellc, (size_t)ncell * sizeof(int4)))) return rc;
+    k_pack_cells<<<(ncell + 255) / 256, 256, 0, st>>>(ptr<Cell>(t->cells), ncell, ptr<int4>(t->cellc));
     if (mode == kModeLearned) {
         if (!M || mstride < 20) return set_error(FMM_ERR_ARG, "learned traversal: multipoles of order >= 3 needed");
         if ((rc = grow(t->cfeat, (size_t)ncell * sizeof(float4)))) return rc;
@@ -543,6 +554,7 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         a.rcut = P->r_cut;
         a.cf = ptr<float4>(t->cfeat);
         a.model = model;
+        a.cellc = ptr<int4>(t->cellc);
         for (int l = 0; l < t->nlevel; ++l) {
             a.lbeg = t->lvl_beg[l];
             a.ln = t->lvl_beg[l + 1] - a.lbeg;
