@@ -3,7 +3,7 @@
 // counted iff 0 < r^2 < r_cut^2.
 //
 // One 64-lane wave per sink leaf.  The sources of up to 64 list entries form one stream
-// of slots (a wave prefix sum over the entry sizes), staged 192 slots at a time in LDS.
+// of slots (a wave prefix sum over the entry sizes), staged 256 slots at a time in LDS.
 // A sink of n_A <= 64 particles is held floor(64 / n_A) times in the wave; copy g walks
 // slots g, g + G, ... of the staged stream, and the copies are summed through LDS at
 // the end.  Larger leaves are processed 64 sink particles at a time.
@@ -88,13 +88,13 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
     s = t;
 }
 
-constexpr int kStage = 192;
+constexpr int kStage = 256;
 
 // POLY (FP32 form, polynomial split): f_(1) = -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5) evaluated
 // as -(1-x)^2 (1 + 2x + 3x^2 + 3x^3/2) / r^3, x = r / r_c: the three terms cancel near r_cut
 // in FP32, the factored form does not.
 template <bool F64, bool POLY>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 6))) void k_p2p(P2PArgs a, P2PConst k)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
 {
     using R = typename std::conditional<F64, double, float>::type;
     using V4 = typename std::conditional<F64, double4, float4>::type;
