@@ -125,14 +125,21 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
     return __builtin_bit_cast(uint32_t, v);
 }
 
+// ReLU(c + bias) of one output fragment, rounded to BF16 and packed as a B operand.
+__device__ __forceinline__ short4v relu_pack(const float4v c, const float4 bias)
+{
+    const uint2 v = make_uint2(pack_bf16(fmaxf(c[0] + bias.x, 0.0f), fmaxf(c[1] + bias.y, 0.0f)),
+                               pack_bf16(fmaxf(c[2] + bias.z, 0.0f), fmaxf(c[3] + bias.w, 0.0f)));
+    return __builtin_bit_cast(short4v, v);
+}
+
 // Logits of the 64 pairs of a wave (one per lane; lanes without a pair take part with
 // zero features).  `act` is 64 x 64 BF16 of LDS, `out` receives 8 logits per lane.
 // v_mfma_f32_16x16x16_bf16 operand layout (per lane l): A[i = l%16][k = 4(l/16)+r],
 // B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.  Each layer computes
 // the transposed product D = W^T act^T: the weight fragment is the A operand and the
-// activations the B operand, so a lane ends with 4 consecutive outputs of one pair and
-// writes them as one 8-byte store.  Row tile t holds pairs 16t .. 16t+15.  Each layer
-// first reads all its input fragments, then writes its output over the same LDS rows.
+// activations the B operand, so a lane ends with 4 consecutive outputs of one pair.
+// Row tile t holds pairs 16t .. 16t+15.
 __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float *fin, short *act, float *out)
 {
     const int lane = threadIdx.x & 63;
@@ -147,30 +154,26 @@ __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float
         row[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
     }
     __syncthreads();
-    // layer 1: 16 -> 64
-    short4v a1[4];
+    // The output fragment of a layer (4 consecutive outputs of one pair per lane) is laid
+    // out as the next layer's B operand (4 consecutive inputs of one pair), so the hidden
+    // activations stay in registers; only the input (one pair per lane) and the logits
+    // (back to one pair per lane) pass through LDS.
+    short4v h1[4][4];  // [pair tile t][output chunk u]
+    {
+        short4v a1[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a1[t] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 4 * lk);
+        for (int t = 0; t < 4; ++t) a1[t] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 4 * lk);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const short4v w = W.w1[u][lane];
-        const float4 bias = *reinterpret_cast<const float4 *>(W.b1 + 16 * u + 4 * lk);
+        for (int u = 0; u < 4; ++u) {
+            const short4v w = W.w1[u][lane];
+            const float4 bias = *reinterpret_cast<const float4 *>(W.b1 + 16 * u + 4 * lk);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float4v c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a1[t], float4v{0, 0, 0, 0}, 0, 0, 0);
-            *reinterpret_cast<uint2 *>(act + (16 * t + li) * 64 + 16 * u + 4 * lk) =
-                make_uint2(pack_bf16(fmaxf(c[0] + bias.x, 0.0f), fmaxf(c[1] + bias.y, 0.0f)),
-                           pack_bf16(fmaxf(c[2] + bias.z, 0.0f), fmaxf(c[3] + bias.w, 0.0f)));
+            for (int t = 0; t < 4; ++t)
+                h1[t][u] = relu_pack(__builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a1[t], float4v{0, 0, 0, 0}, 0, 0, 0),
+                                     bias);
         }
     }
-    __syncthreads();
-    // layer 2: 64 -> 64
-    short4v a[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
-            a[t][kc] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 16 * kc + 4 * lk);
+    short4v h2[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -178,30 +181,21 @@ __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float
         for (int kc = 0; kc < 4; ++kc) {
             const short4v w = W.w2[kc][u][lane];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a[t][kc], c[t], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[t][kc], c[t], 0, 0, 0);
         }
         const float4 bias = *reinterpret_cast<const float4 *>(W.b2 + 16 * u + 4 * lk);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            *reinterpret_cast<uint2 *>(act + (16 * t + li) * 64 + 16 * u + 4 * lk) =
-                make_uint2(pack_bf16(fmaxf(c[t][0] + bias.x, 0.0f), fmaxf(c[t][1] + bias.y, 0.0f)),
-                           pack_bf16(fmaxf(c[t][2] + bias.z, 0.0f), fmaxf(c[t][3] + bias.w, 0.0f)));
+        for (int t = 0; t < 4; ++t) h2[t][u] = relu_pack(c[t], bias);
     }
-    __syncthreads();
-    // layer 3: 64 -> 8 (padded to 16 outputs); logits as FP32 over the first 4 KB of act
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
-            a[t][kc] = *reinterpret_cast<const short4v *>(act + (16 * t + li) * 64 + 16 * kc + 4 * lk);
+    // layer 3: 64 -> 8 (padded to 16 outputs)
     float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
         const short4v w = W.w3[kc][lane];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, a[t][kc], c[t], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h2[t][kc], c[t], 0, 0, 0);
     }
-    __syncthreads();  // every lane has read its layer-3 inputs before the logits overwrite them
+    __syncthreads();  // every lane has read its input rows before the logits overwrite them
     float *fout = reinterpret_cast<float *>(act);
     if (lk < 2) {  // classes 4 lk .. 4 lk + 3 of pair 16 t + li
         const float4 bias = *reinterpret_cast<const float4 *>(W.b3 + 4 * lk);
