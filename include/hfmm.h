@@ -115,6 +115,19 @@ int fmm_build_tree(const fmm_params *params, int64_t n, const double *pos, const
  * was too small the traversal is rerun with enough room). */
 int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
 
+/* The same evaluation as fmm_short_range_forces, recorded once as a HIP graph and then
+ * replayed, for callers that evaluate one built tree (one box or a forest of boxes)
+ * repeatedly: a replay is one hipGraphLaunch on `stream`, with no host synchronisation.
+ * The first call on a tree, and any call after the tree is rebuilt or with other params,
+ * acc or stream, runs the evaluation eagerly (its result is this call's result) and then
+ * records the same stages, on `stream` and the tree's second stream, into a graph the
+ * tree owns (freed by fmm_free_tree or replaced on the next recording).  A replay reuses
+ * the recorded list sizes: they repeat exactly on an unchanged tree.  Plain MAC only
+ * (params->learned = 1: FMM_ERR_ARG); `stream` must be a created stream (the null
+ * stream cannot be recorded: FMM_ERR_ARG).  Errors as fmm_short_range_forces; a failed
+ * recording (FMM_ERR_HIP) leaves no graph behind and the eager result stands. */
+int fmm_short_range_forces_graph(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
+
 /* Long-range accelerations by the particle-mesh method with a mesh of mesh^3 cells
  * (Sec. 2.2: Poisson Green function filtered by exp(-k^2 r_s^2)): CIC deposit, FFT,
  * filtered Green function with the CIC window deconvolved, spectral gradient, inverse

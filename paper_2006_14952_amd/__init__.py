@@ -65,6 +65,7 @@ def lib():
         vp, i64, dp = C.c_void_p, C.c_int64, C.c_void_p
         L.fmm_build_tree.argtypes = [C.POINTER(Params), i64, dp, dp, vp, C.POINTER(vp)]
         L.fmm_short_range_forces.argtypes = [vp, C.POINTER(Params), dp, vp]
+        L.fmm_short_range_forces_graph.argtypes = [vp, C.POINTER(Params), dp, vp]
         L.pm_long_range_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.hybrid_forces.argtypes = [C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
         L.fmm_hybrid_forces_tree.argtypes = [C.POINTER(vp), C.POINTER(Params), C.c_int, i64, dp, dp, dp, vp]
@@ -178,6 +179,16 @@ class Tree:
             out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
         _check(lib().fmm_short_range_forces(self._h, C.byref(prm), _dev64(out, (3,)) if self.n else None,
                                             _stream(stream)))
+        return out
+
+    def short_range_graph(self, prm: Params, out=None, stream=None):
+        """Short range through the recorded HIP graph of this tree (fmm_short_range_forces_graph):
+        the first call records, later calls with the same out, params and stream replay."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n, 3), dtype=torch.float64, device="cuda")
+        _check(lib().fmm_short_range_forces_graph(self._h, C.byref(prm), _dev64(out, (3,)) if self.n else None,
+                                                  _stream(stream)))
         return out
 
     def set_timing(self, on=True):

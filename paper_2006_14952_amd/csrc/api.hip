@@ -163,6 +163,7 @@ static int build_common(const fmm_params *P, int64_t n, const double *pos, const
         fresh = true;
     }
     if (t->timing) (void)hipEventRecord(t->ev[14], st);  // timing only
+    ++t->build_serial;  // buffers may move: a recorded evaluation of the old tree is void
     int rc = tree_build(t, P, n, pos, mass, nbox, offsets, st);
     if (rc) {
         if (fresh) fmm_free_tree(t);
@@ -237,6 +238,53 @@ int fmm_short_range_forces(fmm_tree *t, const fmm_params *P, double *acc, void *
         return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
     if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
     return run_forces(t, P, acc, (hipStream_t)stream);
+}
+
+int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, void *stream)
+{
+    clear_error();
+    if (!t) return set_error(FMM_ERR_ARG, "tree is NULL");
+    if (int rc = check_params(P)) return rc;
+    if (P->box != t->box || P->n_crit != t->ncrit)
+        return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
+    if (P->learned) return set_error(FMM_ERR_ARG, "the recorded form takes the plain MAC (learned = 0)");
+    if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return set_error(FMM_ERR_ARG, "the recorded form needs a created stream, not the null stream");
+    if (t->n == 0) return 0;
+    if (t->gexec && t->gserial == t->build_serial && same_params(t->gparams, *P) && t->gacc == acc &&
+        t->gstream == st)
+        return hip_check(hipGraphLaunch(t->gexec, st), "graph launch");
+    if (t->gexec) {
+        (void)hipGraphExecDestroy(t->gexec);
+        t->gexec = nullptr;
+    }
+    // one eager evaluation (it sizes every buffer and gives this call's result), then the
+    // same stages are recorded; a buffer that would still have to grow fails the recording
+    if (int rc = run_forces(t, P, acc, st)) return rc;
+    const int timing = t->timing;
+    t->timing = 0;
+    t->capturing = true;
+    int rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc_run = rc ? rc : run_forces(t, P, acc, st);
+    hipGraph_t g = nullptr;
+    if (!rc) rc = hip_check(hipStreamEndCapture(st, &g), "end capture");
+    t->capturing = false;
+    t->timing = timing;
+    if (!rc) rc = rc_run;
+    if (!rc) rc = hip_check(hipGraphInstantiate(&t->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+    if (g) (void)hipGraphDestroy(g);
+    if (rc) {
+        if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
+        t->gexec = nullptr;
+        (void)hipGetLastError();
+        return rc;
+    }
+    t->gparams = *P;
+    t->gacc = acc;
+    t->gstream = st;
+    t->gserial = t->build_serial;
+    return 0;
 }
 
 int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t n, const double *pos,
@@ -466,6 +514,7 @@ void fmm_free_tree(fmm_tree *t)
         free_buf(t->litems[k]);
         free_buf(t->lnext[k]);
     }
+    if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
     if (t->host) (void)hipHostFree(t->host);
     if (t->events_ready)
         for (auto &e : t->ev) (void)hipEventDestroy(e);

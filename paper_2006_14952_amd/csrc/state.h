@@ -70,6 +70,15 @@ struct fmm_tree {
     hipEvent_t bev[hfmm::kMaxLevel + 1]{};  // tree build: one per level launch
     bool bev_ready = false;
 
+    // recorded evaluation (fmm_short_range_forces_graph): the executable graph, what it was
+    // recorded with, and the build it belongs to
+    hipGraphExec_t gexec = nullptr;
+    fmm_params gparams{};
+    double *gacc = nullptr;
+    hipStream_t gstream = nullptr;
+    uint64_t build_serial = 0, gserial = 0;
+    bool capturing = false;  // run_forces is being recorded: no host reads, no timing
+
     // timing
     int timing = 0;
     fmm_stats stats{};

@@ -526,10 +526,10 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
         // counters: [0..3] 64-bit stats, err at byte 96, 64-bit M2L counts per learned order
         // at byte 128, P2P evaluated pairs at byte 192, pool counters from byte kPoolByte
         unsigned char *cb = ptr<unsigned char>(t->counters);
-        if ((rc = hip_check(hipMemsetAsync(cb, 0, kCounterBytes, st), "traversal counters"))) return rc;
+        if ((rc = zero_async(cb, kCounterBytes, st))) return rc;  // a kernel: also valid inside a recorded graph
         k_wstate_init<<<(nw + 255) / 256, 256, 0, st>>>(ptr<int>(t->wstate), nw,
                                                         reinterpret_cast<int *>(cb + kPoolByte));
-        if ((rc = hip_check(hipMemsetAsync(t->lcnt.p, 0, ncnt * 4, st), "list counts"))) return rc;
+        if ((rc = zero_async(t->lcnt.p, ncnt * 4, st))) return rc;
         TravArgs a;
         a.cells = ptr<Cell>(t->cells);
         a.ncell = ncell;
@@ -564,6 +564,10 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             else k_traverse<kModeLearned><<<g, 64, 0, st>>>(a, mc);
         }
         if ((rc = hip_check(hipGetLastError(), "traversal"))) return rc;
+        // Being recorded: the tree and parameters are those of the evaluation just run, whose
+        // pools and stacks fitted; the lists, their sizes and every wave's use of pool blocks
+        // and stack (sinks are dealt statically) repeat exactly, so no readback is needed.
+        if (t->capturing) return 0;
         if ((rc = hip_check(hipMemcpyAsync(t->host, cb, kCounterBytes, hipMemcpyDeviceToHost, st), "counters")))
             return rc;
         if ((rc = hip_check(hipStreamSynchronize(st), "traversal sync"))) return rc;

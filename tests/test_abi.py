@@ -59,3 +59,8 @@ def test_autotune_and_hybrid_tree_reject_bad_arguments_without_gpu():
     assert L.fmm_hybrid_forces_tree(C.byref(h), C.byref(prm), 32, 10, None, None, None, None) == hf.FMM_ERR_ARG
     prm.theta = 0.0
     assert L.fmm_hybrid_forces_tree(C.byref(h), C.byref(prm), 32, 10, fake, fake, fake, None) == hf.FMM_ERR_ARG
+    # the recorded evaluation refuses a missing tree and bad parameters before any GPU call
+    prm.theta = 0.5
+    assert L.fmm_short_range_forces_graph(None, C.byref(prm), fake, fake) == hf.FMM_ERR_ARG
+    prm.theta = 0.0
+    assert L.fmm_short_range_forces_graph(fake, C.byref(prm), fake, fake) == hf.FMM_ERR_ARG

@@ -1,0 +1,79 @@
+"""The recorded (HIP graph) short-range evaluation: every replay equals the eager
+evaluation of the same tree, with the program's own eager work and synchronisations
+between replays; a rebuilt tree is recorded again; a forest of boxes replays as well."""
+import numpy as np
+import pytest
+
+from paper_2006_14952_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+hf = pytest.importorskip("paper_2006_14952_amd")
+
+
+def dev(x):
+    return torch.tensor(np.ascontiguousarray(x), device="cuda")
+
+
+def _close(got, ref, rtol):
+    # FP32 M2L partial sums are added with atomics in a run-dependent order: rounding level
+    np.testing.assert_allclose(got, ref, rtol=rtol, atol=rtol * 1e-3 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_replays_equal_the_eager_evaluation(precision):
+    pos, m = inputs.clustered(30000, 12, inputs.rng_for(401, precision))
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.4, p=5, n_crit=32, precision=precision)
+    rtol = 2e-5 if precision else 1e-11
+    print("case: recorded evaluation, precision", precision, flush=True)
+    t = hf.Tree().build(dev(pos), dev(m), prm)
+    ref = t.short_range(prm).cpu().numpy()
+    st_ref = t.stats()
+    out = torch.empty((len(pos), 3), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()  # a created stream of default priority (the null stream cannot be recorded)
+    for rep in range(4):  # first call records, the others replay
+        out.fill_(np.nan)  # eager work between replays
+        torch.cuda.synchronize()
+        t.short_range_graph(prm, out=out, stream=s)
+        torch.cuda.synchronize()
+        _close(out.cpu().numpy(), ref, rtol)
+        st = t.stats()
+        assert st["n_m2l"] == st_ref["n_m2l"] and st["n_p2p"] == st_ref["n_p2p"]
+        assert st["p2p_pairs"] == st_ref["p2p_pairs"] and st["p2p_evaluated"] == st_ref["p2p_evaluated"]
+    # a rebuilt tree (other positions) is recorded again
+    pos2, m2 = inputs.clustered(24000, 9, inputs.rng_for(402, precision))
+    t.build(dev(pos2), dev(m2), prm)
+    ref2 = t.short_range(prm).cpu().numpy()
+    out2 = torch.empty((len(pos2), 3), dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        t.short_range_graph(prm, out=out2, stream=s)
+        torch.cuda.synchronize()
+        _close(out2.cpu().numpy(), ref2, rtol)
+    t.free()
+
+
+def test_forest_replays_and_rejects_the_learned_selector():
+    rng = inputs.rng_for(403)
+    sizes = [int(round(2 ** rng.uniform(10, 14))) for _ in range(6)]
+    boxes = [inputs.clustered(nb, max(1, nb // 2000), inputs.rng_for(403, b)) for b, nb in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate([b[0] for b in boxes])
+    m = np.concatenate([b[1] for b in boxes])
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=16, precision=1)
+    print("case: recorded forest of", len(sizes), "boxes", flush=True)
+    t = hf.Tree().build_batched(dev(pos), dev(m), [prm] * len(sizes), off)
+    ref = t.short_range(prm).cpu().numpy()
+    out = torch.empty((len(pos), 3), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        t.short_range_graph(prm, out=out, stream=s)
+        torch.cuda.synchronize()
+        _close(out.cpu().numpy(), ref, 2e-5)
+    lp = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=16, precision=1, learned=1)
+    with pytest.raises(hf.FMMError):
+        t.short_range_graph(lp, out=out, stream=s)
+    with pytest.raises(hf.FMMError):  # the null stream cannot be recorded
+        t.short_range_graph(prm, out=out, stream=0)
+    t.free()
