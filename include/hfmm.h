@@ -118,7 +118,8 @@ int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc
 /* The same evaluation as fmm_short_range_forces, recorded once as a HIP graph and then
  * replayed, for callers that evaluate one built tree (one box or a forest of boxes)
  * repeatedly: a replay is one hipGraphLaunch on `stream`, with no host synchronisation.
- * The first call on a tree, and any call after the tree is rebuilt or with other params,
+ * The first call on a tree, and any call after the tree is rebuilt, after any library
+ * buffer was reallocated (e.g. by an eager call with a higher order), or with other params,
  * acc or stream, runs the evaluation eagerly (its result is this call's result) and then
  * records the same stages, on `stream` and the tree's second stream, into a graph the
  * tree owns (freed by fmm_free_tree or replaced on the next recording).  A replay reuses

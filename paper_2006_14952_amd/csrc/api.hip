@@ -252,9 +252,18 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     hipStream_t st = (hipStream_t)stream;
     if (!st) return set_error(FMM_ERR_ARG, "the recorded form needs a created stream, not the null stream");
     if (t->n == 0) return 0;
-    if (t->gexec && t->gserial == t->build_serial && same_params(t->gparams, *P) && t->gacc == acc &&
-        t->gstream == st)
+    // replay only while every buffer the graph uses is where it was recorded: no rebuild,
+    // and no reallocation since (an eager call with other parameters may grow a buffer)
+    if (t->gexec && t->gserial == t->build_serial && t->gmoves == buffer_moves() && same_params(t->gparams, *P) &&
+        t->gacc == acc && t->gstream == st) {
+        t->n_m2l = t->g_n_m2l;  // the counts of the recorded evaluation, which the replay repeats
+        t->n_p2p = t->g_n_p2p;
+        t->n_visit = t->g_n_visit;
+        t->stats.n_m2l = t->n_m2l;
+        t->stats.n_p2p = t->n_p2p;
+        t->stats.n_visit = t->n_visit;
         return hip_check(hipGraphLaunch(t->gexec, st), "graph launch");
+    }
     if (t->gexec) {
         (void)hipGraphExecDestroy(t->gexec);
         t->gexec = nullptr;
@@ -284,6 +293,10 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     t->gacc = acc;
     t->gstream = st;
     t->gserial = t->build_serial;
+    t->gmoves = buffer_moves();
+    t->g_n_m2l = t->n_m2l;
+    t->g_n_p2p = t->n_p2p;
+    t->g_n_visit = t->n_visit;
     return 0;
 }
 

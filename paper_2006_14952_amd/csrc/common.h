@@ -77,6 +77,7 @@ struct DevBuf {
 };
 
 int grow(DevBuf &b, size_t bytes);                    // 0 or FMM_ERR_NOMEM; content is lost
+uint64_t buffer_moves();  // reallocations by grow() so far (process-wide): recorded graphs check it
 int grow_keep(DevBuf &b, size_t bytes, size_t used);  // keeps the first `used` bytes
 template <class T> inline T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
 

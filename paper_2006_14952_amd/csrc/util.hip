@@ -2,6 +2,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <atomic>
+
 #include "common.h"
 
 namespace hfmm {
@@ -26,9 +28,13 @@ int hip_check(hipError_t e, const char *what)
     return set_error(FMM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+static std::atomic<uint64_t> g_moves{0};
+uint64_t buffer_moves() { return g_moves.load(std::memory_order_relaxed); }
+
 int grow(DevBuf &b, size_t bytes)
 {
     if (bytes <= b.bytes) return 0;
+    g_moves.fetch_add(1, std::memory_order_relaxed);  // a recorded graph may hold the old address
     size_t want = bytes + bytes / 4 + 256;
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {

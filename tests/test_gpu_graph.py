@@ -40,6 +40,19 @@ def test_replays_equal_the_eager_evaluation(precision):
         st = t.stats()
         assert st["n_m2l"] == st_ref["n_m2l"] and st["n_p2p"] == st_ref["n_p2p"]
         assert st["p2p_pairs"] == st_ref["p2p_pairs"] and st["p2p_evaluated"] == st_ref["p2p_evaluated"]
+    # an eager call with other parameters grows buffers the graph uses (order 8 expansions):
+    # the next recorded call must record again, and its counts are those of its own evaluation
+    prm8 = hf.params(r_s=0.012, r_cut=0.054, theta=0.5, p=8, n_crit=32, precision=precision)
+    t.short_range(prm8)
+    st8 = t.stats()
+    assert st8["n_m2l"] != st_ref["n_m2l"]
+    for rep in range(2):
+        out.fill_(np.nan)
+        torch.cuda.synchronize()
+        t.short_range_graph(prm, out=out, stream=s)
+        torch.cuda.synchronize()
+        _close(out.cpu().numpy(), ref, rtol)
+        assert t.stats()["n_m2l"] == st_ref["n_m2l"]
     # a rebuilt tree (other positions) is recorded again
     pos2, m2 = inputs.clustered(24000, 9, inputs.rng_for(402, precision))
     t.build(dev(pos2), dev(m2), prm)
