@@ -123,10 +123,11 @@ int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc
  * acc or stream, runs the evaluation eagerly (its result is this call's result) and then
  * records the same stages, on `stream` and the tree's second stream, into a graph the
  * tree owns (freed by fmm_free_tree or replaced on the next recording).  A replay reuses
- * the recorded list sizes: they repeat exactly on an unchanged tree.  Plain MAC only
- * (params->learned = 1: FMM_ERR_ARG); `stream` must be a created stream (the null
- * stream cannot be recorded: FMM_ERR_ARG).  Errors as fmm_short_range_forces; a failed
- * recording (FMM_ERR_HIP) leaves no graph behind and the eager result stands. */
+ * the recorded list sizes: they repeat exactly on an unchanged tree.  With the learned
+ * selector, loading or clearing a model also makes the next call record again.  `stream`
+ * must be a created stream (the null stream cannot be recorded: FMM_ERR_ARG).  Errors
+ * as fmm_short_range_forces; a failed recording (FMM_ERR_HIP) leaves no graph behind and
+ * the eager result stands. */
 int fmm_short_range_forces_graph(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
 
 /* Long-range accelerations by the particle-mesh method with a mesh of mesh^3 cells

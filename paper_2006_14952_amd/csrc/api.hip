@@ -16,6 +16,7 @@ int pm_forces(const fmm_params *P, int mesh, int64_t n, const double *pos, const
 int add_into(double *acc, const double *other, int64_t n3, hipStream_t st);
 int pm_forces_tree(const fmm_params *P, int mesh, fmm_tree *t, double *acc, hipStream_t st);
 const MacModel *current_model(MacModel *host_copy);
+uint64_t model_serial();
 int run_labels(fmm_tree *t, const fmm_params *P, const double *aref_sorted, double eps, int stride, float *feats,
                int *labels, float *errs, uint64_t *pairs, int cap, int *dcounter, hipStream_t st);
 int sort_soa(fmm_tree *t, const double *acc, double *out, hipStream_t st);
@@ -247,7 +248,6 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     if (int rc = check_params(P)) return rc;
     if (P->box != t->box || P->n_crit != t->ncrit)
         return set_error(FMM_ERR_STATE, "box / n_crit differ from the values the tree was built with");
-    if (P->learned) return set_error(FMM_ERR_ARG, "the recorded form takes the plain MAC (learned = 0)");
     if (t->n > 0 && !acc) return set_error(FMM_ERR_ARG, "acc is NULL");
     hipStream_t st = (hipStream_t)stream;
     if (!st) return set_error(FMM_ERR_ARG, "the recorded form needs a created stream, not the null stream");
@@ -255,7 +255,8 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     // replay only while every buffer the graph uses is where it was recorded: no rebuild,
     // and no reallocation since (an eager call with other parameters may grow a buffer)
     if (t->gexec && t->gserial == t->build_serial && t->gmoves == buffer_moves() && same_params(t->gparams, *P) &&
-        t->gacc == acc && t->gstream == st) {
+        t->gacc == acc && t->gstream == st && (!P->learned || t->gmodel == model_serial())) {
+        for (int o = 0; o < kOrders; ++o) t->stats.n_m2l_by_order[o] = t->g_by_order[o];
         t->n_m2l = t->g_n_m2l;  // the counts of the recorded evaluation, which the replay repeats
         t->n_p2p = t->g_n_p2p;
         t->n_visit = t->g_n_visit;
@@ -294,6 +295,8 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     t->gstream = st;
     t->gserial = t->build_serial;
     t->gmoves = buffer_moves();
+    t->gmodel = model_serial();  // the selector's weights and theta_max are part of the recording
+    for (int o = 0; o < kOrders; ++o) t->g_by_order[o] = t->stats.n_m2l_by_order[o];
     t->g_n_m2l = t->n_m2l;
     t->g_n_p2p = t->n_p2p;
     t->g_n_visit = t->n_visit;

@@ -23,6 +23,13 @@ static std::mutex g_model_mu;
 static MacModel g_hmodel;
 static MacModel *g_dmodel = nullptr;
 static bool g_have_model = false;
+static uint64_t g_model_serial = 0;  // changes with every model set or cleared
+
+uint64_t model_serial()
+{
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    return g_model_serial;
+}
 
 const MacModel *current_model(MacModel *host_copy)
 {
@@ -218,6 +225,7 @@ int fmm_set_mac_model(const float *params, const float *mu, const float *isd, do
     if (!params || !mu || !isd) {
         std::lock_guard<std::mutex> lk(g_model_mu);
         g_have_model = false;
+        ++g_model_serial;
         return 0;
     }
     if (!(theta_max > 0) || !(theta_max < 0.75)) return set_error(FMM_ERR_ARG, "theta_max must be in (0, 0.75)");
@@ -233,6 +241,7 @@ int fmm_set_mac_model(const float *params, const float *mu, const float *isd, do
         return set_error(FMM_ERR_HIP, "model upload");
     g_hmodel = M;
     g_have_model = true;
+    ++g_model_serial;
     return 0;
 }
 

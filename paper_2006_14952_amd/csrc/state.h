@@ -78,6 +78,8 @@ struct fmm_tree {
     hipStream_t gstream = nullptr;
     uint64_t build_serial = 0, gserial = 0, gmoves = 0;
     int64_t g_n_m2l = 0, g_n_p2p = 0, g_n_visit = 0;  // the recorded evaluation's counts
+    int64_t g_by_order[hfmm::kOrders] = {0};
+    uint64_t gmodel = 0;                              // selector model the graph was recorded with
     bool capturing = false;  // run_forces is being recorded: no host reads, no timing
 
     // timing

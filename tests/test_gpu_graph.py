@@ -65,7 +65,7 @@ def test_replays_equal_the_eager_evaluation(precision):
     t.free()
 
 
-def test_forest_replays_and_rejects_the_learned_selector():
+def test_forest_replays():
     rng = inputs.rng_for(403)
     sizes = [int(round(2 ** rng.uniform(10, 14))) for _ in range(6)]
     boxes = [inputs.clustered(nb, max(1, nb // 2000), inputs.rng_for(403, b)) for b, nb in enumerate(sizes)]
@@ -84,9 +84,32 @@ def test_forest_replays_and_rejects_the_learned_selector():
         t.short_range_graph(prm, out=out, stream=s)
         torch.cuda.synchronize()
         _close(out.cpu().numpy(), ref, 2e-5)
-    lp = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=16, precision=1, learned=1)
-    with pytest.raises(hf.FMMError):
-        t.short_range_graph(lp, out=out, stream=s)
     with pytest.raises(hf.FMMError):  # the null stream cannot be recorded
         t.short_range_graph(prm, out=out, stream=0)
+    t.free()
+
+
+def test_learned_selector_replays():
+    from paper_2006_14952_amd import learned
+    learned.load_model()
+    pos, m = inputs.clustered(40000, 16, inputs.rng_for(404))
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.5, p=8, n_crit=32, precision=1, learned=1)
+    print("case: recorded evaluation with the learned selector", flush=True)
+    t = hf.Tree().build(dev(pos), dev(m), prm)
+    ref = t.short_range(prm).cpu().numpy()
+    by_order = t.stats()["n_m2l_by_order"]
+    assert sum(by_order) > 0
+    out = torch.empty((len(pos), 3), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    for rep in range(3):
+        out.fill_(np.nan)
+        torch.cuda.synchronize()
+        t.short_range_graph(prm, out=out, stream=s)
+        torch.cuda.synchronize()
+        _close(out.cpu().numpy(), ref, 2e-5)
+        assert t.stats()["n_m2l_by_order"] == by_order
+    learned.load_model()  # a model load (same file) makes the next call record again
+    t.short_range_graph(prm, out=out, stream=s)
+    torch.cuda.synchronize()
+    _close(out.cpu().numpy(), ref, 2e-5)
     t.free()
