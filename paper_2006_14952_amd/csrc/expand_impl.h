@@ -475,6 +475,12 @@ __global__ __launch_bounds__(64) void k_m2m_axis(const Cell *__restrict__ cells,
     const int nch = cell_nchild(cc);
     if (nch == 0) return;
     T *out = M + (size_t)c * NC;
+    // FP32: the sum over the children is kept in this thread's LDS row (odd stride NC, no
+    // bank conflicts) and written once, instead of a read-modify-write of the parent's
+    // coefficients in global memory per child
+    constexpr bool kLds = sizeof(T) == 4;
+    __shared__ T accs[kLds ? 64 * NC : 1];
+    T *acc = kLds ? accs + threadIdx.x * NC : out;
     for (int q = 0; q < nch; ++q) {
         const int ch = cc.child + q;
         const Cell cq = cells[ch];
@@ -490,11 +496,15 @@ __global__ __launch_bounds__(64) void k_m2m_axis(const Cell *__restrict__ cells,
         shift_axis<P, T, 2, true>(C, wz);
         if (q == 0) {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) out[k] = C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
+            for (int k = 0; k < NC; ++k) acc[k] = C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
         } else {
 #pragma unroll
-            for (int k = 0; k < NC; ++k) out[k] += C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
+            for (int k = 0; k < NC; ++k) acc[k] += C[k] * (T)(1.0 / (double)(1 << tb.d[k]));
         }
+    }
+    if constexpr (kLds) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) out[k] = acc[k];
     }
 }
 
