@@ -122,8 +122,11 @@ int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc
  * buffer was reallocated (e.g. by an eager call with a higher order), or with other params,
  * acc or stream, runs the evaluation eagerly (its result is this call's result) and then
  * records the same stages, on `stream` and the tree's second stream, into a graph the
- * tree owns (freed by fmm_free_tree or replaced on the next recording).  A replay reuses
- * the recorded list sizes: they repeat exactly on an unchanged tree.  With the learned
+ * tree owns (freed by fmm_free_tree or replaced on the next recording).  The graph
+ * writes the acc it was recorded with: keep that buffer allocated while replaying.  A
+ * replay reuses the recorded list sizes (they repeat exactly on an unchanged tree);
+ * fmm_get_stats after a replay reports those counts and the replay's own pair
+ * counters.  With the learned
  * selector, loading or clearing a model also makes the next call record again.  `stream`
  * must be a created stream (the null stream cannot be recorded: FMM_ERR_ARG).  Errors
  * as fmm_short_range_forces; a failed recording (FMM_ERR_HIP) leaves no graph behind and
