@@ -58,7 +58,10 @@ extern "C" {
  *             baseline of the cost comparison of Sec. 3 (item 2 alone: no neglect beyond
  *             r_cut, no forced opening across it; forces stay correct, at higher cost)
  *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
- *             compensated per-particle sums, FP64 positions, cell offsets and final sum
+ *             compensated per-particle sums, FP64 positions, cell offsets and final sum;
+ *             with split 0 the FP32 pair force uses a fitted polynomial whose degree (10, 14
+ *             or 16) is chosen for r_cut / r_s, and r_cut beyond about 8 r_s is rejected
+ *             (FMM_ERR_ARG) as no degree meets the FP32 tolerance there
  *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see
  *             fmm_load_mac_model), the plain MAC's hard rules still apply
  *   split     0: the Gaussian (erfc) split of Sec. 2.2 with scale r_s, hard cut at r_cut;
@@ -103,7 +106,10 @@ typedef struct fmm_tree fmm_tree; /* opaque; owned by the library */
  * pos (n,3) and mass (n) stay owned by the caller and must not change before the
  * forces are computed.  *out receives a new tree, or an existing tree passed in *out
  * is reused (its device memory only grows).  Uses params->box and params->n_crit.
- * Synchronises the stream (level sizes are read back).  n = 0 is allowed. */
+ * Synchronises the stream (level sizes are read back).  n = 0 is allowed, n <= 2^30.
+ * A tree of 2^27 cells or more is rejected with FMM_ERR_ARG (interaction-list entries
+ * address cells with 27 bits; a larger n_crit gives fewer cells); the tree passed in
+ * *out is then left empty. */
 int fmm_build_tree(const fmm_params *params, int64_t n, const double *pos, const double *mass, void *stream,
                    fmm_tree **out);
 
@@ -252,8 +258,9 @@ int fmm_mlp_infer(const float *X, int B, float *logits, void *stream);
 int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const float *X, const int *y,
                  const float *class_w, int B, float *grad, float *loss, void *stream);
 
-/* One Adam step (DEVICE params, grad, m, v of 5768 floats), step >= 1 (bias correction),
- * decoupled weight decay weight_decay * params added to the gradient. */
+/* One Adam step (DEVICE params, grad, m, v of 5768 floats), step >= 1 (bias correction).
+ * weight_decay is a coupled L2 term: weight_decay * params is added to the gradient before
+ * the moment updates (as torch.optim.Adam's weight_decay), not a decoupled (AdamW) decay. */
 int fmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
                  float beta2, float eps, float weight_decay, void *stream);
 

@@ -28,8 +28,12 @@
  *   - MAC item 3 "transition region": default STRICT reading (open while the pair's
  *     maximum distance exceeds r_cut and its minimum distance does not); mac_mode 1
  *     takes the literal S_c > r_cut > S_m test.
- *   - theta = L / S_c, accepted at equality; L is the larger side of the two cells by
- *     default (mac_mode bit 1 takes the source side only, as worded in Sec. 2.3).
+ *   - theta = L / S_c, accepted at equality.
+ * Departure from the paper (not a reading): Sec. 2.3 defines L = L_B, the side of the
+ * source cell; by default L here is the larger side of the two cells, because with L_B
+ * alone a large leaf sink meets tiny adjacent sources whose local expansions do not
+ * converge in p.  mac_mode bit 1 restores the paper's L_B (with bit 0 as well, the MAC
+ * exactly as printed).
  *   - mac_mode bit 2: the conventional MAC the cost comparison of Sec. 3 measures against:
  *     item 2 alone decides (no neglect beyond r_cut, no forced opening across it).
  *   - Periodicity: 27 root images; r_cut < box/2 makes the image of any pair unique.
@@ -681,8 +685,8 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
     orc_mac mac; mac_setup(P, &mac);
     if (n > 0)
         for (int s = 0; s < 27; ++s) traverse(S, &mac, 0, 0, s);
-    qsort(S->m2l.v, (size_t)S->m2l.n, sizeof(opair), cmp_pair);
-    qsort(S->p2p.v, (size_t)S->p2p.n, sizeof(opair), cmp_pair);
+    if (S->m2l.n) qsort(S->m2l.v, (size_t)S->m2l.n, sizeof(opair), cmp_pair);  /* an empty list has no array */
+    if (S->p2p.n) qsort(S->p2p.v, (size_t)S->p2p.n, sizeof(opair), cmp_pair);
 
     /* M2L grouped by sink (lists sorted by sink) */
     {

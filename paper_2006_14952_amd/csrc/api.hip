@@ -20,6 +20,7 @@ uint64_t model_serial();
 int run_labels(fmm_tree *t, const fmm_params *P, const double *aref_sorted, double eps, int stride, float *feats,
                int *labels, float *errs, uint64_t *pairs, int cap, int *dcounter, hipStream_t st);
 int sort_soa(fmm_tree *t, const double *acc, double *out, hipStream_t st);
+int p2p_setup(const fmm_params *P, P2PConst &k);
 }  // namespace hfmm
 
 using namespace hfmm;
@@ -39,6 +40,10 @@ static int check_params(const fmm_params *P)
     if (P->learned != 0 && P->learned != 1) return set_error(FMM_ERR_ARG, "learned must be 0 or 1");
     if (P->split != 0 && P->split != 1) return set_error(FMM_ERR_ARG, "split must be 0 or 1");
     if (P->learned && P->split) return set_error(FMM_ERR_ARG, "the learned selector requires split 0");
+    if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
+        P2PConst k;
+        if (int rc = p2p_setup(P, k)) return rc;
+    }
     return 0;
 }
 

@@ -50,10 +50,15 @@ struct MacConst {
 
 // Interaction lists are chains of kChunk-entry chunks (entry = source cell << 5 | image).
 constexpr int kChunk = 64;
+// A list entry keeps 27 bits for the cell index: a tree holds fewer cells than this.
+constexpr int kMaxCells = 1 << 27;
 
 // Per-call constants of the P2P force law in FP32: f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),
-// t = 2 r^2 / r_cut^2 - 1, S a degree-10 polynomial fitted on the host.
-constexpr int kP2PPoly = 11;
+// t = 2 r^2 / r_cut^2 - 1, S a polynomial fitted on the host: of degree 10, 14 or 16, the
+// lowest whose error in r^3 f_(1) stays below kP2PFitTol over [0, r_cut] (checked on the
+// host at every fit; degree 10 serves r_cut up to about 5 r_s, 16 up to about 8 r_s).
+constexpr int kP2PPolyMax = 17;
+constexpr double kP2PFitTol = 1.0e-6;
 // The short range's truncation function: kind 0 the Gaussian split (scale = r_s), kind 1
 // the polynomial split g(r/r_cut)/r (scale = r_cut).
 struct Split {
@@ -62,8 +67,9 @@ struct Split {
 };
 
 struct P2PConst {
-    float c[kP2PPoly];  // S(t) / (8 r_s^3), coefficients of t^0 .. t^(kP2PPoly-1)
-    int split;          // 0: Gaussian split; 1: polynomial split (c[0] = 1 / r_cut, see p2p_setup)
+    float c[kP2PPolyMax];  // S(t) / (8 r_s^3), coefficients of t^0 .. t^(ncoef-1)
+    int ncoef;             // 11, 15 or 17
+    int split;             // 0: Gaussian split; 1: polynomial split (c[0] = 1 / r_cut, see p2p_setup)
     float two_over_rc2;
     float rc2;
     double rs, rc2d;

@@ -13,13 +13,15 @@
 // centre offset c_B + s box - c_A added when staging, and
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
-// degree-10 polynomial fitted on the host (its coefficients carry the factor 1/(8 r_s^3));
+// polynomial of degree 10, 14 or 16 fitted on the host, the lowest that meets the FP32
+// tolerance at this r_cut / r_s (its coefficients carry the factor 1/(8 r_s^3));
 // the sum of each staged block is added to a Kahan-compensated per-particle accumulator.
 // A listed source leaf whose particles' bounding box lies farther than r_cut from the sink
 // leaf's box, and any single source particle farther than r_cut from that box, hold no
 // pair inside the cutoff and are not staged (the lists themselves are unchanged).
 #include <math.h>
 
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -93,7 +95,7 @@ constexpr int kStage = 256;
 // POLY (FP32 form, polynomial split): f_(1) = -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5) evaluated
 // as -(1-x)^2 (1 + 2x + 3x^2 + 3x^3/2) / r^3, x = r / r_c: the three terms cancel near r_cut
 // in FP32, the factored form does not.
-template <bool F64, bool POLY>
+template <bool F64, bool POLY, int NPC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
 {
     using R = typename std::conditional<F64, double, float>::type;
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5)
                         float px = 0, py = 0, pz = 0;
                         // the leading coefficient as a vector operand: each Horner step then
                         // reads a single scalar
-                        float clead = k.c[kP2PPoly - 1];
+                        float clead = k.c[NPC - 1];
                         asm volatile("" : "+v"(clead));
                         auto pair = [&](const float4 s) __attribute__((always_inline)) {
                             const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5)
                                 const float t = fmaf(r2, k.two_over_rc2, -1.0f);
                                 float S = clead;  // S(t) / (8 r_s^3)
 #pragma unroll
-                                for (int c = kP2PPoly - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
+                                for (int c = NPC - 2; c >= 0; --c) S = fmaf(S, t, k.c[c]);
                                 f1 = fmaf(-rinv * rinv, rinv, S);
                             }
                             const float w = r2 < k.rc2 ? s.w * f1 : 0.0f;
@@ -366,11 +368,11 @@ static double S_of_v(double v)
     return (erf(u) - 2.0 * u / sqrt(M_PI) * exp(-v)) / (u * u * u);
 }
 
-void p2p_setup(const fmm_params *P, P2PConst &k)
+// Interpolation of S at the m Chebyshev points of t in [-1, 1] (solved in FP64), the
+// coefficients of t^0 .. t^(m-1) returned in FP64.
+static void fit_S(double vcut, int m, double *coef)
 {
-    const int m = kP2PPoly;
-    double vcut = (P->r_cut * P->r_cut) / (4.0 * P->r_s * P->r_s);
-    double Amat[kP2PPoly][kP2PPoly + 1];
+    double Amat[kP2PPolyMax][kP2PPolyMax + 1];
     for (int i = 0; i < m; ++i) {
         double t = cos(M_PI * (i + 0.5) / m);
         double v = (t + 1.0) * 0.5 * vcut;
@@ -389,18 +391,67 @@ void p2p_setup(const fmm_params *P, P2PConst &k)
             for (int j = c; j <= m; ++j) Amat[r][j] -= f * Amat[c][j];
         }
     }
+    for (int j = 0; j < m; ++j) coef[j] = Amat[j][m] / Amat[j][j];
+}
+
+// Largest error of the fit, with its coefficients rounded to FP32, in r^3 f_(1) = S u^3 - 1
+// (u = r / 2 r_s): the pair force's error relative to the Newtonian one, on 4001 points.
+static double fit_error(double vcut, int m, const double *coef)
+{
+    double worst = 0.0;
+    for (int i = 0; i <= 4000; ++i) {
+        const double t = -1.0 + i / 2000.0, v = (t + 1.0) * 0.5 * vcut;
+        double S = (double)(float)coef[m - 1];
+        for (int j = m - 2; j >= 0; --j) S = S * t + (double)(float)coef[j];
+        const double e = fabs(S - S_of_v(v)) * v * sqrt(v);
+        worst = e > worst ? e : worst;
+    }
+    return worst;
+}
+
+// FP32 force-law constants.  Gaussian split: the lowest polynomial length of 11, 15 and 17
+// whose checked error is at most kP2PFitTol; returns FMM_ERR_ARG if none is (r_cut beyond
+// about 8 r_s).  The last fit is cached (same vcut, same result).
+int p2p_setup(const fmm_params *P, P2PConst &k)
+{
+    static std::mutex mu;
+    static double cached_vcut = -1.0;
+    static int cached_m = 0;
+    static double cached[kP2PPolyMax];
+    const double vcut = (P->r_cut * P->r_cut) / (4.0 * P->r_s * P->r_s);
+    double coef[kP2PPolyMax] = {0};
+    int m = 0;
+    if (P->split == 0) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (vcut != cached_vcut) {
+            cached_m = 0;
+            for (int mm : {11, 15, 17}) {
+                fit_S(vcut, mm, cached);
+                if (fit_error(vcut, mm, cached) <= kP2PFitTol) {
+                    cached_m = mm;
+                    break;
+                }
+            }
+            cached_vcut = vcut;
+        }
+        m = cached_m;
+        for (int j = 0; j < m; ++j) coef[j] = cached[j];
+        if (m == 0)
+            return set_error(FMM_ERR_ARG, "precision 1 supports r_cut up to about 8 r_s (r_cut / r_s = %.3g: no "
+                                          "polynomial of degree <= 16 meets the FP32 force-law tolerance)",
+                             P->r_cut / P->r_s);
+    }
     // the kernel evaluates S(t) / (8 r_s^3): the factor is folded into the coefficients
     const double inv8rs3 = 1.0 / (8.0 * P->r_s * P->r_s * P->r_s);
-    for (int j = 0; j < m; ++j) k.c[j] = (float)(Amat[j][m] / Amat[j][j] * inv8rs3);
+    for (int j = 0; j < kP2PPolyMax; ++j) k.c[j] = j < m ? (float)(coef[j] * inv8rs3) : 0.0f;
+    k.ncoef = m > 0 ? m : 11;
     k.split = P->split;
-    if (P->split == 1) {  // polynomial split: the FP32 kernel needs 1 / r_cut only
-        for (int j = 0; j < m; ++j) k.c[j] = 0.0f;
-        k.c[0] = (float)(1.0 / P->r_cut);
-    }
+    if (P->split == 1) k.c[0] = (float)(1.0 / P->r_cut);  // polynomial split: the FP32 kernel needs 1 / r_cut only
     k.two_over_rc2 = (float)(2.0 / (P->r_cut * P->r_cut));
     k.rc2 = (float)(P->r_cut * P->r_cut);
     k.rs = P->r_s;
     k.rc2d = P->r_cut * P->r_cut;
+    return 0;
 }
 
 // The FP32 form's leaf bounding boxes (they depend on the tree only).
@@ -417,7 +468,7 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
     if (t->nleaf == 0) return 0;
     P2PConst k;
-    p2p_setup(P, k);
+    if (int rc = p2p_setup(P, k)) return rc;
     P2PArgs a;
     a.cells = ptr<Cell>(t->cells);
     a.leaves = ptr<int>(t->leaves);
@@ -441,9 +492,11 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
         if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
         a.bbox = ptr<float4>(t->bbox);
     }
-    if (P->precision && P->split == 1) k_p2p<false, true><<<t->nleaf, 64, 0, st>>>(a, k);
-    else if (P->precision) k_p2p<false, false><<<t->nleaf, 64, 0, st>>>(a, k);
-    else k_p2p<true, false><<<t->nleaf, 64, 0, st>>>(a, k);
+    if (P->precision && P->split == 1) k_p2p<false, true, 11><<<t->nleaf, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 17) k_p2p<false, false, 17><<<t->nleaf, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<t->nleaf, 64, 0, st>>>(a, k);
+    else if (P->precision) k_p2p<false, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);
+    else k_p2p<true, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");
 }
 

@@ -462,6 +462,15 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     for (int l = 0; l <= launched && hl[l + 1] > hl[l]; ++l) t->lvl_beg.push_back(hl[l + 1]);
     t->nlevel = (int)t->lvl_beg.size() - 1;
     t->ncell = t->lvl_beg.back();
+    if (t->ncell >= kMaxCells) {  // interaction-list entries hold the cell index in 27 bits
+        const int nc = t->ncell;
+        t->n = 0;  // the tree is unusable: later calls see an empty tree, never aliased entries
+        t->ncell = t->nleaf = t->nlevel = 0;
+        t->lvl_beg.assign(1, 0);
+        t->stats.n = t->stats.n_cells = t->stats.n_leaves = t->stats.max_level = 0;
+        return set_error(FMM_ERR_ARG, "octree of %d cells exceeds the %d cells an interaction-list entry can "
+                                      "address (raise n_crit)", nc, kMaxCells - 1);
+    }
     if (n == 0) {
         t->nleaf = 0;
         return hip_check(hipStreamSynchronize(st), "tree");

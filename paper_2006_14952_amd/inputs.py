@@ -114,7 +114,10 @@ CONFIGS = {
     "large": dict(n=256 ** 3, mesh=256, p=8, theta=0.5, precision=1, kind="clustered", clumps=8000),
     "full": dict(n=512 ** 3, mesh=512, p=8, theta=0.5, precision=1, kind="full", clumps=32000),
 }
-CONFIG_INDEX = {"uniform": 0, "clustered": 1, "batched": 2, "large": 3, "full": 4}
+# Seeds: workload k (1 .. 5, in the order above) draws from default_rng([2006_14952, k]);
+# box b of the batched workload from default_rng([2006_14952, 3, b]), its sizes from
+# default_rng([2006_14952, 3]).
+CONFIG_INDEX = {"uniform": 1, "clustered": 2, "batched": 3, "large": 4, "full": 5}
 
 
 def split_params(name):

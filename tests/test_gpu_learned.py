@@ -1,5 +1,5 @@
 """GPU checks of the learned acceptance / order selector: training kernels against an
-FP64 backpropagation reference and finite differences, BF16 MFMA inference against a
+FP64 backpropagation reference, BF16 MFMA inference against a
 BF16-rounded reference, and the label generator against the oracle's own expansions."""
 import os
 
@@ -31,21 +31,15 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
 
 
-def test_mlp_gradient_matches_fp64_backprop_and_finite_differences():
+def test_mlp_gradient_matches_fp64_backprop():
     X, y, w, mu, isd, cw = _batch(300, 1)
     loss, g = learned.grad(_dev(w), _dev(mu), _dev(isd), _dev(X), _dev(y), _dev(cw))
     lref, gref = omlp.loss_and_grad(w.astype(np.float64), X, y, cw, mu, isd)
     assert abs(loss - lref) < 1e-5 * max(1.0, abs(lref))
     g = g.cpu().numpy()
     np.testing.assert_allclose(g, gref, rtol=2e-3, atol=2e-6 * np.abs(gref).max())
-    rng = np.random.default_rng(2)
-    for p in rng.choice(5768, 12, replace=False):
-        h = 1e-6  # small enough not to straddle ReLU kinks in practice
-        wp, wm = w.astype(np.float64).copy(), w.astype(np.float64).copy()
-        wp[p] += h
-        wm[p] -= h
-        fd = (omlp.loss_and_grad(wp, X, y, cw, mu, isd)[0] - omlp.loss_and_grad(wm, X, y, cw, mu, isd)[0]) / (2 * h)
-        assert abs(fd - gref[p]) < 1e-7 + 2e-4 * abs(gref[p])
+    # the reference itself is pinned on the CPU (tests/test_mlp_oracle.py): torch autograd,
+    # torch.optim.Adam, torch's bfloat16 rounding and central finite differences
 
 
 def test_adam_matches_reference():

@@ -112,13 +112,47 @@ def test_clustered_midsize_fp64_and_fp32():
         assert np.percentile(rel_err(got, bf), 99) <= 1e-3
 
 
+@pytest.mark.parametrize("ratio", [5.0, 6.0, 7.5])
+def test_fp32_force_law_at_larger_cutoffs(ratio):
+    """The FP32 pair force is a polynomial fit whose degree the library raises with
+    r_cut / r_s (10 up to about 5 r_s, 14 up to about 7, 16 up to about 8): at cutoffs
+    beyond the workloads' 4.5 r_s the FP32 form must still meet the FP32 bar against the
+    FP64 oracle."""
+    rng = inputs.rng_for(108, int(ratio * 10))
+    pos, m = inputs.clustered(40000, 40, rng)
+    rs = 0.008
+    prm = hf.params(r_s=rs, r_cut=ratio * rs, theta=0.4, p=6, n_crit=32, precision=1)
+    got32, t = gpu_run(pos, m, prm)
+    t.free()
+    ref = oracle.fmm(pos, m, opar(prm)).acc
+    e32 = rel_err(got32, ref)
+    print("r_cut = %.1f r_s fp32 vs oracle: median %.2e p99 %.2e max %.2e" % (
+        ratio, np.median(e32), np.percentile(e32, 99), e32.max()))
+    assert np.median(e32) <= 1e-6 and np.percentile(e32, 99) <= 2e-5 and e32.max() <= 1e-3
+
+
+def test_fp32_rejects_cutoffs_beyond_the_fit():
+    pos, m = inputs.clustered(2000, 4, inputs.rng_for(109))
+    prm = hf.params(r_s=0.005, r_cut=0.05, theta=0.5, p=4, n_crit=16, precision=1)  # r_cut = 10 r_s
+    with pytest.raises(hf.FMMError) as ei:
+        gpu_run(pos, m, prm)
+    assert ei.value.code == hf.FMM_ERR_ARG and "r_cut" in str(ei.value)
+    prm.precision = 0  # the FP64 form has no such limit
+    got, t = gpu_run(pos, m, prm)
+    t.free()
+    assert rel_err(got, oracle.fmm(pos, m, opar(prm)).acc).max() < 1e-9
+
+
 def test_clustered_config_full_size_sampled():
-    """N = 128^3 clustered, p = 6, theta = 0.4, FP32 and FP64 forms at full size; the oracle
-    evaluates 1500 sampled particles exactly (only their sink cells are traversed)."""
+    """N = 128^3 clustered, p = 6, at the opening angle and leaf limit the benchmark times
+    for this box, FP32 and FP64 forms at full size; the oracle evaluates 1500 sampled
+    particles exactly (only their sink cells are traversed)."""
+    import bench
+    wl = bench.WORKLOADS["clustered"]
     pos, m = inputs.make("clustered")
     pr = inputs.split_params("clustered")
     tg = inputs.rng_for(1, 7).choice(len(pos), 1500, replace=False)
-    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=0.4, p=6, n_crit=32, precision=0)
+    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"], precision=0)
     got64, ref, e64 = check_fp64(pos, m, prm, lists=False, targets=tg)
     bf = oracle.bruteforce(pos, m, opar(prm), targets=tg)
     assert np.percentile(rel_err(got64[tg], bf), 99) <= 1e-3
@@ -186,6 +220,32 @@ def test_errors_reported():
     with pytest.raises(hf.FMMError) as ei:
         t.short_range(prm2)
     assert ei.value.code == hf.FMM_ERR_STATE
+
+
+def test_cell_count_limit_is_an_error_not_an_alias():
+    """List entries address cells with 27 bits.  A uniform box with leaves of one particle
+    has about 1.49 cells per particle: 96 Mi particles need about 150M cells (>= 2^27) and
+    must be rejected; the same tree object then builds 80 Mi particles (about 119M cells)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2006)
+    prm = hf.params(r_s=0.002, r_cut=0.009, theta=0.5, p=0, n_crit=1)
+    small = torch.rand((1000, 3), dtype=torch.float64, device="cuda", generator=g)
+    t = hf.Tree().build(small, torch.full((1000,), 1e-3, dtype=torch.float64, device="cuda"), prm)
+    n = 96 << 20
+    pos = torch.rand((n, 3), dtype=torch.float64, device="cuda", generator=g)
+    m = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    with pytest.raises(hf.FMMError) as ei:
+        t.build(pos, m, prm)
+    assert ei.value.code == hf.FMM_ERR_ARG and "cells" in str(ei.value)
+    assert t.stats()["n_cells"] == 0
+    n = 80 << 20
+    pos, m = pos[:n].contiguous(), torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
+    t.build(pos, m, prm)
+    st = t.stats()
+    assert 100_000_000 < st["n_cells"] < (1 << 27) and st["n_leaves"] == n
+    t.free()
+    del pos, m
+    torch.cuda.empty_cache()
 
 
 def test_tree_reuse_shrink_and_grow():

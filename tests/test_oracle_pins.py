@@ -391,7 +391,10 @@ def test_uniform_m2l_vanishes_only_with_the_truncated_mac():
     truncated MAC leaves no M2L at all (every surviving pair is handled by P2P, as in P3M),
     the conventional MAC needs many.  Here every leaf lies on one level, so the
     conventional MAC opens exactly the 27 adjacent leaves of each leaf (L / S_c = 1) and
-    accepts every pair two cells apart (L / S_c = 1/2 = theta)."""
+    accepts every pair two cells apart (L / S_c = 1/2 = theta).  The leaves are the
+    occupied cells of the 16^3 grid (counted here from the positions): the conventional
+    P2P count is the number of ordered pairs of occupied cells that are periodic
+    neighbours (each cell with itself included)."""
     pos, m = inputs.make("uniform")
     pr = inputs.split_params("uniform")
     kw = dict(rs=pr["rs"], rcut=pr["rcut"], theta=0.5, p=2, ncrit=32)
@@ -399,8 +402,16 @@ def test_uniform_m2l_vanishes_only_with_the_truncated_mac():
     cv = oracle.fmm(pos, m, oracle.make_params(mac_mode=4, **kw)).stats
     assert tr["n_m2l"] == 0 and tr["n_p2p"] > 0
     assert cv["n_m2l"] > 1000
-    assert cv["nleaf"] == 16 ** 3 and cv["maxlevel"] == 4
-    assert cv["n_p2p"] == 27 * cv["nleaf"]
+    c3 = np.bincount(np.ravel_multi_index(np.floor(pos * 8).astype(int).T, (8, 8, 8)), minlength=512)
+    assert c3.min() > 32  # every level-3 cell splits, no level-4 cell does (count <= 32 below)
+    c4 = np.bincount(np.ravel_multi_index(np.floor(pos * 16).astype(int).T, (16, 16, 16)),
+                     minlength=4096).reshape(16, 16, 16)
+    assert c4.max() <= 32
+    occ = c4 > 0
+    assert cv["nleaf"] == occ.sum() and cv["maxlevel"] == 4
+    neigh = sum(np.roll(occ, (dx, dy, dz), axis=(0, 1, 2)).astype(int)
+                for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1))
+    assert cv["n_p2p"] == int((neigh * occ).sum())
 
 
 # ---- polynomial split (the alternative truncation function of Sec. 5) ------------------
