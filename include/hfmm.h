@@ -59,16 +59,19 @@ extern "C" {
  *             r_cut, no forced opening across it; forces stay correct, at higher cost)
  *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
  *             compensated per-particle sums, FP64 positions, cell offsets and final sum;
- *             with split 0 the FP32 pair force uses a fitted polynomial whose degree (10, 14
- *             or 16) is chosen for r_cut / r_s, and r_cut beyond about 8 r_s is rejected
- *             (FMM_ERR_ARG) as no degree meets the FP32 tolerance there
+ *             with split 0 the FP32 pair force uses a fitted polynomial whose degree (10 or
+ *             14) is chosen for r_cut / r_s, and r_cut > 6 r_s is rejected (FMM_ERR_ARG):
+ *             beyond it FP32 cancellation near the cutoff exceeds the form's error bar
  *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see
  *             fmm_load_mac_model), the plain MAC's hard rules still apply
  *   split     0: the Gaussian (erfc) split of Sec. 2.2 with scale r_s, hard cut at r_cut;
  *             1: the polynomial split (the alternative truncation function Sec. 5 allows):
  *             phi_s = g(r/r_cut)/r, g(x) = 1 - 15/8 x + 5/4 x^3 - 3/8 x^5 below r_cut and 0
  *             beyond (r_s unused by the short range); PM filters with the transform of
- *             its smoothing density.  The learned selector requires split 0. */
+ *             its smoothing density.  The learned selector requires split 0.
+ *   pm_assign mass assignment of the PM long range: 0 or 2 cloud-in-cell, 3 triangular-
+ *             shaped cloud, 4 piecewise cubic (B-splines of that order; the window
+ *             sinc^order is divided out twice).  Unused by the short range. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
@@ -76,7 +79,8 @@ typedef struct fmm_params {
     int precision;
     int learned;
     int split;
-    int reserved[2];
+    int pm_assign;
+    int reserved[1];
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts
@@ -140,9 +144,10 @@ int fmm_short_range_forces(fmm_tree *tree, const fmm_params *params, double *acc
 int fmm_short_range_forces_graph(fmm_tree *tree, const fmm_params *params, double *acc, void *stream);
 
 /* Long-range accelerations by the particle-mesh method with a mesh of mesh^3 cells
- * (Sec. 2.2: Poisson Green function filtered by exp(-k^2 r_s^2)): CIC deposit, FFT,
- * filtered Green function with the CIC window deconvolved, spectral gradient, inverse
- * FFTs, CIC interpolation.  acc (n,3) is overwritten.  8 <= mesh <= 1024. */
+ * (Sec. 2.2: Poisson Green function filtered by exp(-k^2 r_s^2)): mass deposit (CIC, TSC
+ * or PCS by params->pm_assign), FFT, filtered Green function with the assignment window
+ * deconvolved, spectral gradient, inverse FFTs, interpolation with the same weights.
+ * acc (n,3) is overwritten.  8 <= mesh <= 1024. */
 int pm_long_range_forces(const fmm_params *params, int mesh, int64_t n, const double *pos, const double *mass,
                          double *acc, void *stream);
 

@@ -72,6 +72,7 @@ def lib():
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_stats.argtypes = [C.c_void_p, _lp]
         L.orc_seconds.argtypes = [C.c_void_p]; L.orc_seconds.restype = C.c_double
+        L.orc_phase_seconds.argtypes = [C.c_void_p, _dp]
         L.orc_ncell.argtypes = [C.c_void_p]; L.orc_ncell.restype = C.c_int
         L.orc_nlist.argtypes = [C.c_void_p, C.c_int]; L.orc_nlist.restype = C.c_long
         L.orc_copy_list.argtypes = [C.c_void_p, C.c_int, _up]
@@ -173,6 +174,9 @@ class FMMResult:
         lib().orc_stats(handle, st)
         self.stats = {k: int(st[i]) for i, k in enumerate(STAT_NAMES)}
         self.seconds = lib().orc_seconds(handle)
+        ph = np.zeros(5)
+        lib().orc_phase_seconds(handle, ph)
+        self.phases = dict(zip(("tree", "traversal", "upward", "m2l", "downward_p2p"), ph.tolist()))
 
     def lists(self, kind):
         """kind 'm2l' or 'p2p': array (n, 3) of (sink key, source key, image)."""

@@ -370,6 +370,7 @@ typedef struct {
     oplist m2l, p2p;
     long stats[16];
     double seconds;
+    double phase[5];   /* seconds: tree, traversal, upward, M2L, downward + P2P */
 } orc_state;
 
 /* stats slots */
@@ -401,12 +402,20 @@ static int is_leaf(const orc_state *S, int c) { return S->cell[c].nchild == 0; }
 /* Octree with a leaf-size limit (Sec. 2.1 "particle packs"; the octree replaces the
  * paper's ORB tree).  A cell is split into its eight octants while it holds more than
  * ncrit particles and is above the finest level; empty octants are dropped; children
- * are ordered by octant o = 4 bx + 2 by + bz.  Cells are created breadth-first. */
+ * are ordered by octant o = 4 bx + 2 by + bz.  Cells are created breadth-first, level by
+ * level: the cells of one level own disjoint particle ranges, so their counting sorts
+ * run in parallel; their children are then appended in cell order. */
+static int octant_of(const int *coord, int shift)
+{
+    return (((coord[0] >> shift) & 1) << 2) | (((coord[1] >> shift) & 1) << 1) | ((coord[2] >> shift) & 1);
+}
+
 static void build_tree(orc_state *S)
 {
     long n = S->n;
     const double scale = ldexp(1.0, ORC_MAXLEVEL);
     const int imax = (1 << ORC_MAXLEVEL) - 1;
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i)
         for (int a = 0; a < 3; ++a) {
             int c = (int)floor(S->x[3 * i + a] / S->P.box * scale);
@@ -419,51 +428,57 @@ static void build_tree(orc_state *S)
     long *tmp = (long *)malloc((size_t)(n > 0 ? n : 1) * sizeof(long));
     double *tx = (double *)malloc((size_t)(n > 0 ? n : 1) * 4 * sizeof(double));
     int *tc = (int *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(int));
-    for (int c = 0; c < S->ncell; ++c) {      /* breadth-first: ncell grows while we scan */
-        ocell cc = S->cell[c];
-        long cnt = cc.end - cc.beg;
-        if (cnt <= S->P.ncrit || cc.level >= ORC_MAXLEVEL) continue;
-        int shift = ORC_MAXLEVEL - 1 - cc.level;
-        long bucket[9] = {0};
-        for (long i = cc.beg; i < cc.end; ++i) {
-            int o = (((S->coord[3 * i] >> shift) & 1) << 2) | (((S->coord[3 * i + 1] >> shift) & 1) << 1)
-                    | ((S->coord[3 * i + 2] >> shift) & 1);
-            bucket[o + 1]++;
+    int lbeg = 0;
+    while (lbeg < S->ncell) {                   /* one level: cells lbeg .. lend-1 */
+        const int lend = S->ncell;
+        long (*bucket)[9] = (long (*)[9])calloc((size_t)(lend - lbeg), sizeof(long[9]));
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (int c = lbeg; c < lend; ++c) {
+            ocell cc = S->cell[c];
+            long cnt = cc.end - cc.beg;
+            long *bk = bucket[c - lbeg];
+            if (cnt <= S->P.ncrit || cc.level >= ORC_MAXLEVEL) continue;
+            int shift = ORC_MAXLEVEL - 1 - cc.level;
+            for (long i = cc.beg; i < cc.end; ++i) bk[octant_of(&S->coord[3 * i], shift) + 1]++;
+            for (int o = 0; o < 8; ++o) bk[o + 1] += bk[o];
+            long pos[8];
+            for (int o = 0; o < 8; ++o) pos[o] = cc.beg + bk[o];
+            for (long i = cc.beg; i < cc.end; ++i) {  /* stable counting sort by octant */
+                long d = pos[octant_of(&S->coord[3 * i], shift)]++;
+                tmp[d] = S->orig[i];
+                for (int a = 0; a < 3; ++a) { tx[4 * d + a] = S->x[3 * i + a]; tc[3 * d + a] = S->coord[3 * i + a]; }
+                tx[4 * d + 3] = S->m[i];
+            }
+            for (long i = cc.beg; i < cc.end; ++i) {
+                S->orig[i] = tmp[i];
+                for (int a = 0; a < 3; ++a) { S->x[3 * i + a] = tx[4 * i + a]; S->coord[3 * i + a] = tc[3 * i + a]; }
+                S->m[i] = tx[4 * i + 3];
+            }
         }
-        for (int o = 0; o < 8; ++o) bucket[o + 1] += bucket[o];
-        long pos[8];
-        for (int o = 0; o < 8; ++o) pos[o] = bucket[o];
-        for (long i = cc.beg; i < cc.end; ++i) {  /* stable counting sort by octant */
-            int o = (((S->coord[3 * i] >> shift) & 1) << 2) | (((S->coord[3 * i + 1] >> shift) & 1) << 1)
-                    | ((S->coord[3 * i + 2] >> shift) & 1);
-            long d = pos[o]++;
-            tmp[d] = S->orig[i];
-            for (int a = 0; a < 3; ++a) { tx[4 * d + a] = S->x[3 * i + a]; tc[3 * d + a] = S->coord[3 * i + a]; }
-            tx[4 * d + 3] = S->m[i];
+        for (int c = lbeg; c < lend; ++c) {     /* children in cell order, octant order */
+            const long *bk = bucket[c - lbeg];
+            if (bk[8] == 0) continue;           /* not split */
+            ocell cc = S->cell[c];
+            int first = -1, nch = 0;
+            for (int o = 0; o < 8; ++o) {
+                if (bk[o + 1] == bk[o]) continue;
+                int k = new_cell(S);
+                ocell *ch = &S->cell[k];
+                ch->level = cc.level + 1;
+                ch->ix = 2 * cc.ix + ((o >> 2) & 1);
+                ch->iy = 2 * cc.iy + ((o >> 1) & 1);
+                ch->iz = 2 * cc.iz + (o & 1);
+                ch->beg = cc.beg + bk[o];
+                ch->end = cc.beg + bk[o + 1];
+                ch->parent = c;
+                if (first < 0) first = k;
+                nch++;
+            }
+            S->cell[c].child = first;
+            S->cell[c].nchild = nch;
         }
-        for (long d = 0; d < cnt; ++d) {
-            long i = cc.beg + d;
-            S->orig[i] = tmp[d];
-            for (int a = 0; a < 3; ++a) { S->x[3 * i + a] = tx[4 * d + a]; S->coord[3 * i + a] = tc[3 * d + a]; }
-            S->m[i] = tx[4 * d + 3];
-        }
-        int first = -1, nch = 0;
-        for (int o = 0; o < 8; ++o) {
-            if (bucket[o + 1] == bucket[o]) continue;
-            int k = new_cell(S);
-            ocell *ch = &S->cell[k];
-            ch->level = cc.level + 1;
-            ch->ix = 2 * cc.ix + ((o >> 2) & 1);
-            ch->iy = 2 * cc.iy + ((o >> 1) & 1);
-            ch->iz = 2 * cc.iz + (o & 1);
-            ch->beg = cc.beg + bucket[o];
-            ch->end = cc.beg + bucket[o + 1];
-            ch->parent = c;
-            if (first < 0) first = k;
-            nch++;
-        }
-        S->cell[c].child = first;
-        S->cell[c].nchild = nch;
+        free(bucket);
+        lbeg = lend;
     }
     free(tmp); free(tx); free(tc);
 }
@@ -603,10 +618,13 @@ static double now_seconds(void)
 }
 
 /* Run the whole truncated FMM.  targets == NULL means every particle; otherwise only
- * the requested particles get forces, and only sink cells containing one of them are
- * traversed (the per-sink work is exactly that of the full run).  acc (n x 3, input
- * order) is overwritten for targets and left untouched elsewhere.  Returns a state
- * handle holding the tree, lists and statistics (free with orc_free). */
+ * the requested particles get forces, only sink cells containing one of them are
+ * traversed, and multipoles are formed only for the cells those sinks read (the M2L
+ * sources and their subtrees): the per-sink work is exactly that of the full run.  The
+ * traversal, which reads cell geometry only, runs before the upward pass so that these
+ * cells are known.  acc (n x 3, input order) is overwritten for targets and left
+ * untouched elsewhere.  Returns a state handle holding the tree, lists, statistics and
+ * per-phase times (free with orc_free). */
 void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass, long ntarget,
               const long *targets, double *acc, int nthreads)
 {
@@ -625,6 +643,7 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
     S->m = (double *)malloc(nn * sizeof(double));
     S->orig = (long *)malloc(nn * sizeof(long));
     S->coord = (int *)malloc(nn * 3 * sizeof(int));
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         for (int a = 0; a < 3; ++a) {          /* wrap into [0, box) */
             double v = pos[3 * i + a] - P->box * floor(pos[3 * i + a] / P->box);
@@ -655,38 +674,58 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
         free(where); free(want);
     }
 
-    /* upward pass: P2M at leaves, M2M to parents (Sec. 2.1) */
-    S->M = (double *)calloc((size_t)S->ncell * np, sizeof(double));
-    S->L = (double *)calloc((size_t)S->ncell * np, sizeof(double));
-    {
-        double *xm = (double *)malloc(nn * 3 * sizeof(double));
-        memcpy(xm, S->x, (size_t)n * 3 * sizeof(double));
-        #pragma omp parallel for schedule(dynamic, 16)
-        for (int c = 0; c < S->ncell; ++c) {
-            if (!is_leaf(S, c)) continue;
-            double z[3]; cell_centre(S, c, z);
-            orc_p2m(P->p, S->cell[c].end - S->cell[c].beg, xm + 3 * S->cell[c].beg, S->m + S->cell[c].beg, z,
-                    S->M + (size_t)c * np);
-        }
-        free(xm);
-    }
-    for (int c = S->ncell - 1; c >= 0; --c) {   /* children have larger ids than parents */
-        if (is_leaf(S, c)) continue;
-        double zp[3]; cell_centre(S, c, zp);
-        for (int k = 0; k < S->cell[c].nchild; ++k) {
-            int ch = S->cell[c].child + k;
-            double zc[3]; cell_centre(S, ch, zc);
-            double x[3] = {zp[0] - zc[0], zp[1] - zc[1], zp[2] - zc[2]};
-            orc_m2m(P->p, S->M + (size_t)ch * np, x, S->M + (size_t)c * np);
-        }
-    }
+    S->phase[0] = now_seconds() - t0;        /* tree */
 
-    /* dual traversal from the 27 root images */
+    /* dual traversal from the 27 root images (it reads cell geometry only, so the lists
+     * can be made before the multipoles) */
+    double t1 = now_seconds();
     orc_mac mac; mac_setup(P, &mac);
     if (n > 0)
         for (int s = 0; s < 27; ++s) traverse(S, &mac, 0, 0, s);
     if (S->m2l.n) qsort(S->m2l.v, (size_t)S->m2l.n, sizeof(opair), cmp_pair);  /* an empty list has no array */
     if (S->p2p.n) qsort(S->p2p.v, (size_t)S->p2p.n, sizeof(opair), cmp_pair);
+    S->phase[1] = now_seconds() - t1;
+
+    /* upward pass: P2M at leaves, M2M to parents (Sec. 2.1), for the cells whose
+     * multipoles are read: the M2L sources and everything below them (all cells in a
+     * full run).  Parents have smaller ids than children (breadth-first creation). */
+    t1 = now_seconds();
+    S->M = (double *)calloc((size_t)S->ncell * np, sizeof(double));
+    S->L = (double *)calloc((size_t)S->ncell * np, sizeof(double));
+    char *need = (char *)calloc((size_t)(S->ncell > 0 ? S->ncell : 1), 1);
+    if (!targets) {
+        memset(need, 1, (size_t)S->ncell);
+    } else {
+        for (long e = 0; e < S->m2l.n; ++e) need[S->m2l.v[e].b] = 1;
+        for (int c = 1; c < S->ncell; ++c)
+            if (need[S->cell[c].parent]) need[c] = 1;
+    }
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int c = 0; c < S->ncell; ++c) {
+        if (!need[c] || !is_leaf(S, c)) continue;
+        double z[3]; cell_centre(S, c, z);
+        orc_p2m(P->p, S->cell[c].end - S->cell[c].beg, S->x + 3 * S->cell[c].beg, S->m + S->cell[c].beg, z,
+                S->M + (size_t)c * np);
+    }
+    for (int lend = S->ncell; lend > 0;) {     /* levels bottom-up; a level is a contiguous id range */
+        int lbeg = lend - 1;
+        while (lbeg > 0 && S->cell[lbeg - 1].level == S->cell[lend - 1].level) --lbeg;
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int c = lbeg; c < lend; ++c) {
+            if (!need[c] || is_leaf(S, c)) continue;
+            double zp[3]; cell_centre(S, c, zp);
+            for (int k = 0; k < S->cell[c].nchild; ++k) {
+                int ch = S->cell[c].child + k;
+                double zc[3]; cell_centre(S, ch, zc);
+                double x[3] = {zp[0] - zc[0], zp[1] - zc[1], zp[2] - zc[2]};
+                orc_m2m(P->p, S->M + (size_t)ch * np, x, S->M + (size_t)c * np);
+            }
+        }
+        lend = lbeg;
+    }
+    free(need);
+    S->phase[2] = now_seconds() - t1;
+    t1 = now_seconds();
 
     /* M2L grouped by sink (lists sorted by sink) */
     {
@@ -708,6 +747,9 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
         }
         free(start);
     }
+
+    S->phase[3] = now_seconds() - t1;
+    t1 = now_seconds();
 
     /* downward pass: L2L parent -> child (parents first) */
     for (int c = 1; c < S->ncell; ++c) {
@@ -757,6 +799,7 @@ void *orc_fmm(const orc_params *P, long n, const double *pos, const double *mass
         free(where);
     }
     free(accs);
+    S->phase[4] = now_seconds() - t1;
     S->seconds = now_seconds() - t0;
 
     int nleaf = 0, maxl = 0;
@@ -779,6 +822,7 @@ void orc_free(void *h)
 
 void orc_stats(const void *h, long *out16) { memcpy(out16, ((const orc_state *)h)->stats, 16 * sizeof(long)); }
 double orc_seconds(const void *h) { return ((const orc_state *)h)->seconds; }
+void orc_phase_seconds(const void *h, double *out5) { memcpy(out5, ((const orc_state *)h)->phase, 5 * sizeof(double)); }
 int orc_ncell(const void *h) { return ((const orc_state *)h)->ncell; }
 long orc_nlist(const void *h, int kind) { const orc_state *S = (const orc_state *)h; return kind ? S->p2p.n : S->m2l.n; }
 

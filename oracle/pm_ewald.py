@@ -1,9 +1,10 @@
 """CPU references for the long-range step (test infrastructure only).
 
 * ``pm_forces``: the particle-mesh step written plainly with numpy FFTs, in the order of
-  the method: CIC deposit on a cell-centred mesh, Poisson Green function filtered by
-  exp(-k^2 r_s^2) (the Gaussian split of Sec. 2.2, k_s = 1/(2 r_s)), CIC window divided
-  out twice, spectral gradient, inverse transforms, CIC interpolation.
+  the method: mass deposit on a cell-centred mesh (CIC, or the higher-order TSC and PCS
+  B-spline schemes), Poisson Green function filtered by exp(-k^2 r_s^2) (the Gaussian
+  split of Sec. 2.2, k_s = 1/(2 r_s)), assignment window divided out twice, spectral
+  gradient, inverse transforms, interpolation with the same weights.
 * ``ewald_reciprocal`` / ``ewald_total``: textbook Ewald summation with splitting
   parameter alpha = 1/(2 r_s).  The real-space part is the erfc-truncated pair force of
   the short range (Sec. 2.2 force law) summed over images without a cutoff; the
@@ -17,12 +18,31 @@ import numpy as np
 from . import bruteforce, make_params
 
 
-def _cic(pos, box, M):
+def assignment(pos, box, M, order=2):
+    """Mass-assignment weights of the B-spline schemes on a cell-centred mesh (node i at
+    (i + 1/2) box/M): order 2 cloud-in-cell, 3 triangular-shaped cloud, 4 piecewise cubic.
+    Returns the first node index per axis (mod M, shape (N, 3)) and the weights of the
+    `order` consecutive nodes from it (shape (N, 3, order))."""
     g = np.mod(pos, box) * (M / box) - 0.5
-    f = np.floor(g)
-    w1 = g - f
-    i0 = np.mod(f.astype(np.int64), M)
-    return i0, w1
+    if order == 2:
+        f = np.floor(g)
+        t = g - f
+        w = np.stack([1.0 - t, t], -1)
+        first = f
+    elif order == 3:
+        c = np.floor(g + 0.5)          # nearest node
+        dx = g - c                     # in [-1/2, 1/2)
+        w = np.stack([0.5 * (0.5 - dx) ** 2, 0.75 - dx ** 2, 0.5 * (0.5 + dx) ** 2], -1)
+        first = c - 1
+    elif order == 4:
+        f = np.floor(g)
+        t = g - f
+        w = np.stack([(1 - t) ** 3 / 6, (4 - 6 * t ** 2 + 3 * t ** 3) / 6, (1 + 3 * t + 3 * t ** 2 - 3 * t ** 3) / 6,
+                      t ** 3 / 6], -1)
+        first = f - 1
+    else:
+        raise ValueError("assignment order must be 2, 3 or 4")
+    return np.mod(first.astype(np.int64), M), w
 
 
 def long_range_window(k, rs=None, split=0, rcut=None):
@@ -43,22 +63,23 @@ def long_range_window(k, rs=None, split=0, rcut=None):
     return out
 
 
-def pm_forces(pos, mass, box, rs, M, G=1.0, split=0, rcut=None):
+def pm_forces(pos, mass, box, rs, M, G=1.0, split=0, rcut=None, order=2):
+    """order: mass assignment (2 CIC, 3 TSC, 4 PCS); its window sinc^order per axis is
+    divided out once for the deposit and once for the interpolation."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
-    i0, w1 = _cic(pos, box, M)
+    i0, w = assignment(pos, box, M, order)
     d = box / M
     rho = np.zeros((M, M, M))
-    for c in range(8):
-        sx, sy, sz = c >> 2, (c >> 1) & 1, c & 1
-        wt = (w1[:, 0] if sx else 1 - w1[:, 0]) * (w1[:, 1] if sy else 1 - w1[:, 1]) * \
-             (w1[:, 2] if sz else 1 - w1[:, 2])
+    stencil = [(a, b, c) for a in range(order) for b in range(order) for c in range(order)]
+    for sx, sy, sz in stencil:
+        wt = w[:, 0, sx] * w[:, 1, sy] * w[:, 2, sz]
         np.add.at(rho, ((i0[:, 0] + sx) % M, (i0[:, 1] + sy) % M, (i0[:, 2] + sz) % M), mass * wt / d ** 3)
     rk = np.fft.rfftn(rho)
     n1 = np.fft.fftfreq(M, 1.0 / M)
     nz = np.arange(M // 2 + 1)
     kx, ky, kz = np.meshgrid(n1 * 2 * np.pi / box, n1 * 2 * np.pi / box, nz * 2 * np.pi / box, indexing="ij")
     k2 = kx ** 2 + ky ** 2 + kz ** 2
-    W = (np.sinc(kx * d / (2 * np.pi)) * np.sinc(ky * d / (2 * np.pi)) * np.sinc(kz * d / (2 * np.pi))) ** 2
+    W = (np.sinc(kx * d / (2 * np.pi)) * np.sinc(ky * d / (2 * np.pi)) * np.sinc(kz * d / (2 * np.pi))) ** order
     nyq = np.zeros_like(k2, dtype=bool)
     if M % 2 == 0:
         nx_i, ny_i = np.meshgrid(n1, n1, indexing="ij")
@@ -72,10 +93,8 @@ def pm_forces(pos, mass, box, rs, M, G=1.0, split=0, rcut=None):
     for a, ka in enumerate((kx, ky, kz)):
         am = np.fft.irfftn(-1j * ka * phi * rk, s=(M, M, M), axes=(0, 1, 2))
         g = np.zeros(len(pos))
-        for c in range(8):
-            sx, sy, sz = c >> 2, (c >> 1) & 1, c & 1
-            wt = (w1[:, 0] if sx else 1 - w1[:, 0]) * (w1[:, 1] if sy else 1 - w1[:, 1]) * \
-                 (w1[:, 2] if sz else 1 - w1[:, 2])
+        for sx, sy, sz in stencil:
+            wt = w[:, 0, sx] * w[:, 1, sy] * w[:, 2, sz]
             g += wt * am[(i0[:, 0] + sx) % M, (i0[:, 1] + sy) % M, (i0[:, 2] + sz) % M]
         out[:, a] = g
     return out

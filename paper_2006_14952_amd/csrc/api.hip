@@ -40,6 +40,8 @@ static int check_params(const fmm_params *P)
     if (P->learned != 0 && P->learned != 1) return set_error(FMM_ERR_ARG, "learned must be 0 or 1");
     if (P->split != 0 && P->split != 1) return set_error(FMM_ERR_ARG, "split must be 0 or 1");
     if (P->learned && P->split) return set_error(FMM_ERR_ARG, "the learned selector requires split 0");
+    if (P->pm_assign != 0 && (P->pm_assign < 2 || P->pm_assign > 4))
+        return set_error(FMM_ERR_ARG, "pm_assign must be 0, 2 (CIC), 3 (TSC) or 4 (PCS)");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;
@@ -154,7 +156,7 @@ static bool same_params(const fmm_params &a, const fmm_params &b)
 {
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
            a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
-           a.split == b.split;
+           a.split == b.split && a.pm_assign == b.pm_assign;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,

@@ -54,11 +54,17 @@ constexpr int kChunk = 64;
 constexpr int kMaxCells = 1 << 27;
 
 // Per-call constants of the P2P force law in FP32: f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),
-// t = 2 r^2 / r_cut^2 - 1, S a polynomial fitted on the host: of degree 10, 14 or 16, the
-// lowest whose error in r^3 f_(1) stays below kP2PFitTol over [0, r_cut] (checked on the
-// host at every fit; degree 10 serves r_cut up to about 5 r_s, 16 up to about 8 r_s).
-constexpr int kP2PPolyMax = 17;
+// t = 2 r^2 / r_cut^2 - 1, S a polynomial fitted on the host: of degree 10 or 14, the
+// lower whose error in r^3 f_(1) stays below kP2PFitTol over [0, r_cut] (checked on the
+// host at every fit; degree 10 serves r_cut up to about 5 r_s, 14 beyond).  The two terms
+// cancel as r^3 f_(1) = -(erfc(u) + 2u/sqrt(pi) e^(-u^2)), u = r/2r_s, falls towards r_cut:
+// their FP32 rounding (about 1e-7 of 1/r^3) is 2e-5 of a pair's own force at a cutoff of
+// 4.5 r_s, 2e-4 at 6 r_s and 5e-2 at 7 r_s, where particles whose force comes from pairs
+// near the cutoff reach relative errors of 1e-2.  The FP32 form accepts r_cut <=
+// kP2PMaxCut r_s.
+constexpr int kP2PPolyMax = 15;
 constexpr double kP2PFitTol = 1.0e-6;
+constexpr double kP2PMaxCut = 6.0;
 // The short range's truncation function: kind 0 the Gaussian split (scale = r_s), kind 1
 // the polynomial split g(r/r_cut)/r (scale = r_cut).
 struct Split {
@@ -68,7 +74,7 @@ struct Split {
 
 struct P2PConst {
     float c[kP2PPolyMax];  // S(t) / (8 r_s^3), coefficients of t^0 .. t^(ncoef-1)
-    int ncoef;             // 11, 15 or 17
+    int ncoef;             // 11 or 15
     int split;             // 0: Gaussian split; 1: polynomial split (c[0] = 1 / r_cut, see p2p_setup)
     float two_over_rc2;
     float rc2;

@@ -13,8 +13,8 @@
 // centre offset c_B + s box - c_A added when staging, and
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
-// polynomial of degree 10, 14 or 16 fitted on the host, the lowest that meets the FP32
-// tolerance at this r_cut / r_s (its coefficients carry the factor 1/(8 r_s^3));
+// polynomial of degree 10 or 14 fitted on the host, the lower that meets the FP32
+// tolerance at this r_cut / r_s <= 6 (its coefficients carry the factor 1/(8 r_s^3));
 // the sum of each staged block is added to a Kahan-compensated per-particle accumulator.
 // A listed source leaf whose particles' bounding box lies farther than r_cut from the sink
 // leaf's box, and any single source particle farther than r_cut from that box, hold no
@@ -409,9 +409,10 @@ static double fit_error(double vcut, int m, const double *coef)
     return worst;
 }
 
-// FP32 force-law constants.  Gaussian split: the lowest polynomial length of 11, 15 and 17
-// whose checked error is at most kP2PFitTol; returns FMM_ERR_ARG if none is (r_cut beyond
-// about 8 r_s).  The last fit is cached (same vcut, same result).
+// Force-law constants.  FP32 form, Gaussian split: the lower polynomial length of 11 and 15 whose
+// checked error is at most kP2PFitTol; returns FMM_ERR_ARG for r_cut > kP2PMaxCut r_s (FP32
+// cancellation near the cutoff) or if no fit meets the tolerance.  The last fit is cached
+// (same vcut, same result).
 int p2p_setup(const fmm_params *P, P2PConst &k)
 {
     static std::mutex mu;
@@ -421,11 +422,15 @@ int p2p_setup(const fmm_params *P, P2PConst &k)
     const double vcut = (P->r_cut * P->r_cut) / (4.0 * P->r_s * P->r_s);
     double coef[kP2PPolyMax] = {0};
     int m = 0;
-    if (P->split == 0) {
+    if (P->precision == 1 && P->split == 0) {  // the FP64 form evaluates erfc/exp: no fit, no limit
+        if (P->r_cut > kP2PMaxCut * P->r_s)
+            return set_error(FMM_ERR_ARG, "precision 1 supports r_cut <= %.0f r_s (r_cut / r_s = %.3g): beyond it the "
+                                          "FP32 pair force loses accuracy near the cutoff; use precision 0",
+                             kP2PMaxCut, P->r_cut / P->r_s);
         std::lock_guard<std::mutex> lk(mu);
         if (vcut != cached_vcut) {
             cached_m = 0;
-            for (int mm : {11, 15, 17}) {
+            for (int mm : {11, 15}) {
                 fit_S(vcut, mm, cached);
                 if (fit_error(vcut, mm, cached) <= kP2PFitTol) {
                     cached_m = mm;
@@ -437,9 +442,8 @@ int p2p_setup(const fmm_params *P, P2PConst &k)
         m = cached_m;
         for (int j = 0; j < m; ++j) coef[j] = cached[j];
         if (m == 0)
-            return set_error(FMM_ERR_ARG, "precision 1 supports r_cut up to about 8 r_s (r_cut / r_s = %.3g: no "
-                                          "polynomial of degree <= 16 meets the FP32 force-law tolerance)",
-                             P->r_cut / P->r_s);
+            return set_error(FMM_ERR_ARG, "precision 1: no polynomial of degree <= 14 meets the FP32 force-law "
+                                          "tolerance at r_cut / r_s = %.3g; use precision 0", P->r_cut / P->r_s);
     }
     // the kernel evaluates S(t) / (8 r_s^3): the factor is folded into the coefficients
     const double inv8rs3 = 1.0 / (8.0 * P->r_s * P->r_s * P->r_s);
@@ -493,7 +497,6 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
         a.bbox = ptr<float4>(t->bbox);
     }
     if (P->precision && P->split == 1) k_p2p<false, true, 11><<<t->nleaf, 64, 0, st>>>(a, k);
-    else if (P->precision && k.ncoef == 17) k_p2p<false, false, 17><<<t->nleaf, 64, 0, st>>>(a, k);
     else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<t->nleaf, 64, 0, st>>>(a, k);
     else if (P->precision) k_p2p<false, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);
     else k_p2p<true, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);

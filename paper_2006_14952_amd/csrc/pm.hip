@@ -2,10 +2,12 @@
 // filtered by exp(-k^2 r_s^2), so that PM + the erfc-truncated short range sums to
 // Newtonian gravity (the split of the force law g(r) of Sec. 2.2).
 //
-//   CIC deposit -> rho(x);  FFT;  phi_k = -4 pi G rho_k exp(-k^2 r_s^2) / (k^2 W(k)^2);
-//   a_k = -i k phi_k (three components);  inverse FFTs;  CIC interpolation.
-// W(k) = prod_i sinc^2(k_i Delta / 2) is the CIC window, divided out once for the
-// deposit and once for the interpolation.  With the polynomial split the filter is the
+//   deposit -> rho(x);  FFT;  phi_k = -4 pi G rho_k exp(-k^2 r_s^2) / (k^2 W(k)^2);
+//   a_k = -i k phi_k (three components);  inverse FFTs;  interpolation.
+// The mass assignment is cloud-in-cell by default, or the higher-order triangular-shaped
+// cloud (TSC) or piecewise cubic (PCS) B-spline schemes (fmm_params.pm_assign 3, 4);
+// W(k) = prod_i sinc^p(k_i Delta / 2) is the window of the order-p scheme, divided out
+// once for the deposit and once for the interpolation.  With the polynomial split the filter is the
 // transform of its smoothing density 15/(8 pi r_c^3)(1 - r^2/r_c^2) (r < r_c):
 // 15 (3 sin u - 3 u cos u - u^2 sin u) / u^5, u = k r_cut.  The k = 0 mode is dropped (mean density is
 // cancelled by the expanding background).  FFTs are hipFFT (double precision).
@@ -54,13 +56,33 @@ static int pm_plan(int mesh, PMPlan **out)
     return 0;
 }
 
-__device__ __forceinline__ void cic_weights(double x, double inv_d, int M, int &i0, double &w1)
+// Mass-assignment weights of the B-spline schemes on the cell-centred mesh (node i at
+// (i + 0.5) Delta): ORDER 2 cloud-in-cell, 3 triangular-shaped cloud, 4 piecewise cubic.
+// The particle touches nodes i0 .. i0 + ORDER - 1 (mod M) with weights w[0 .. ORDER-1].
+template <int ORDER> __device__ __forceinline__ void assign_weights(double x, double inv_d, int M, int &i0, double *w)
 {
-    // cell-centred mesh: node i at (i + 0.5) Delta
-    double g = x * inv_d - 0.5;
-    double f = floor(g);
-    w1 = g - f;
-    int i = (int)f;
+    const double g = x * inv_d - 0.5;
+    double first;
+    if constexpr (ORDER == 2) {
+        const double f = floor(g), t = g - f;
+        w[0] = 1.0 - t;
+        w[1] = t;
+        first = f;
+    } else if constexpr (ORDER == 3) {
+        const double c = floor(g + 0.5), dx = g - c;  // nearest node, dx in [-1/2, 1/2)
+        w[0] = 0.5 * (0.5 - dx) * (0.5 - dx);
+        w[1] = 0.75 - dx * dx;
+        w[2] = 0.5 * (0.5 + dx) * (0.5 + dx);
+        first = c - 1.0;
+    } else {
+        const double f = floor(g), t = g - f, t2 = t * t, t3 = t2 * t, u = 1.0 - t;
+        w[0] = u * u * u / 6.0;
+        w[1] = (4.0 - 6.0 * t2 + 3.0 * t3) / 6.0;
+        w[2] = (1.0 + 3.0 * t + 3.0 * t2 - 3.0 * t3) / 6.0;
+        w[3] = t3 / 6.0;
+        first = f - 1.0;
+    }
+    const int i = (int)first;
     i0 = ((i % M) + M) % M;
 }
 
@@ -81,26 +103,26 @@ struct MortonOrder {
     __device__ size_t row(int p) const { return 3 * (size_t)perm[p]; }
 };
 
-template <class S>
-__global__ void k_cic_deposit(S src, int n, double box, int M, double inv_vol, double *__restrict__ rho)
+template <class S, int ORDER>
+__global__ void k_deposit(S src, int n, double box, int M, double inv_vol, double *__restrict__ rho)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double inv_d = M / box;
     int i[3];
-    double w[3];
+    double w[3][ORDER];
     for (int a = 0; a < 3; ++a) {
         double x = src.x(p, a);
         x -= box * floor(x / box);
-        cic_weights(x, inv_d, M, i[a], w[a]);
+        assign_weights<ORDER>(x, inv_d, M, i[a], w[a]);
     }
     double m = src.m(p) * inv_vol;
-    for (int c = 0; c < 8; ++c) {
-        int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
-        double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
-        size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
-        atomicAdd(&rho[idx], m * wt);
-    }
+    for (int dx = 0; dx < ORDER; ++dx)
+        for (int dy = 0; dy < ORDER; ++dy)
+            for (int dz = 0; dz < ORDER; ++dz) {
+                size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
+                atomicAdd(&rho[idx], m * w[0][dx] * w[1][dy] * w[2][dz]);
+            }
 }
 
 __device__ __forceinline__ double sinc(double x) { return fabs(x) < 1e-8 ? 1.0 : sin(x) / x; }
@@ -118,7 +140,7 @@ __device__ __forceinline__ double lr_window(double k2, double rs, int split, dou
 
 // a_k component `axis` from rho_k; includes the 1/M^3 of the inverse transform
 __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipfftDoubleComplex *__restrict__ out,
-                             int M, double box, double rs, int split, double rcut, double G, int axis)
+                             int M, double box, double rs, int split, double rcut, double G, int axis, int order)
 {
     int Mh = M / 2 + 1;
     size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -135,8 +157,9 @@ __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipff
         out[t] = o;
         return;
     }
-    double W = sinc(0.5 * k0 * d) * sinc(0.5 * k1 * d) * sinc(0.5 * k2 * d);
-    W = W * W;
+    const double s1 = sinc(0.5 * k0 * d) * sinc(0.5 * k1 * d) * sinc(0.5 * k2 * d);
+    double W = s1;  // the assignment window: sinc^order per axis
+    for (int o = 1; o < order; ++o) W *= s1;
     double phi = -4.0 * M_PI * G * lr_window(k2s, rs, split, rcut) / (k2s * W * W);
     double ka = axis == 0 ? k0 : (axis == 1 ? k1 : k2);
     double s = phi * ka / ((double)M * M * M);  // a_k = -i k phi_k
@@ -145,27 +168,28 @@ __global__ void k_green_grad(const hipfftDoubleComplex *__restrict__ rhok, hipff
     out[t] = o;
 }
 
-template <class S>
-__global__ void k_cic_interp(S src, int n, double box, int M, const double *__restrict__ am, double *__restrict__ acc)
+template <class S, int ORDER>
+__global__ void k_interp(S src, int n, double box, int M, const double *__restrict__ am, double *__restrict__ acc)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     double inv_d = M / box;
     int i[3];
-    double w[3];
+    double w[3][ORDER];
     for (int a = 0; a < 3; ++a) {
         double x = src.x(p, a);
         x -= box * floor(x / box);
-        cic_weights(x, inv_d, M, i[a], w[a]);
+        assign_weights<ORDER>(x, inv_d, M, i[a], w[a]);
     }
     size_t nr = (size_t)M * M * M;
     double g[3] = {0, 0, 0};
-    for (int c = 0; c < 8; ++c) {
-        int dx = c >> 2, dy = (c >> 1) & 1, dz = c & 1;
-        double wt = (dx ? w[0] : 1 - w[0]) * (dy ? w[1] : 1 - w[1]) * (dz ? w[2] : 1 - w[2]);
-        size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
-        for (int a = 0; a < 3; ++a) g[a] += wt * am[a * nr + idx];
-    }
+    for (int dx = 0; dx < ORDER; ++dx)
+        for (int dy = 0; dy < ORDER; ++dy)
+            for (int dz = 0; dz < ORDER; ++dz) {
+                const double wt = w[0][dx] * w[1][dy] * w[2][dz];
+                size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
+                for (int a = 0; a < 3; ++a) g[a] += wt * am[a * nr + idx];
+            }
     const size_t o = src.row(p);
     for (int a = 0; a < 3; ++a) acc[o + a] = g[a];
 }
@@ -201,7 +225,11 @@ static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos
     }
     if (int rc = hip_check(hipMemsetAsync(pl->rho.p, 0, nr * 8, st), "pm mesh")) return rc;
     double d = P->box / mesh;
-    k_cic_deposit<S><<<(n + 255) / 256, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    const int order = P->pm_assign == 0 ? 2 : P->pm_assign;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (order == 3) k_deposit<S, 3><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    else if (order == 4) k_deposit<S, 4><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    else k_deposit<S, 2><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
     if (hipfftSetStream(pl->r2c, st) != HIPFFT_SUCCESS || hipfftSetStream(pl->c2r, st) != HIPFFT_SUCCESS)
         return set_error(FMM_ERR_HIP, "hipfftSetStream");
     if (hipfftExecD2Z(pl->r2c, ptr<double>(pl->rho), ptr<hipfftDoubleComplex>(pl->rhok)) != HIPFFT_SUCCESS)
@@ -209,12 +237,14 @@ static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos
     for (int axis = 0; axis < 3; ++axis) {
         k_green_grad<<<(unsigned)((nc + 255) / 256), 256, 0, st>>>(ptr<hipfftDoubleComplex>(pl->rhok),
                                                                   ptr<hipfftDoubleComplex>(pl->work), mesh, P->box,
-                                                                  P->r_s, P->split, P->r_cut, P->G, axis);
+                                                                  P->r_s, P->split, P->r_cut, P->G, axis, order);
         if (hipfftExecZ2D(pl->c2r, ptr<hipfftDoubleComplex>(pl->work), ptr<double>(pl->amesh) + axis * nr) !=
             HIPFFT_SUCCESS)
             return set_error(FMM_ERR_HIP, "hipfftExecZ2D");
     }
-    k_cic_interp<S><<<(n + 255) / 256, 256, 0, st>>>(src, n, P->box, mesh, ptr<double>(pl->amesh), acc);
+    if (order == 3) k_interp<S, 3><<<nb, 256, 0, st>>>(src, n, P->box, mesh, ptr<double>(pl->amesh), acc);
+    else if (order == 4) k_interp<S, 4><<<nb, 256, 0, st>>>(src, n, P->box, mesh, ptr<double>(pl->amesh), acc);
+    else k_interp<S, 2><<<nb, 256, 0, st>>>(src, n, P->box, mesh, ptr<double>(pl->amesh), acc);
     int rc = hip_check(hipGetLastError(), "pm");
     if (rc == 0) rc = hip_check(hipStreamSynchronize(st), "pm");  // mesh buffers are reused by the next call
     return rc;

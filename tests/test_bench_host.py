@@ -18,7 +18,7 @@ def bench():
 
 
 def _counts(**kw):
-    c = {"n_cells": 1000, "n_m2l": 5000, "n_visit": 20000, "p2p_evaluated": 10 ** 7,
+    c = {"n_cells": 1000, "n_m2l": 5000, "n_visit": 20000, "p2p_pairs": 10 ** 7, "p2p_evaluated": 6 * 10 ** 6,
          "n_m2l_by_order": [0] * 7}
     c.update(kw)
     return c
@@ -59,3 +59,27 @@ def test_learned_counts_each_order_and_fp64_uses_its_peak(bench):
 def test_polynomial_split_counts_thirty_flop_per_pair(bench):
     r = bench.stage_rooflines(_counts(), STAGES, 0.25, 10.0, 10, 4, False, 1, 1)
     assert r["stages"]["p2p"]["work"] == 30 * 10 ** 7
+
+
+def test_p2p_roofline_counts_listed_pairs(bench):
+    wl = {"learned": False, "precision": 1, "theta": 0.42, "n_crit": 32}
+    r = bench.p2p_roofline({"p2p_pairs": 10 ** 9, "p2p_evaluated": 6 * 10 ** 8}, 2.0, wl, "none", {"p": 6}, 100, 0)
+    assert r["flop_per_launch"] == 38 * 10 ** 9
+    assert r["achieved"] == pytest.approx(38e9 / 2e-3 / 1e12)
+    assert r["frac"] == pytest.approx(38e9 / 2e-3 / 157.3e12)
+    assert r["traffic"] is None  # no counters recorded for this workload
+
+
+def test_cube_sample_takes_whole_seeded_cubes(bench):
+    import numpy as np
+    rng = np.random.default_rng(0)
+    pos = rng.random((200000, 3))
+    tg = bench.cube_sample(pos, 0.01, 5)
+    side = 1 << bench.CUBE_LEVEL
+    cube = np.ravel_multi_index(np.floor(pos * side).astype(np.int64).T, (side,) * 3)
+    chosen = np.unique(cube[tg])
+    assert len(chosen) <= round(0.01 * side ** 3)
+    assert np.array_equal(np.sort(tg), np.nonzero(np.isin(cube, chosen))[0])  # every particle of those cubes
+    assert 0.005 < len(tg) / len(pos) < 0.015
+    assert np.array_equal(tg, bench.cube_sample(pos, 0.01, 5))  # seeded
+    assert len(bench.cube_sample(pos, 1.0, 5)) == len(pos)

@@ -112,10 +112,10 @@ def test_clustered_midsize_fp64_and_fp32():
         assert np.percentile(rel_err(got, bf), 99) <= 1e-3
 
 
-@pytest.mark.parametrize("ratio", [5.0, 6.0, 7.5])
+@pytest.mark.parametrize("ratio", [5.0, 5.5, 6.0])
 def test_fp32_force_law_at_larger_cutoffs(ratio):
     """The FP32 pair force is a polynomial fit whose degree the library raises with
-    r_cut / r_s (10 up to about 5 r_s, 14 up to about 7, 16 up to about 8): at cutoffs
+    r_cut / r_s (10 up to about 5 r_s, 14 up to 6 r_s, the largest it accepts): at cutoffs
     beyond the workloads' 4.5 r_s the FP32 form must still meet the FP32 bar against the
     FP64 oracle."""
     rng = inputs.rng_for(108, int(ratio * 10))
@@ -133,7 +133,7 @@ def test_fp32_force_law_at_larger_cutoffs(ratio):
 
 def test_fp32_rejects_cutoffs_beyond_the_fit():
     pos, m = inputs.clustered(2000, 4, inputs.rng_for(109))
-    prm = hf.params(r_s=0.005, r_cut=0.05, theta=0.5, p=4, n_crit=16, precision=1)  # r_cut = 10 r_s
+    prm = hf.params(r_s=0.005, r_cut=0.0325, theta=0.5, p=4, n_crit=16, precision=1)  # r_cut = 6.5 r_s
     with pytest.raises(hf.FMMError) as ei:
         gpu_run(pos, m, prm)
     assert ei.value.code == hf.FMM_ERR_ARG and "r_cut" in str(ei.value)

@@ -31,6 +31,39 @@ def test_pm_matches_cpu_reference(M):
     assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("order", [3, 4])
+@pytest.mark.parametrize("M", [16, 33])
+def test_pm_higher_order_assignment_matches_cpu_reference(M, order):
+    """TSC (3) and PCS (4) mass assignment with their windows divided out: the library's
+    PM step against the numpy reference, element by element."""
+    pos, m = inputs.clustered(3000, 4, inputs.rng_for(307, M, order))
+    rs = 1.25 / M
+    prm = hf.params(r_s=rs, p=4, pm_assign=order)
+    got = hf.pm_long_range(dev(pos), dev(m), prm, M).cpu().numpy()
+    ref = pm_ewald.pm_forces(pos, m, 1.0, rs, M, order=order)
+    assert rms_rel(got, ref) < 1e-10
+    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+def test_hybrid_with_higher_order_pm_is_closer_to_ewald():
+    """The hybrid total (PM + short range) against Ewald: the PM's aliasing error falls
+    from CIC to TSC to PCS at the same mesh; the tree-based hybrid entry point agrees."""
+    pos, m = inputs.clustered(4000, 5, inputs.rng_for(308))
+    M = 32
+    rs = 1.25 / M
+    ew = pm_ewald.ewald_total(pos, m, 1.0, rs)
+    err = {}
+    for order in (2, 3, 4):
+        prm = hf.params(r_s=rs, r_cut=4.5 * rs, theta=0.4, p=6, n_crit=16, pm_assign=order)
+        tot = hf.hybrid(dev(pos), dev(m), prm, M).cpu().numpy()
+        t = hf.Tree()
+        tot2 = t.hybrid(dev(pos), dev(m), prm, M).cpu().numpy()
+        t.free()
+        assert rms_rel(tot2, tot) < 1e-12
+        err[order] = rms_rel(tot, ew)
+    assert err[2] > err[3] > err[4], err
+
+
 def test_pm_edge_cases():
     prm = hf.params(r_s=0.02, p=4)
     out = hf.pm_long_range(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
@@ -43,6 +76,9 @@ def test_pm_edge_cases():
     assert ei.value.code == hf.FMM_ERR_NAN
     with pytest.raises(hf.FMMError):
         hf.pm_long_range(dev(np.zeros((4, 3))), dev(np.ones(4)), prm, 4)
+    with pytest.raises(hf.FMMError) as ei:  # only CIC, TSC and PCS
+        hf.pm_long_range(dev(np.zeros((4, 3))), dev(np.ones(4)), hf.params(r_s=0.02, p=4, pm_assign=5), 32)
+    assert ei.value.code == hf.FMM_ERR_ARG
 
 
 def test_hybrid_equals_parts_and_approaches_ewald():

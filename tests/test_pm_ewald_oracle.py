@@ -1,5 +1,6 @@
 """Pins of the long-range CPU references (PM and Ewald)."""
 import numpy as np
+import pytest
 
 from oracle import pm_ewald
 from paper_2006_14952_amd import inputs
@@ -80,3 +81,44 @@ def test_poly_split_pm_plus_short_range_is_newtonian():
         sr = bruteforce(pos, m, make_params(rs=rs, rcut=rc, split=split))
         tot[split] = np.sqrt(((pm + sr - ew) ** 2).sum(1).mean()) / scale
     assert tot[1] < 1e-4 and tot[0] < 1e-3 and tot[1] < tot[0], tot
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_assignment_weights_are_the_b_spline_of_their_order(order):
+    """Each weight equals the order-p B-spline (p-fold convolution of the unit box,
+    formed here numerically on a fine grid) at the node's distance from the particle;
+    the weights sum to 1 and keep the particle's position as their mean."""
+    from scipy.signal import fftconvolve
+    h = 1e-4
+    box1 = np.ones(int(round(1 / h)))
+    spline = box1.copy()
+    for _ in range(order - 1):
+        spline = fftconvolve(spline, box1) * h
+    xs = (np.arange(len(spline)) + 0.5) * h - order / 2.0  # support [-p/2, p/2]
+    rng = inputs.rng_for(205, order)
+    M = 16
+    pos = rng.random((500, 3))
+    first, w = pm_ewald.assignment(pos, 1.0, M, order)
+    g = pos * M - 0.5                                      # particle in node units
+    np.testing.assert_allclose(w.sum(-1), 1.0, atol=1e-14)
+    nodes = first[:, :, None] + np.arange(order)          # mod M: unwrap by the nearest image
+    d = (nodes - g[:, :, None] + M / 2) % M - M / 2
+    np.testing.assert_allclose((w * (g[:, :, None] + d)).sum(-1), g, atol=1e-12)
+    np.testing.assert_allclose(w, np.interp(d, xs, spline), atol=5e-4)
+    assert np.all(np.abs(d) <= order / 2.0 + 1e-12)
+
+
+def test_higher_order_assignment_brings_pm_closer_to_ewald():
+    """The PM step approximates the reciprocal Ewald sum; with the window divided out,
+    its aliasing error falls as the assignment order rises (CIC > TSC > PCS)."""
+    rng = inputs.rng_for(206)
+    pos, m = inputs.clustered(3000, 4, rng)
+    M = 32
+    rs = 1.25 / M
+    ew = pm_ewald.ewald_reciprocal(pos, m, 1.0, rs)
+    err = {}
+    for order in (2, 3, 4):
+        pm = pm_ewald.pm_forces(pos, m, 1.0, rs, M, order=order)
+        err[order] = np.sqrt(((pm - ew) ** 2).sum(1).mean() / (ew ** 2).sum(1).mean())
+    assert err[2] > err[3] > err[4], err
+    assert err[4] < 0.5 * err[2], err
