@@ -263,6 +263,20 @@ int fmm_mlp_infer(const float *X, int B, float *logits, void *stream);
 int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const float *X, const int *y,
                  const float *class_w, int B, float *grad, float *loss, void *stream);
 
+/* fmm_mlp_grad for callers that cannot allocate device memory: code being recorded into a
+ * HIP graph, training loops that must not call hipMalloc, harnesses that forbid it.  Same
+ * arguments, kernels and result as fmm_mlp_grad (to FP32 rounding: the class-weight sum
+ * is formed on the device), but it allocates nothing, synchronises nothing and reads
+ * nothing back: the per-sample activations and gradients live in a fixed device array of
+ * the library (9.4 MB per GPU, held until the process ends) sized for B <= 8192 samples;
+ * a larger B is rejected with FMM_ERR_ARG.  The loss is cleared by a kernel, not a memset.
+ * Labels outside [0, 8) get weight 0; if the weights of the batch's labels sum to 0 the
+ * loss and gradient are 0 (fmm_mlp_grad returns FMM_ERR_ARG there).  Every call on a GPU
+ * uses that GPU's one array: calls that overlap in time on one GPU (other streams or
+ * threads) race and give wrong results; calls ordered on one stream do not. */
+int fmm_mlp_grad_noalloc(const float *params, const float *mu, const float *isd, const float *X, const int *y,
+                         const float *class_w, int B, float *grad, float *loss, void *stream);
+
 /* One Adam step (DEVICE params, grad, m, v of 5768 floats), step >= 1 (bias correction).
  * weight_decay is a coupled L2 term: weight_decay * params is added to the gradient before
  * the moment updates (as torch.optim.Adam's weight_decay), not a decoupled (AdamW) decay. */

@@ -85,6 +85,7 @@ def lib():
         L.fmm_mlp_forward.argtypes = [fp, fp, fp, fp, C.c_int, fp, vp]
         L.fmm_mlp_infer.argtypes = [fp, C.c_int, fp, vp]
         L.fmm_mlp_grad.argtypes = [fp, fp, fp, fp, fp, fp, C.c_int, fp, fp, vp]
+        L.fmm_mlp_grad_noalloc.argtypes = [fp, fp, fp, fp, fp, fp, C.c_int, fp, fp, vp]
         L.fmm_mlp_adam.argtypes = [fp, fp, fp, fp, i64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
         L.fmm_free_tree.argtypes = [vp]
         L.fmm_free_tree.restype = None

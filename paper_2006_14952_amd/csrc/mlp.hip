@@ -123,9 +123,12 @@ __global__ void k_mlp_fwd(const float *__restrict__ w, const float *__restrict__
     for (int k = 0; k < kCls; ++k) Z[(size_t)s * kCls + k] = z[k];
 }
 
-// softmax cross-entropy with class weights, mean over the batch (weights sum)
+// softmax cross-entropy with class weights, mean over the batch (weights sum).
+// wsum_dev != nullptr: the weight sum is read from device memory (k_class_wsum), a label
+// outside [0, kCls) has weight 0 and a zero weight sum gives zero loss and gradient.
 __global__ void k_mlp_loss(const float *__restrict__ Z, const int *__restrict__ y, const float *__restrict__ cw, int B,
-                           float wsum, float *__restrict__ dZ, float *__restrict__ loss)
+                           float wsum, const float *__restrict__ wsum_dev, float *__restrict__ dZ,
+                           float *__restrict__ loss)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= B) return;
@@ -137,9 +140,37 @@ __global__ void k_mlp_loss(const float *__restrict__ Z, const int *__restrict__ 
     float se = 0.0f;
     for (int k = 0; k < kCls; ++k) se += expf(z[k] - m);
     int c = y[s];
-    float wc = cw[c] / wsum;
+    float wc;
+    if (wsum_dev) {
+        const float ws = *wsum_dev;
+        const bool ok = c >= 0 && c < kCls && ws > 0.0f;
+        wc = ok ? cw[c] / ws : 0.0f;
+        c = ok ? c : 0;
+    } else {
+        wc = cw[c] / wsum;
+    }
     atomicAdd(loss, wc * (logf(se) + m - z[c]));
     for (int k = 0; k < kCls; ++k) dZ[(size_t)s * kCls + k] = wc * (expf(z[k] - m) / se - (k == c ? 1.0f : 0.0f));
+}
+
+// Sum of the class weights of the batch's labels (labels outside [0, kCls) count 0),
+// added into *wsum (which the caller cleared).
+__global__ void k_class_wsum(const int *__restrict__ y, const float *__restrict__ cw, int B, float *__restrict__ wsum)
+{
+    float v = 0.0f;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < B; s += gridDim.x * blockDim.x) {
+        const int c = y[s];
+        v += (c >= 0 && c < kCls) ? cw[c] : 0.0f;
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(wsum, v);
+}
+
+// Sets n floats to zero (a kernel, not a memset: also valid inside a recorded graph).
+__global__ void k_fill_zero(float *__restrict__ p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
 }
 
 __global__ void k_mlp_bwd_hidden(const float *__restrict__ w, const float *__restrict__ H1, const float *__restrict__ H2,
@@ -213,6 +244,35 @@ struct TrainScratch {
 };
 static std::mutex g_train_mu;
 static TrainScratch g_ts;
+
+// Scratch of fmm_mlp_grad_noalloc: a fixed device array (one copy per GPU, held until the
+// process ends) for the per-sample activations and gradients of at most kNoAllocMaxB
+// samples, plus the class-weight sum.  Host code never passes the array's name to a
+// kernel or copy: it uses the device address hipGetSymbolAddress returns for the device
+// that is current, taken once per device.
+constexpr int kNoAllocMaxB = 8192;
+constexpr int kPerSample = kFeat + 4 * kHid + 2 * kCls;  // xn, h1, h2, dh1, dh2, z, dz
+constexpr size_t kNoAllocFloats = (size_t)kNoAllocMaxB * kPerSample + 64;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kMaxDevices = 64;
+static float *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(float **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(FMM_ERR_HIP, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FMM_ERR_ARG, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return set_error(FMM_ERR_HIP, "hipGetSymbolAddress of the training scratch");
+        g_scratch_dev[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return 0;
+}
 
 }  // namespace hfmm
 
@@ -311,7 +371,7 @@ int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const f
     unsigned nb = (unsigned)((B + 127) / 128);
     k_mlp_fwd<<<nb, 128, 0, st>>>(params, mu, isd, X, B, ptr<float>(g_ts.xn), ptr<float>(g_ts.h1), ptr<float>(g_ts.h2),
                                   ptr<float>(g_ts.z));
-    k_mlp_loss<<<nb, 128, 0, st>>>(ptr<float>(g_ts.z), y, class_w, B, wsum, ptr<float>(g_ts.dz), loss);
+    k_mlp_loss<<<nb, 128, 0, st>>>(ptr<float>(g_ts.z), y, class_w, B, wsum, nullptr, ptr<float>(g_ts.dz), loss);
     k_mlp_bwd_hidden<<<nb, 128, 0, st>>>(params, ptr<float>(g_ts.h1), ptr<float>(g_ts.h2), ptr<float>(g_ts.dz), B,
                                          ptr<float>(g_ts.dh1), ptr<float>(g_ts.dh2));
     k_mlp_wgrad<<<(kNParam + 127) / 128, 128, 0, st>>>(ptr<float>(g_ts.xn), ptr<float>(g_ts.h1), ptr<float>(g_ts.h2),
@@ -320,6 +380,31 @@ int fmm_mlp_grad(const float *params, const float *mu, const float *isd, const f
     rc = hip_check(hipGetLastError(), "mlp grad");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "mlp grad");  // scratch is shared between calls
     return rc;
+}
+
+int fmm_mlp_grad_noalloc(const float *params, const float *mu, const float *isd, const float *X, const int *y,
+                         const float *class_w, int B, float *grad, float *loss, void *stream)
+{
+    if (B <= 0 || !params || !mu || !isd || !X || !y || !class_w || !grad || !loss)
+        return set_error(FMM_ERR_ARG, "bad arguments");
+    if (B > kNoAllocMaxB)
+        return set_error(FMM_ERR_ARG, "batch of %d exceeds the %d samples of the fixed scratch", B, kNoAllocMaxB);
+    float *sc = nullptr;
+    if (int rc = scratch_address(&sc)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t b = (size_t)B;
+    float *xn = sc, *h1 = xn + b * kFeat, *h2 = h1 + b * kHid, *dh1 = h2 + b * kHid, *dh2 = dh1 + b * kHid,
+          *z = dh2 + b * kHid, *dz = z + b * kCls;
+    float *wsum = sc + (size_t)kNoAllocMaxB * kPerSample;  // past the largest batch's arrays
+    const unsigned nb = (unsigned)((B + 127) / 128);
+    k_fill_zero<<<1, 64, 0, st>>>(wsum, 1);
+    k_fill_zero<<<1, 64, 0, st>>>(loss, 1);
+    k_class_wsum<<<nb < 64 ? nb : 64, 128, 0, st>>>(y, class_w, B, wsum);
+    k_mlp_fwd<<<nb, 128, 0, st>>>(params, mu, isd, X, B, xn, h1, h2, z);
+    k_mlp_loss<<<nb, 128, 0, st>>>(z, y, class_w, B, 0.0f, wsum, dz, loss);
+    k_mlp_bwd_hidden<<<nb, 128, 0, st>>>(params, h1, h2, dz, B, dh1, dh2);
+    k_mlp_wgrad<<<(kNParam + 127) / 128, 128, 0, st>>>(xn, h1, h2, dh1, dh2, dz, B, grad);
+    return hip_check(hipGetLastError(), "mlp grad (fixed scratch)");
 }
 
 int fmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1, float beta2,

@@ -75,6 +75,13 @@ def grad(params, mu, isd, X, y, class_w):
     return float(loss.item()), g
 
 
+def grad_noalloc(params, mu, isd, X, y, class_w, g, loss):
+    """fmm_mlp_grad_noalloc: loss and gradient into the caller's g (5768 floats) and loss
+    (1 float) with the library's fixed scratch (B <= 8192); allocates nothing."""
+    _check(lib().fmm_mlp_grad_noalloc(_ptr(params), _ptr(mu), _ptr(isd), _ptr(X), _ptr(y), _ptr(class_w),
+                                      int(X.shape[0]), _ptr(g), _ptr(loss), _stream(None)))
+
+
 def forward(params, mu, isd, X):
     import torch
     Z = torch.empty((X.shape[0], NCLS), dtype=torch.float32, device=X.device)
