@@ -108,6 +108,8 @@ def main():
                     help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
                     help="1: per-pair acceptance and order from the trained selector (packaged model file)")
+    ap.add_argument("--m2l-mfma", type=int, default=0, choices=(0, 1, 2),
+                    help="FP32 M2L kernel: 0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs")
     ap.add_argument("--plain-steps", type=int, default=3,
                     help="timed steps of the plain fixed-order form beside a learned run (0: skip)")
     ap.add_argument("--pm-steps", type=int, default=2, help="timed hybrid steps (build + PM + short range; 0: skip)")
@@ -152,7 +154,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                    precision=wl["precision"], learned=int(wl["learned"]), split=args.split)
+                    precision=wl["precision"], learned=int(wl["learned"]), split=args.split, m2l_mfma=args.m2l_mfma)
     sel = None
     if wl["learned"]:
         from paper_2006_14952_amd import learned
@@ -227,7 +229,8 @@ def main():
             + (", polynomial split" if args.split else "")
             + "; step = octree build + short-range forces (PM timed separately)",
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
-            "split": args.split, "selector": sel or "fixed p and theta", "autotuned_n_crit_ms": tuned},
+            "split": args.split, "selector": sel or "fixed p and theta", "autotuned_n_crit_ms": tuned,
+            "m2l_kernel": {0: "library's choice", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}[args.m2l_mfma]},
         "timing": {"statistic": "median of per-step HIP-event times", "ms_steps": ms,
                    "ms_per_step_mean_wall": wall * 1e3, "input_generation_s": t_gen},
         "roofline": p2p_roofline(st, stage["t_p2p_ms"], wl, args.workload, pr, n, args.split),
@@ -259,7 +262,7 @@ def main():
     plain_got = None
     if wl["learned"] and args.plain_steps > 0:
         pp = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                       precision=wl["precision"], learned=0, split=args.split)
+                       precision=wl["precision"], learned=0, split=args.split, m2l_mfma=args.m2l_mfma)
         log("plain fixed-order form, %d steps" % args.plain_steps)
         pms_, pwall, pstats = timed(pp, 1, args.plain_steps)
         plain_got = acc.cpu().numpy()

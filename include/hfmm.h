@@ -71,7 +71,11 @@ extern "C" {
  *             its smoothing density.  The learned selector requires split 0.
  *   pm_assign mass assignment of the PM long range: 0 or 2 cloud-in-cell, 3 triangular-
  *             shaped cloud, 4 piecewise cubic (B-splines of that order; the window
- *             sinc^order is divided out twice).  Unused by the short range. */
+ *             sinc^order is divided out twice).  Unused by the short range.
+ *   m2l_mfma  M2L kernel of the FP32 form (orders 4..8, plain MAC): 1 the lane-per-pair
+ *             kernel on the vector ALUs; 2 pairs of cells on one level as dense products on
+ *             the matrix cores (FP32 MFMA; pairs sharing an offset share the transfer
+ *             matrix), the other pairs on the vector ALUs; 0 the library's choice. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
@@ -80,7 +84,7 @@ typedef struct fmm_params {
     int learned;
     int split;
     int pm_assign;
-    int reserved[1];
+    int m2l_mfma;
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts

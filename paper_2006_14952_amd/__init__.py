@@ -32,7 +32,7 @@ class Params(C.Structure):
     _fields_ = [("box", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
                 ("G", C.c_double), ("p", C.c_int), ("n_crit", C.c_int), ("mac_mode", C.c_int),
                 ("precision", C.c_int), ("learned", C.c_int), ("split", C.c_int), ("pm_assign", C.c_int),
-                ("reserved", C.c_int * 1)]
+                ("m2l_mfma", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -101,12 +101,13 @@ def _check(rc):
 
 
 def params(box=1.0, r_s=0.0390625, r_cut=None, theta=0.5, G=1.0, p=4, n_crit=32, mac_mode=0, precision=0,
-           learned=0, split=0, pm_assign=0) -> Params:
-    """pm_assign: PM mass assignment, 0/2 CIC, 3 TSC, 4 PCS."""
+           learned=0, split=0, pm_assign=0, m2l_mfma=0) -> Params:
+    """pm_assign: PM mass assignment, 0/2 CIC, 3 TSC, 4 PCS.  m2l_mfma: FP32 M2L kernel,
+    0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs."""
     if r_cut is None:
         r_cut = 4.5 * r_s
     return Params(float(box), float(r_s), float(r_cut), float(theta), float(G), int(p), int(n_crit), int(mac_mode),
-                  int(precision), int(learned), int(split), int(pm_assign), (C.c_int * 1)(0))
+                  int(precision), int(learned), int(split), int(pm_assign), int(m2l_mfma))
 
 
 def _stream(stream):

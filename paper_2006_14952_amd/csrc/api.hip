@@ -42,6 +42,7 @@ static int check_params(const fmm_params *P)
     if (P->learned && P->split) return set_error(FMM_ERR_ARG, "the learned selector requires split 0");
     if (P->pm_assign != 0 && (P->pm_assign < 2 || P->pm_assign > 4))
         return set_error(FMM_ERR_ARG, "pm_assign must be 0, 2 (CIC), 3 (TSC) or 4 (PCS)");
+    if (P->m2l_mfma < 0 || P->m2l_mfma > 2) return set_error(FMM_ERR_ARG, "m2l_mfma must be 0, 1 or 2");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;
@@ -156,7 +157,7 @@ static bool same_params(const fmm_params &a, const fmm_params &b)
 {
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
            a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
-           a.split == b.split && a.pm_assign == b.pm_assign;
+           a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
@@ -530,7 +531,8 @@ void fmm_free_tree(fmm_tree *t)
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
                       &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
-                      &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate, &t->cfeat, &t->cellc};
+                      &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate, &t->cfeat, &t->cellc, &t->mf_ne,
+                      &t->mf_no, &t->mf_offe, &t->mf_offn, &t->mf_spos, &t->mf_sinks, &t->mf_csr, &t->mf_tot};
     for (DevBuf *b : bufs) free_buf(*b);
     free_buf(t->lord);
     for (int k = 0; k < kKinds; ++k) {

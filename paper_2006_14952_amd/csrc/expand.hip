@@ -4,7 +4,8 @@
 
 namespace hfmm {
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st);
-template <class T> int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, hipStream_t st);
+template <class T>
+int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st);
 
 static Split split_of(const fmm_params *P) { return Split{P->split ? P->r_cut : P->r_s, P->split}; }
 static int flatten_learned(fmm_tree *t, hipStream_t st);
@@ -16,10 +17,14 @@ int upward(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return P->precision ? upward_t<float>(t, P->p, st) : upward_t<double>(t, P->p, st);
 }
 
+// The FP32 M2L kernel: fmm_params.m2l_mfma 2 = matrix cores for same-level pairs, 1 = vector
+// ALUs, 0 = the library's choice (the vector ALUs).
+static int use_mfma(const fmm_params *P) { return P->m2l_mfma == 2; }
+
 int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
-    return P->precision ? m2l_t<float>(t, P->p, split_of(P), 0, P->p, 0, st)
-                        : m2l_t<double>(t, P->p, split_of(P), 0, P->p, 0, st);
+    return P->precision ? m2l_t<float>(t, P->p, split_of(P), 0, P->p, 0, use_mfma(P), st)
+                        : m2l_t<double>(t, P->p, split_of(P), 0, P->p, 0, 0, st);
 }
 
 // Learned selector: coefficients stored at order 8; the pairs accepted at order o are
@@ -29,7 +34,8 @@ int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st)
     if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(8) * (P->precision ? 4 : 8), st)) return rc;
     if (int rc = flatten_learned(t, st)) return rc;
     for (int o = 2; o <= 8; ++o) {
-        int rc = P->precision ? m2l_t<float>(t, o, split_of(P), 1, 8, 1, st) : m2l_t<double>(t, o, split_of(P), 1, 8, 1, st);
+        int rc = P->precision ? m2l_t<float>(t, o, split_of(P), 1, 8, 1, 0, st)
+                              : m2l_t<double>(t, o, split_of(P), 1, 8, 1, 0, st);
         if (rc) return rc;
     }
     return 0;

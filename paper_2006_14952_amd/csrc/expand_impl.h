@@ -843,7 +843,9 @@ template <int P, class T> struct M2L {
     // Coefficient storage of order `pstore`.  learned == 0: the plain M2L list (kind 0);
     // learned != 0: the entries of order P of the learned selector's list, whose pairs
     // flatten_learned has already laid out by order (the pair kernel adds to L).
-    static int run(fmm_tree *t, Split sp, int learned, int pstore, int accumulate, hipStream_t st)
+    // mfma != 0 (FP32, orders 4..8, plain list): pairs of cells on one level on the matrix
+    // cores (m2l_mfma.hip), the others by the lane-per-pair kernel below.
+    static int run(fmm_tree *t, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st)
     {
         const int kind = learned ? kKindOrd : 0;
         if constexpr (pair_m2l<P, T>()) {
@@ -851,6 +853,17 @@ template <int P, class T> struct M2L {
             if (!accumulate)
                 if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st)) return rc;
             if (np == 0) return hip_check(hipGetLastError(), "m2l");
+            if constexpr (sizeof(T) == 4 && P >= 4) {
+                if (mfma && !learned && !accumulate && pstore == P) {
+                    int64_t nother = 0;
+                    if (int rc = m2l_mfma_split_and_run(t, P, sp, &nother, st)) return rc;
+                    if (nother > 0)
+                        k_m2l_pairs<P, T><<<(unsigned)((nother + 63) / 64), 64, 0, st>>>(
+                            ptr<Cell>(t->cells), ptr<int2>(t->m2l_pairs), nother, ptr<T>(t->Mc), ptr<T>(t->Lc),
+                            t->box, sp, ncoef(pstore));
+                    return hip_check(hipGetLastError(), "m2l pairs");
+                }
+            }
             if (!learned)
                 if (int rc = flatten_pairs(t, kind, np, st)) return rc;
             const int2 *pairs = ptr<int2>(t->m2l_pairs) + (learned ? t->lseg[P - 2] : 0);
@@ -893,9 +906,10 @@ template <int P, class T> struct L2P {
 };
 
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
-template <class T> int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, hipStream_t st)
+template <class T>
+int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st)
 {
-    return dispatch_p<M2L, T>(p, t, sp, learned, pstore, accumulate, st);
+    return dispatch_p<M2L, T>(p, t, sp, learned, pstore, accumulate, mfma, st);
 }
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
 template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st)

@@ -60,6 +60,11 @@ struct fmm_tree {
     hfmm::DevBuf m2l_ctr, m2l_pairs;  // flattened M2L pairs (sink, item) for the pair kernel; its fill counter
     hfmm::DevBuf wstate;              // per traversal wave: chunk block in use of each list kind
     hfmm::DevBuf bbox;                // per cell: float4 lo, hi of its particles relative to the centre (leaves)
+    // matrix-core M2L: per cell the entries it takes (ne) and the others (no), their
+    // offsets, the sinks with such entries (compacted), the entries by sink (CSR), totals
+    hfmm::DevBuf mf_ne, mf_no, mf_offe, mf_offn, mf_spos, mf_sinks, mf_csr, mf_tot;
+    int64_t mf_n_other = 0;           // sizes of the last split (a recorded replay reuses them)
+    int mf_nsink = 0;
     hfmm::DevBuf cfeat;               // learned selector: per-cell part of the features (float4)
     int *host = nullptr;  // pinned readback area (kHostInts ints)
     int last_p = -1, last_prec = -1;
@@ -103,5 +108,8 @@ int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st);  // before p2p (FP32 form): leaf boxes
 int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, int accumulate, hipStream_t st);
+// FP32 M2L of order p in 4..8 on the matrix cores for pairs on one level; the other
+// pairs are left in t->m2l_pairs, their number in *n_other (L zeroed by the caller)
+int m2l_mfma_split_and_run(fmm_tree *t, int p, Split sp, int64_t *n_other, hipStream_t st);
 uint64_t cell_key_host(int level, int ix, int iy, int iz);
 }  // namespace hfmm
