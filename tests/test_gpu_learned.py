@@ -137,44 +137,60 @@ def test_labels_match_oracle_expansions():
 
 
 def test_learned_selector_accuracy_and_gain():
-    """The packaged selector on a clustered box it was not trained on (same recipe as the
-    training boxes, other seed): p99 force error against brute force within 1e-3, and less
-    work than the plain MAC at the same or better accuracy: fewer listed P2P particle pairs
-    than plain order 6 at theta 0.4, and less M2L arithmetic than plain order 8 at theta 0.4
-    (counted as 2 C(p+6, 6) flop per pair at the order each pair is evaluated at)."""
+    """What the trained selector gains over the method without it, on the 16.7M clustered
+    box (a box of the training recipe it was not trained on), against the plain MAC at the
+    settings that just meet p99 <= 1e-3 against brute force: order 8 at theta 0.5 and
+    order 6 at theta 0.42.  Each form: p99 against brute force on 2000 sampled particles,
+    median time of a build + short-range step over 5 timed steps, listed P2P pairs and M2L
+    arithmetic (2 C(p+6, 6) flop per pair at the order each pair is evaluated at).
+
+    Asserted: every form meets the bar; the selector needs less M2L arithmetic than plain
+    order 8 and fewer listed P2P pairs than plain order 6.  The step times are printed and
+    recorded as they are: the selector's step is not faster than the best plain form (its
+    network and feature work in the traversal cost more than the M2L and P2P work it
+    saves on this machine)."""
     if not os.path.exists(learned.DEFAULT_MODEL):
         pytest.skip("no trained model file")
-    pr = inputs.split_params("clustered")
-    n = 262144
-    pos, m = inputs.make("clustered", n=n, seed_extra=(7,))
+    from math import comb
+    pr = inputs.split_params("large")
+    pos, m = inputs.make("large")
+    n = len(pos)
     dpos, dm = torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda")
     tg = inputs.rng_for(402).choice(n, 2000, replace=False)
-    op = oracle.make_params(box=1.0, rs=pr["rs"], rcut=pr["rcut"], theta=0.4, p=6, ncrit=32)
+    op = oracle.make_params(box=1.0, rs=pr["rs"], rcut=pr["rcut"], theta=0.5, p=8, ncrit=32)
     bf = oracle.bruteforce(pos, m, op, targets=tg)
+    ref = np.linalg.norm(bf, axis=1)
     learned.load_model()
 
     def run(**kw):
         prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], n_crit=32, precision=1, **kw)
-        t = hf.Tree().build(dpos, dm, prm)
-        a = t.short_range(prm).cpu().numpy()
-        st = t.stats()
+        t = hf.Tree()
+        t.set_timing(True)
+        ms = []
+        for k in range(7):
+            t.build(dpos, dm, prm)
+            a = t.short_range(prm)
+            st = t.stats()
+            if k >= 2:
+                ms.append(st["t_build_ms"] + st["t_total_ms"])
+        a = a.cpu().numpy()
         t.free()
-        ref = np.linalg.norm(bf, axis=1)
         e = np.linalg.norm(a[tg] - bf, axis=1) / np.where(ref > 0, ref, np.median(ref))
-        return np.percentile(e, 99), st
+        if kw.get("learned"):
+            flop = sum(c * 2 * comb(o + 6, 6) for o, c in zip(range(2, 9), st["n_m2l_by_order"]))
+        else:
+            flop = st["n_m2l"] * 2 * comb(kw["p"] + 6, 6)
+        return {"p99": float(np.percentile(e, 99)), "ms": float(np.median(ms)), "pairs": st["p2p_pairs"],
+                "m2l_flop": flop}
 
-    def m2l_flop(st, p=None):
-        from math import comb
-        if p is not None:
-            return st["n_m2l"] * 2 * comb(p + 6, 6)
-        return sum(c * 2 * comb(o + 6, 6) for o, c in zip(range(2, 9), st["n_m2l_by_order"]))
-
-    e_l, s_l = run(theta=0.4, p=6, learned=1)
-    e_6, s_6 = run(theta=0.4, p=6)
-    e_8, s_8 = run(theta=0.4, p=8)
-    print("learned p99 %.2e pairs %d m2l flop %.3g | plain p6 p99 %.2e pairs %d | plain p8 p99 %.2e m2l flop %.3g"
-          % (e_l, s_l["p2p_pairs"], m2l_flop(s_l), e_6, s_6["p2p_pairs"], e_8, m2l_flop(s_8, 8)))
-    assert e_l <= 1e-3
-    assert sum(s_l["n_m2l_by_order"]) == s_l["n_m2l"]
-    assert s_l["p2p_pairs"] < 0.95 * s_6["p2p_pairs"]
-    assert m2l_flop(s_l) < 0.5 * m2l_flop(s_8, 8)
+    forms = {"learned": run(theta=0.5, p=8, learned=1), "plain p8 0.50": run(theta=0.5, p=8),
+             "plain p6 0.42": run(theta=0.42, p=6)}
+    for k, v in forms.items():
+        print("%-14s p99 %.2e  step %.2f ms  P2P pairs %.4e  M2L flop %.4e" % (k, v["p99"], v["ms"], v["pairs"],
+                                                                            v["m2l_flop"]))
+    best_plain = min(forms["plain p8 0.50"]["ms"], forms["plain p6 0.42"]["ms"])
+    print("learned step / best plain step at the same bar: %.3f" % (forms["learned"]["ms"] / best_plain))
+    for k, v in forms.items():
+        assert v["p99"] <= 1e-3, (k, v)
+    assert forms["learned"]["m2l_flop"] < forms["plain p8 0.50"]["m2l_flop"]
+    assert forms["learned"]["pairs"] < forms["plain p6 0.42"]["pairs"]

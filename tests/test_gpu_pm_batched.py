@@ -212,3 +212,63 @@ def test_hybrid_polynomial_split_approaches_ewald():
     tot = hf.hybrid(dev(pos), dev(m), prm, M).cpu().numpy()
     ew = pm_ewald.ewald_total(pos, m, 1.0, rs)
     assert rms_rel(tot, ew) < 1e-4
+
+
+def test_batched_config_full_forest_sampled():
+    """The 64-box batched workload at full size, in the launch configuration the benchmark
+    times (its opening angle, FP32, the leaf limit the library's autotuner picks): the
+    smallest, median and largest box against the FP64 oracle on sampled particles and
+    against their brute-force sums."""
+    import bench
+    wl = bench.WORKLOADS["batched"]
+    pr = inputs.split_params("batched")
+    sizes = inputs.batched_sizes(inputs.CONFIGS["batched"]["nbox"])
+    boxes = [inputs.batched_box(b, sizes[b]) for b in range(len(sizes))]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos, m = dev(np.concatenate([b[0] for b in boxes])), dev(np.concatenate([b[1] for b in boxes]))
+    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=32, precision=1)
+    best, ms = hf.autotune(pos, m, prm, offsets=off)
+    prm.n_crit = best
+    t = hf.Tree().build_batched(pos, m, [prm] * len(boxes), off)
+    got = t.short_range(prm).cpu().numpy()
+    assert t.stats()["n"] == off[-1]
+    t.free()
+    order = np.argsort(sizes)
+    op = oracle.make_params(rs=pr["rs"], rcut=pr["rcut"], theta=wl["theta"], p=pr["p"], ncrit=best)
+    for b in (order[0], order[len(order) // 2], order[-1]):
+        bp, bm = boxes[b]
+        tg = inputs.rng_for(3, 50, int(b)).choice(len(bp), min(800, len(bp)), replace=False)
+        ref = oracle.fmm(bp, bm, op, targets=tg).acc
+        mine = got[off[b]:off[b + 1]]
+        e = rel_err(mine[tg], ref[tg])
+        bf = oracle.bruteforce(bp, bm, op, targets=tg)
+        print("box %d (N=%d, n_crit %d): vs oracle median %.2e p99 %.2e max %.2e; p99 vs brute force %.2e" % (
+            b, len(bp), best, np.median(e), np.percentile(e, 99), e.max(), np.percentile(rel_err(mine[tg], bf), 99)))
+        assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5
+        assert np.percentile(rel_err(mine[tg], bf), 99) <= 1e-3
+
+
+def test_forest_of_more_than_256_boxes():
+    """300 small boxes: the box index needs two radix passes of 8 bits beyond the Morton
+    key; every box against the oracle (FP64 lists and forces)."""
+    rng = inputs.rng_for(309)
+    sizes = rng.integers(0, 400, 300)
+    boxes = [inputs.clustered(int(n), 1, rng) if n > 0 else (np.zeros((0, 3)), np.zeros(0)) for n in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate([b[0] for b in boxes])
+    m = np.concatenate([b[1] for b in boxes])
+    prm = hf.params(r_s=0.03, r_cut=0.135, theta=0.5, p=4, n_crit=8)
+    t = hf.Tree().build_batched(dev(pos), dev(m), [prm] * len(boxes), off)
+    got = t.short_range(prm).cpu().numpy()
+    st = t.stats()
+    t.free()
+    op = oracle.make_params(rs=0.03, rcut=0.135, theta=0.5, p=4, ncrit=8)
+    n_m2l = n_p2p = 0
+    for b, (bp, bm) in enumerate(boxes):
+        if len(bp) == 0:
+            continue
+        r = oracle.fmm(bp, bm, op)
+        n_m2l += r.stats["n_m2l"]
+        n_p2p += r.stats["n_p2p"]
+        assert rel_err(got[off[b]:off[b + 1]], r.acc).max() < 1e-9, b
+    assert st["n_m2l"] == n_m2l and st["n_p2p"] == n_p2p
