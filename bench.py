@@ -51,6 +51,8 @@ WORKLOADS = {
     "batched": dict(theta=0.4, precision=1, n_crit=32, learned=False, autotune=True, cpu_cubes=0.1,
                     cpu_cubes_1t=0.01),
 }
+M2L_KERNELS = {0: "library's choice (vector ALUs)", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}
+SCHEDULES = {0: "library's choice (two streams)", 1: "two streams", 2: "one persistent P2P + M2L kernel"}
 CUBE_LEVEL = 6
 CONFIG_SAMPLE_SEED = 777
 _T0 = time.perf_counter()
@@ -103,7 +105,10 @@ def main():
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--n-crit", type=int, default=None)
     ap.add_argument("--autotune", type=int, default=None, choices=(0, 1),
-                    help="1: choose n_crit with the library's autotuner before timing (default: batched only)")
+                    help="1: choose n_crit, schedule and M2L kernel with the library's autotuner before timing "
+                         "(default: batched only)")
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2),
+                    help="P2P and M2L: 0 library's choice, 1 two kernels on two streams, 2 one persistent kernel")
     ap.add_argument("--split", type=int, default=0, choices=(0, 1),
                     help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
@@ -154,7 +159,8 @@ def main():
     t_gen = time.perf_counter() - t_gen
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                    precision=wl["precision"], learned=int(wl["learned"]), split=args.split, m2l_mfma=args.m2l_mfma)
+                    precision=wl["precision"], learned=int(wl["learned"]), split=args.split, m2l_mfma=args.m2l_mfma,
+                    schedule=args.schedule)
     sel = None
     if wl["learned"]:
         from paper_2006_14952_amd import learned
@@ -167,9 +173,9 @@ def main():
     mass = torch.tensor(m_np, device=dev)
     tuned = None
     if args.autotune if args.autotune is not None else wl.get("autotune", False):
-        best, ms = hf.autotune(pos, mass, prm, offsets=offsets if batched else None)
-        prm.n_crit = wl["n_crit"] = best
-        tuned = {str(k): round(v, 3) for k, v in ms.items()}
+        log("autotuning n_crit, schedule and M2L kernel")
+        prm, tuned = tune_kernels(hf, pos, mass, prm, offsets if batched else None)
+        wl["n_crit"] = prm.n_crit
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
     tree = hf.Tree()
@@ -229,11 +235,12 @@ def main():
             + (", polynomial split" if args.split else "")
             + "; step = octree build + short-range forces (PM timed separately)",
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
-            "split": args.split, "selector": sel or "fixed p and theta", "autotuned_n_crit_ms": tuned,
-            "m2l_kernel": {0: "library's choice", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}[args.m2l_mfma]},
+            "split": args.split, "selector": sel or "fixed p and theta", "autotuned_ms": tuned,
+            "m2l_kernel": M2L_KERNELS[prm.m2l_mfma], "schedule": SCHEDULES[prm.schedule]},
         "timing": {"statistic": "median of per-step HIP-event times", "ms_steps": ms,
                    "ms_per_step_mean_wall": wall * 1e3, "input_generation_s": t_gen},
-        "roofline": p2p_roofline(st, stage["t_p2p_ms"], wl, args.workload, pr, n, args.split),
+        "roofline": p2p_roofline(st, stage["t_p2p_ms"], wl, args.workload, pr, n, args.split,
+                                 fused=prm.schedule == 2),
         "stages_ms": stage,
         "roofline_step": stage_rooflines(st, stage, stage["t_build_ms"], med, n, pr["p"], bool(wl["learned"]),
                                          wl["precision"], args.split),
@@ -262,7 +269,8 @@ def main():
     plain_got = None
     if wl["learned"] and args.plain_steps > 0:
         pp = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
-                       precision=wl["precision"], learned=0, split=args.split, m2l_mfma=args.m2l_mfma)
+                       precision=wl["precision"], learned=0, split=args.split, m2l_mfma=args.m2l_mfma,
+                       schedule=args.schedule)
         log("plain fixed-order form, %d steps" % args.plain_steps)
         pms_, pwall, pstats = timed(pp, 1, args.plain_steps)
         plain_got = acc.cpu().numpy()
@@ -333,14 +341,28 @@ def cpu_baseline(oracle, pos, m, op, frac, nthreads, what):
     return rec, (tg, res.acc)
 
 
-def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None):
+def tune_kernels(hf, pos, mass, prm, offsets=None, n_crits=(32, 48), reps=2):
+    """The library's autotuner over the leaf limits n_crits crossed with the schedules and
+    M2L kernels that serve prm; returns the fastest parameter set and every set's ms."""
+    cands = hf.kernel_candidates(prm, n_crits=n_crits)
+    best, ms = hf.autotune_params(pos, mass, cands, reps=reps, offsets=offsets)
+    table = {"n_crit %d, %s, M2L on %s" % (c.n_crit, SCHEDULES[c.schedule], M2L_KERNELS[c.m2l_mfma]): round(t, 3)
+             for c, t in zip(cands, ms)}
+    return cands[best], table
+
+
+def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=False):
     """Roofline of the P2P kernel (the dominant one on the clustered boxes): algorithmic
     work = 38 flop per listed pair (30 with the polynomial split) over the launch's
-    HIP-event duration on its own stream, against the FP32 (or FP64) vector peak.
+    HIP-event duration on its own stream, against the FP32 (or FP64) vector peak.  Under
+    the persistent schedule the kernel is the one P2P + M2L launch and its work adds the
+    M2L arithmetic, 2 C(p+6, 6) flop per accepted pair.
     traffic: scaled FETCH_SIZE + WRITE_SIZE per launch from profiles/, when those counters
     were taken on this workload with these parameters and the current P2P sources."""
     learned = wl["learned"] if learned is None else learned
     flop = P2P_FLOP_PER_PAIR[split] * st["p2p_pairs"]
+    m2l_flop = 2 * _binom(pr["p"] + 6, 6) * st["n_m2l"] if fused else 0
+    flop += m2l_flop
     peak = PEAK["fp32_vector"] if wl["precision"] else PEAK["fp64_vector"]
     achieved = flop / (p2p_ms * 1e-3) if p2p_ms > 0 else 0.0
     traffic = None
@@ -350,11 +372,13 @@ def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None):
         same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
                                                 ("n_crit", wl["n_crit"]), ("learned", bool(learned)),
                                                 ("split", split), ("p2p_source_sha", p2p_source_sha())))
-        if same:
+        if same and not fused:
             traffic = rec.get("bytes_per_launch")
-    return {"kernel": "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+    return {"kernel": "p2p + m2l (one persistent launch)" if fused else "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "flop_per_launch": flop,
-            "unit_of_work": "%.0f flop per listed particle pair" % P2P_FLOP_PER_PAIR[split],
+            "unit_of_work": "%.0f flop per listed particle pair" % P2P_FLOP_PER_PAIR[split]
+                            + (" + 2 C(p+6,6) flop per M2L pair" if fused else ""),
+            "m2l_flop_in_launch": m2l_flop,
             "listed_pairs": st["p2p_pairs"], "evaluated_pairs": st["p2p_evaluated"],
             "p2p_ms_per_launch": p2p_ms}
 

@@ -75,7 +75,15 @@ extern "C" {
  *   m2l_mfma  M2L kernel of the FP32 form (orders 4..8, plain MAC): 1 the lane-per-pair
  *             kernel on the vector ALUs; 2 pairs of cells on one level as dense products on
  *             the matrix cores (FP32 MFMA; pairs sharing an offset share the transfer
- *             matrix), the other pairs on the vector ALUs; 0 the library's choice. */
+ *             matrix), the other pairs on the vector ALUs; 0 the library's choice.
+ *   schedule  how P2P and M2L share the GPU (the task pool of Sec. 4): 1 two kernels on
+ *             two streams, P2P beside M2L; 2 one persistent kernel whose workgroups pull
+ *             sink leaves (P2P) and then blocks of 64 M2L pairs from one device queue
+ *             until both stages are done; 0 the library's choice (1).  Schedule 2 requires
+ *             precision 1, learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, the
+ *             degree-10 force law (r_cut / r_s up to about 5.6); FMM_ERR_ARG otherwise.
+ *             The results do not depend on the schedule beyond FP32 summation order.
+ *   reserved  must be 0. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
@@ -85,6 +93,8 @@ typedef struct fmm_params {
     int split;
     int pm_assign;
     int m2l_mfma;
+    int schedule;
+    int reserved;
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts
@@ -101,6 +111,8 @@ typedef struct fmm_stats {
     int64_t p2p_evaluated;     /* particle pairs the P2P kernel evaluated: the listed pairs less
                                   those of source leaves whose particles' bounding box is
                                   farther than r_cut from the sink leaf's (FP32 form) */
+    /* stage spans (with timing on; stages on the two streams overlap); under schedule 2
+       t_m2l_ms and t_p2p_ms are both the span of the one P2P + M2L launch */
     double t_tree_ms, t_upward_ms, t_traverse_ms, t_m2l_ms, t_p2p_ms, t_downward_ms, t_total_ms;
     double t_build_ms;         /* last fmm_build_tree */
     double t_pm_ms;            /* long-range (PM) part of the last fmm_hybrid_forces_tree */
@@ -200,6 +212,21 @@ int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const in
 int fmm_autotune(const fmm_params *params, int nbox, const int64_t *offsets, int64_t n, const double *pos,
                  const double *mass, double *acc, const int *candidates, int ncand, int reps, void *stream,
                  int *best_n_crit, double *ms_out);
+
+/* Autotuner over whole parameter sets (the tile and kernel choices of Sec. 4's GPU
+ * form): times complete steps (tree build + fmm_short_range_forces) for each of the ncand
+ * parameter sets in cands (HOST array), reps timed steps each after one untimed one, and
+ * returns the index of the fastest in *best.  The sets normally differ only in what picks
+ * tile shapes and kernels: n_crit (P2P sink and source tiles, list lengths, tree depth),
+ * schedule (two streams, or one persistent P2P + M2L kernel) and m2l_mfma (vector ALUs or
+ * matrix cores); which of them may vary is the caller's choice (the lists, and so the
+ * forces, depend on n_crit).  nbox, offsets, n, pos, mass, acc: as fmm_autotune.  ms_out
+ * (host, ncand entries, may be NULL) receives each set's mean step time.  Every set is
+ * validated before any is timed (FMM_ERR_ARG names the first invalid one's fault).
+ * Uses a temporary tree; synchronises the stream. */
+int fmm_autotune_params(const fmm_params *cands, int ncand, int nbox, const int64_t *offsets, int64_t n,
+                        const double *pos, const double *mass, double *acc, int reps, void *stream, int *best,
+                        double *ms_out);
 
 /* Counters and stage times of the last force evaluation (host struct, caller-owned). */
 int fmm_get_stats(const fmm_tree *tree, fmm_stats *out);

@@ -32,7 +32,7 @@ class Params(C.Structure):
     _fields_ = [("box", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
                 ("G", C.c_double), ("p", C.c_int), ("n_crit", C.c_int), ("mac_mode", C.c_int),
                 ("precision", C.c_int), ("learned", C.c_int), ("split", C.c_int), ("pm_assign", C.c_int),
-                ("m2l_mfma", C.c_int)]
+                ("m2l_mfma", C.c_int), ("schedule", C.c_int), ("reserved", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.fmm_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.fmm_autotune.argtypes = [C.POINTER(Params), C.c_int, C.POINTER(i64), i64, dp, dp, dp, C.POINTER(C.c_int),
                                    C.c_int, C.c_int, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.fmm_autotune_params.argtypes = [C.POINTER(Params), C.c_int, C.c_int, C.POINTER(i64), i64, dp, dp, dp,
+                                          C.c_int, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.fmm_set_timing.argtypes = [vp, C.c_int]
         L.fmm_copy_interactions.argtypes = [vp, C.c_int, vp, i64, C.POINTER(i64)]
         L.fmm_load_mac_model.argtypes = [C.c_char_p]
@@ -101,13 +103,23 @@ def _check(rc):
 
 
 def params(box=1.0, r_s=0.0390625, r_cut=None, theta=0.5, G=1.0, p=4, n_crit=32, mac_mode=0, precision=0,
-           learned=0, split=0, pm_assign=0, m2l_mfma=0) -> Params:
+           learned=0, split=0, pm_assign=0, m2l_mfma=0, schedule=0) -> Params:
     """pm_assign: PM mass assignment, 0/2 CIC, 3 TSC, 4 PCS.  m2l_mfma: FP32 M2L kernel,
-    0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs."""
+    0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs.  schedule:
+    0 library's choice, 1 P2P and M2L on two streams, 2 one persistent P2P + M2L kernel."""
     if r_cut is None:
         r_cut = 4.5 * r_s
     return Params(float(box), float(r_s), float(r_cut), float(theta), float(G), int(p), int(n_crit), int(mac_mode),
-                  int(precision), int(learned), int(split), int(pm_assign), int(m2l_mfma))
+                  int(precision), int(learned), int(split), int(pm_assign), int(m2l_mfma), int(schedule), 0)
+
+
+def copy_params(prm: Params, **changes) -> Params:
+    """A copy of prm with the named fields replaced."""
+    q = Params()
+    C.pointer(q)[0] = prm
+    for k, v in changes.items():
+        setattr(q, k, v)
+    return q
 
 
 def _stream(stream):
@@ -253,6 +265,42 @@ def autotune(pos, mass, prm: Params, candidates=(16, 24, 32, 48, 64), reps=2, of
     _check(lib().fmm_autotune(C.byref(prm), nbox, off, n, _dev64(pos, (3,)), _dev64(mass), _dev64(acc, (3,)), cand,
                               len(candidates), int(reps), _stream(stream), C.byref(best), ms))
     return best.value, {int(c): float(m) for c, m in zip(candidates, ms)}
+
+
+def autotune_params(pos, mass, cands, reps=2, offsets=None, stream=None):
+    """Index of the parameter set in cands (a sequence of Params) with the fastest build +
+    short-range step on these particles (fmm_autotune_params), and the mean ms per step
+    of each set."""
+    import torch
+    n = int(pos.shape[0])
+    acc = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    arr = (Params * len(cands))(*cands)
+    ms = (C.c_double * len(cands))()
+    best = C.c_int()
+    nbox, off = 1, None
+    if offsets is not None:
+        nbox = len(offsets) - 1
+        off = (C.c_int64 * (nbox + 1))(*[int(v) for v in offsets])
+    _check(lib().fmm_autotune_params(arr, len(cands), nbox, off, n, _dev64(pos, (3,)), _dev64(mass),
+                                     _dev64(acc, (3,)), int(reps), _stream(stream), C.byref(best), ms))
+    return best.value, [float(m) for m in ms]
+
+
+def kernel_candidates(prm: Params, n_crits=(32, 48)):
+    """The tile and kernel settings the autotuner may vary for prm: each leaf limit in
+    n_crits, crossed with the two schedules and (FP32 orders 4..8, plain MAC) the two M2L
+    kernels; combinations the library does not serve are left out."""
+    fp32_plain = prm.precision == 1 and not prm.learned
+    scheds = (1, 2) if fp32_plain and 3 <= prm.p <= 8 else (1,)
+    mfmas = (1, 2) if fp32_plain and 4 <= prm.p <= 8 else (prm.m2l_mfma,)
+    out = []
+    for nc in n_crits:
+        for sc in scheds:
+            for mf in mfmas:
+                if sc == 2 and mf == 2:
+                    continue
+                out.append(copy_params(prm, n_crit=int(nc), schedule=sc, m2l_mfma=mf))
+    return out
 
 
 def pm_long_range(pos, mass, prm: Params, mesh, out=None, stream=None):

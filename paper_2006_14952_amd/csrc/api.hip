@@ -43,10 +43,15 @@ static int check_params(const fmm_params *P)
     if (P->pm_assign != 0 && (P->pm_assign < 2 || P->pm_assign > 4))
         return set_error(FMM_ERR_ARG, "pm_assign must be 0, 2 (CIC), 3 (TSC) or 4 (PCS)");
     if (P->m2l_mfma < 0 || P->m2l_mfma > 2) return set_error(FMM_ERR_ARG, "m2l_mfma must be 0, 1 or 2");
+    if (P->schedule < 0 || P->schedule > 2) return set_error(FMM_ERR_ARG, "schedule must be 0, 1 or 2");
+    if (P->reserved != 0) return set_error(FMM_ERR_ARG, "reserved must be 0");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;
     }
+    if (P->schedule == 2 && !fused_applies(P))
+        return set_error(FMM_ERR_ARG, "schedule 2 (one persistent P2P + M2L kernel) requires precision 1, learned 0, "
+                                      "3 <= p <= 8, m2l_mfma != 2 and the degree-10 force law");
     return 0;
 }
 
@@ -117,18 +122,31 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
     }
     if (rc) return rc;
     mark(t, 2, st);
-    if ((rc = hip_check(hipEventRecord(t->dep[2], st), "event")) || (rc = hip_check(hipStreamWaitEvent(ax, t->dep[2], 0), "event wait")))
+    const bool fused = P->schedule == 2;
+    if (fused) {  // P2P and M2L in one persistent launch on st, after the second stream's work
+        if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[3], 0), "event wait")))
+            return rc;
+        if ((rc = p2p_m2l_fused_prepare(t, P, st))) return rc;
+        mark(t, 5, st);
+        if ((rc = p2p_m2l_fused_launch(t, P, st))) return rc;
+        mark(t, 6, st);
+        mark(t, 3, st);
+    }
+    if (!fused && ((rc = hip_check(hipEventRecord(t->dep[2], st), "event")) ||
+                   (rc = hip_check(hipStreamWaitEvent(ax, t->dep[2], 0), "event wait"))))
         return rc;
-    mark(t, 5, ax);
-    if ((rc = p2p(t, P, ax))) return rc;
-    mark(t, 6, ax);
-    if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[1], 0), "event wait")))
-        return rc;
-    if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
-    mark(t, 3, st);
+    if (!fused) mark(t, 5, ax);
+    if (!fused) {
+        if ((rc = p2p(t, P, ax))) return rc;
+        mark(t, 6, ax);
+        if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[1], 0), "event wait")))
+            return rc;
+        if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
+        mark(t, 3, st);
+    }
     if ((rc = downward_l2l(t, &P8, st))) return rc;
     mark(t, 4, st);
-    if ((rc = hip_check(hipStreamWaitEvent(st, t->dep[3], 0), "event wait"))) return rc;
+    if (!fused && (rc = hip_check(hipStreamWaitEvent(st, t->dep[3], 0), "event wait"))) return rc;
     mark(t, 10, st);
     if ((rc = l2p_combine(t, &P8, acc, accumulate, st))) return rc;
     mark(t, 11, st);
@@ -143,7 +161,7 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
         if ((rc = hip_check(hipEventSynchronize(t->ev[11]), "timing event"))) return rc;
         S.t_upward_ms = ev_ms(t, 9, 1);
         S.t_traverse_ms = P->learned ? ev_ms(t, 1, 2) : ev_ms(t, 0, 2);
-        S.t_m2l_ms = ev_ms(t, 2, 3);
+        S.t_m2l_ms = fused ? ev_ms(t, 5, 6) : ev_ms(t, 2, 3);  // schedule 2: both stages are one launch
         S.t_downward_ms = ev_ms(t, 3, 4) + ev_ms(t, 10, 11);
         S.t_p2p_ms = ev_ms(t, 5, 6);
         S.t_total_ms = ev_ms(t, 0, 11);
@@ -157,7 +175,7 @@ static bool same_params(const fmm_params &a, const fmm_params &b)
 {
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
            a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
-           a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma;
+           a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma && a.schedule == b.schedule;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
@@ -311,40 +329,39 @@ int fmm_short_range_forces_graph(fmm_tree *t, const fmm_params *P, double *acc, 
     return 0;
 }
 
-int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t n, const double *pos,
-                 const double *mass, double *acc, const int *candidates, int ncand, int reps, void *stream,
-                 int *best_n_crit, double *ms_out)
+// Times each parameter set of cands (reps timed steps after one untimed one that sizes the
+// tree's buffers) and returns the index of the fastest in *best.
+static int autotune_sets(const fmm_params *cands, int ncand, int nbox, const int64_t *offsets, int64_t n,
+                         const double *pos, const double *mass, double *acc, int reps, void *stream, int *best,
+                         double *ms_out)
 {
-    clear_error();
-    if (int rc = check_params(P)) return rc;
-    if (n <= 0 || !pos || !mass || !acc || !candidates || ncand <= 0 || !best_n_crit || nbox < 1 ||
-        (nbox > 1 && !offsets))
+    if (!cands || ncand <= 0) return set_error(FMM_ERR_ARG, "no parameter sets");
+    for (int c = 0; c < ncand; ++c)
+        if (int rc = check_params(&cands[c])) return rc;
+    if (n <= 0 || !pos || !mass || !acc || !best || nbox < 1 || (nbox > 1 && !offsets))
         return set_error(FMM_ERR_ARG, "bad arguments");
     if (nbox > 1 && offsets[nbox] != n) return set_error(FMM_ERR_ARG, "offsets[nbox] != n");
     std::vector<fmm_params> per_box((size_t)nbox);
-    for (int c = 0; c < ncand; ++c)
-        if (candidates[c] < 1) return set_error(FMM_ERR_ARG, "n_crit candidate %d < 1", candidates[c]);
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(FMM_ERR_HIP, "hipEventCreate");
     fmm_tree *t = nullptr;
     int rc = 0;
-    double best = 1e300;
-    *best_n_crit = candidates[0];
+    double fastest = 1e300;
+    *best = 0;
+    const int nrep = reps > 0 ? reps : 1;
     for (int c = 0; c < ncand && !rc; ++c) {
-        fmm_params Q = *P;
-        Q.n_crit = candidates[c];
+        const fmm_params &Q = cands[c];
         for (auto &b : per_box) b = Q;
         auto build = [&]() {
             return nbox > 1 ? fmm_build_tree_batched(per_box.data(), nbox, offsets, pos, mass, stream, &t)
                             : fmm_build_tree(&Q, n, pos, mass, stream, &t);
         };
-        // one untimed step sizes the tree's buffers for this leaf size
         rc = build();
         if (!rc) rc = run_forces(t, &Q, acc, st);
         float total = 0.0f;
-        for (int r = 0; r < (reps > 0 ? reps : 1) && !rc; ++r) {
+        for (int r = 0; r < nrep && !rc; ++r) {
             (void)hipEventRecord(e0, st);  // timing events; failures surface in the step's own checks
             rc = build();
             if (!rc) rc = run_forces(t, &Q, acc, st);
@@ -354,17 +371,43 @@ int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t 
             (void)hipEventElapsedTime(&ms, e0, e1);
             total += ms;
         }
-        const double ms = total / (reps > 0 ? reps : 1);
+        const double ms = total / nrep;
         if (ms_out) ms_out[c] = ms;
-        if (!rc && ms < best) {
-            best = ms;
-            *best_n_crit = Q.n_crit;
+        if (!rc && ms < fastest) {
+            fastest = ms;
+            *best = c;
         }
     }
     if (t) fmm_free_tree(t);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return rc;
+}
+
+int fmm_autotune(const fmm_params *P, int nbox, const int64_t *offsets, int64_t n, const double *pos,
+                 const double *mass, double *acc, const int *candidates, int ncand, int reps, void *stream,
+                 int *best_n_crit, double *ms_out)
+{
+    clear_error();
+    if (int rc = check_params(P)) return rc;
+    if (!candidates || ncand <= 0 || !best_n_crit) return set_error(FMM_ERR_ARG, "bad arguments");
+    std::vector<fmm_params> cands((size_t)ncand, *P);
+    for (int c = 0; c < ncand; ++c) {
+        if (candidates[c] < 1) return set_error(FMM_ERR_ARG, "n_crit candidate %d < 1", candidates[c]);
+        cands[c].n_crit = candidates[c];
+    }
+    int bi = 0;
+    int rc = autotune_sets(cands.data(), ncand, nbox, offsets, n, pos, mass, acc, reps, stream, &bi, ms_out);
+    *best_n_crit = candidates[bi];
+    return rc;
+}
+
+int fmm_autotune_params(const fmm_params *cands, int ncand, int nbox, const int64_t *offsets, int64_t n,
+                        const double *pos, const double *mass, double *acc, int reps, void *stream, int *best,
+                        double *ms_out)
+{
+    clear_error();
+    return autotune_sets(cands, ncand, nbox, offsets, n, pos, mass, acc, reps, stream, best, ms_out);
 }
 
 int fmm_get_stats(const fmm_tree *tc, fmm_stats *out)

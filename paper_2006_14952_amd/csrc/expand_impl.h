@@ -724,18 +724,27 @@ __device__ __forceinline__ void m2l_hi_outputs(const T *Ms, const T *D, T *buf, 
     if constexpr (N1 < NC) m2l_hi_outputs<P, T, N1, HC, STR>(Ms, D, buf, sid, one, L, stride);
 }
 
+// Shared memory of one 64-pair block of the pair kernel.
+template <int P, class T> struct M2LPairShared {
+    static constexpr int NMID = m2l_mid_rows<P>(), HC = m2l_hi_chunk<P>();
+    static constexpr int STR = (NMID > HC ? NMID : HC) | 1;  // odd row stride: no bank conflicts
+    T buf[64 * STR];
+    int sid[64];
+};
+
+// Pairs blk*64 .. blk*64+63 of the flattened array (one 64-lane wave).
 template <int P, class T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : P >= 7 ? 2 : 3))) void k_m2l_pairs(
-    const Cell *__restrict__ cells, const int2 *__restrict__ pairs, int64_t npair, const T *__restrict__ M,
-    T *__restrict__ L, double box, Split sp, int stride)
+__device__ __forceinline__ void m2l_pairs_block(const Cell *__restrict__ cells, const int2 *__restrict__ pairs,
+                                                int64_t npair, const T *__restrict__ M, T *__restrict__ L, double box,
+                                                Split sp, int stride, int64_t blk, M2LPairShared<P, T> &sh)
 {
     constexpr int NC = ncoef(P), NHB = m2l_hi_begin<P>(), NMID = m2l_mid_rows<P>(), HC = m2l_hi_chunk<P>();
-    constexpr int STR = (NMID > HC ? NMID : HC) | 1;  // odd row stride: no bank conflicts
+    constexpr int STR = M2LPairShared<P, T>::STR;
     constexpr int MB = 16;
-    __shared__ T buf[64 * STR];
-    __shared__ int sid[64];
+    T *buf = sh.buf;
+    int *sid = sh.sid;
     const int lane = threadIdx.x;
-    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t idx = blk * 64 + lane;
     T D[NC], rp[P + 1], M0[MB];
 #pragma unroll
     for (int k = 0; k < NC; ++k) D[k] = 0;
@@ -794,6 +803,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     for (int k = 0; k < kLo; ++k) row[k] = lo[k];
     __syncthreads();
     m2l_reduce_rows<T, STR, kLo>(buf, sid, one, 0, L, stride);
+}
+
+template <int P, class T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : P >= 7 ? 2 : 3))) void k_m2l_pairs(
+    const Cell *__restrict__ cells, const int2 *__restrict__ pairs, int64_t npair, const T *__restrict__ M,
+    T *__restrict__ L, double box, Split sp, int stride)
+{
+    __shared__ M2LPairShared<P, T> sh;
+    m2l_pairs_block<P, T>(cells, pairs, npair, M, L, box, sp, stride, blockIdx.x, sh);
 }
 
 int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st);

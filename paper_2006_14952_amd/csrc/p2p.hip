@@ -21,11 +21,12 @@
 // pair inside the cutoff and are not staged (the lists themselves are unchanged).
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 #include <vector>
 
-#include "state.h"
+#include "expand_impl.h"
 
 namespace hfmm {
 
@@ -95,18 +96,28 @@ constexpr int kStage = 256;
 // POLY (FP32 form, polynomial split): f_(1) = -1/r^3 + 5/(2 r_c^3) - 3 r^2/(2 r_c^5) evaluated
 // as -(1-x)^2 (1 + 2x + 3x^2 + 3x^3/2) / r^3, x = r / r_c: the three terms cancel near r_cut
 // in FP32, the factored form does not.
+// Shared memory of one sink leaf's P2P (one 64-lane wave).
+template <bool F64> struct P2PShared {
+    using R = typename std::conditional<F64, double, float>::type;
+    using V4 = typename std::conditional<F64, double4, float4>::type;
+    V4 src[kStage];
+    int ebeg[64], epref[64];
+    int smark[kStage];
+    R eoff[64][3];
+};
+
+// P2P of sink leaf `leaves[li]`.
 template <bool F64, bool POLY, int NPC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
+__device__ __forceinline__ void p2p_leaf(const P2PArgs &a, const P2PConst &k, int li, P2PShared<F64> &sh)
 {
     using R = typename std::conditional<F64, double, float>::type;
     using V4 = typename std::conditional<F64, double4, float4>::type;
-    __shared__ V4 src[kStage];
-    __shared__ int ebeg[64], epref[64];
-    __shared__ int smark[kStage];
-    __shared__ R eoff[64][3];
+    V4 *src = sh.src;
+    int *ebeg = sh.ebeg, *epref = sh.epref, *smark = sh.smark;
+    R(*eoff)[3] = sh.eoff;
     const int lane = threadIdx.x;
     const uint64_t lt = (1ull << lane) - 1ull;
-    const int A = a.leaves[blockIdx.x];
+    const int A = a.leaves[li];
     const Cell ca = a.cells[A];
     const double hA = ldexp(a.box, -cell_level(ca));
     const double cax = (cell_ix(ca) + 0.5) * hA, cay = (ca.iy + 0.5) * hA, caz = (ca.iz + 0.5) * hA;
@@ -350,6 +361,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5)
     }
 }
 
+template <bool F64, bool POLY, int NPC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
+{
+    __shared__ P2PShared<F64> sh;
+    p2p_leaf<F64, POLY, NPC>(a, k, blockIdx.x, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent fused P2P + M2L (FP32, plain MAC): the grid holds as many 64-lane blocks as
+// fit on the device at once; each block pulls items from one device counter until the
+// queue is empty: first the sink leaves (P2P), then the 64-pair blocks of the flattened
+// M2L array.  One launch covers both stages of every box of a forest, so no stage waits
+// for the tail of another and no launch boundary falls between them.
+template <bool POLY, int P>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 2 : (P >= 5 ? 3 : 4)))) void k_p2p_m2l_persist(
+    P2PArgs a, P2PConst k, const int2 *__restrict__ pairs, int64_t npair, const float *__restrict__ M,
+    float *__restrict__ L, Split sp, int stride, int *__restrict__ queue)
+{
+    __shared__ union {
+        P2PShared<false> p;
+        M2LPairShared<P, float> m;
+    } sh;
+    const int nleaf = a.nleaf;
+    const int total = nleaf + (int)((npair + 63) / 64);
+    for (;;) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(queue, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (item >= total) break;
+        if (item < nleaf) p2p_leaf<false, POLY, 11>(a, k, item, sh.p);
+        else m2l_pairs_block<P, float>(a.cells, pairs, npair, M, L, a.box, sp, stride, item - nleaf, sh.m);
+        __syncthreads();  // the block's shared memory is reused by the next item
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host: fit of S(t) on [-1, 1] at Chebyshev points (interpolation, solved in FP64)
 
@@ -468,12 +514,8 @@ int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return hip_check(hipGetLastError(), "leaf boxes");
 }
 
-int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
+static void p2p_args(fmm_tree *t, P2PArgs &a)
 {
-    if (t->nleaf == 0) return 0;
-    P2PConst k;
-    if (int rc = p2p_setup(P, k)) return rc;
-    P2PArgs a;
     a.cells = ptr<Cell>(t->cells);
     a.leaves = ptr<int>(t->leaves);
     a.nleaf = t->nleaf;
@@ -491,10 +533,97 @@ int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
     a.n = (int)t->n;
     a.pairs = ptr<unsigned long long>(t->counters) + 1;
     a.evaluated = ptr<unsigned long long>(t->counters) + 24;
-    a.bbox = nullptr;
+    a.bbox = ptr<float4>(t->bbox);
+}
+
+// Whether the fused persistent kernel serves these parameters: the FP32 plain form with
+// the pair M2L kernel (orders 3..8) and the degree-10 force law or the polynomial split.
+bool fused_applies(const fmm_params *P)
+{
+    if (P->precision != 1 || P->learned || P->p < 3 || P->m2l_mfma == 2) return false;
+    if (P->split == 1) return true;
+    P2PConst k;
+    return p2p_setup(P, k) == 0 && k.ncoef == 11;
+}
+
+template <bool POLY, int P> static int launch_persist(fmm_tree *t, const P2PArgs &a, const P2PConst &k, Split sp,
+                                                      int64_t np, int *queue, hipStream_t st)
+{
+    static int per_cu = 0, ncu = 0;
+    if (per_cu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_p2p_m2l_persist<POLY, P>, 64, 0) != hipSuccess ||
+            per_cu <= 0)
+            return set_error(FMM_ERR_HIP, "occupancy of the fused kernel");
+    }
+    const int64_t items = (int64_t)t->nleaf + (np + 63) / 64;
+    const int64_t g = std::min<int64_t>(items, (int64_t)per_cu * ncu);
+    if (g <= 0) return 0;
+    k_p2p_m2l_persist<POLY, P><<<(unsigned)g, 64, 0, st>>>(a, k, ptr<int2>(t->m2l_pairs), np, ptr<float>(t->Mc),
+                                                          ptr<float>(t->Lc), sp, ncoef(P), queue);
+    return hip_check(hipGetLastError(), "fused p2p + m2l");
+}
+
+// P2P and M2L of a built tree (or forest) in one persistent launch on `st`.  The
+// preparation (L zeroed, the M2L list flattened, the queue counter zeroed) is its own call
+// so that stage timing can bracket the launch alone.
+int p2p_m2l_fused_prepare(fmm_tree *t, const fmm_params *P, hipStream_t st)
+{
+    if (t->nleaf == 0) return 0;
+    if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
+    const int64_t np = t->n_m2l;
+    if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(P->p) * sizeof(float), st)) return rc;
+    if (np > 0)
+        if (int rc = flatten_pairs(t, 0, np, st)) return rc;
+    if (int rc = grow(t->m2l_ctr, 256)) return rc;
+    return zero_async(ptr<int>(t->m2l_ctr) + 32, 4, st);
+}
+
+int p2p_m2l_fused_launch(fmm_tree *t, const fmm_params *P, hipStream_t st)
+{
+    if (t->nleaf == 0) return 0;
+    P2PConst k;
+    if (int rc = p2p_setup(P, k)) return rc;
+    const int64_t np = t->n_m2l;
+    int *queue = ptr<int>(t->m2l_ctr) + 32;
+    P2PArgs a;
+    p2p_args(t, a);
+    const Split sp{P->split ? P->r_cut : P->r_s, P->split};
+    if (P->split == 1) {
+        switch (P->p) {
+        case 3: return launch_persist<true, 3>(t, a, k, sp, np, queue, st);
+        case 4: return launch_persist<true, 4>(t, a, k, sp, np, queue, st);
+        case 5: return launch_persist<true, 5>(t, a, k, sp, np, queue, st);
+        case 6: return launch_persist<true, 6>(t, a, k, sp, np, queue, st);
+        case 7: return launch_persist<true, 7>(t, a, k, sp, np, queue, st);
+        case 8: return launch_persist<true, 8>(t, a, k, sp, np, queue, st);
+        }
+    } else {
+        switch (P->p) {
+        case 3: return launch_persist<false, 3>(t, a, k, sp, np, queue, st);
+        case 4: return launch_persist<false, 4>(t, a, k, sp, np, queue, st);
+        case 5: return launch_persist<false, 5>(t, a, k, sp, np, queue, st);
+        case 6: return launch_persist<false, 6>(t, a, k, sp, np, queue, st);
+        case 7: return launch_persist<false, 7>(t, a, k, sp, np, queue, st);
+        case 8: return launch_persist<false, 8>(t, a, k, sp, np, queue, st);
+        }
+    }
+    return set_error(FMM_ERR_ARG, "fused kernel compiled for orders 3..8");
+}
+
+int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
+{
+    if (t->nleaf == 0) return 0;
+    P2PConst k;
+    if (int rc = p2p_setup(P, k)) return rc;
+    P2PArgs a;
+    p2p_args(t, a);
     if (P->precision) {
         if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
-        a.bbox = ptr<float4>(t->bbox);
+    } else {
+        a.bbox = nullptr;
     }
     if (P->precision && P->split == 1) k_p2p<false, true, 11><<<t->nleaf, 64, 0, st>>>(a, k);
     else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<t->nleaf, 64, 0, st>>>(a, k);

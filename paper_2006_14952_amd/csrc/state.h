@@ -107,6 +107,9 @@ int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st);  // before p2p (FP32 form): leaf boxes
+bool fused_applies(const fmm_params *P);                            // schedule 2 serves these parameters
+int p2p_m2l_fused_prepare(fmm_tree *t, const fmm_params *P, hipStream_t st);  // schedule 2: L, pairs, queue
+int p2p_m2l_fused_launch(fmm_tree *t, const fmm_params *P, hipStream_t st);   // P2P + M2L, one launch
 int l2p_combine(fmm_tree *t, const fmm_params *P, double *acc, int accumulate, hipStream_t st);
 // FP32 M2L of order p in 4..8 on the matrix cores for pairs on one level; the other
 // pairs are left in t->m2l_pairs, their number in *n_other (L zeroed by the caller)

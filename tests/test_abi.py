@@ -16,7 +16,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_param_struct_layout_matches_header():
-    assert C.sizeof(hf.Params) == 5 * 8 + 8 * 4
+    assert C.sizeof(hf.Params) == 5 * 8 + 10 * 4
     assert C.sizeof(hf.Stats) == 16 * 8 + 16 * 8
 
 
@@ -26,7 +26,11 @@ def test_version_and_error_string():
 
 
 @pytest.mark.parametrize("bad", [dict(theta=0.0), dict(p=9), dict(p=-1), dict(n_crit=0), dict(r_cut=0.6),
-                                 dict(r_s=-1.0), dict(precision=2), dict(mac_mode=8), dict(box=0.0)])
+                                 dict(r_s=-1.0), dict(precision=2), dict(mac_mode=8), dict(box=0.0),
+                                 dict(schedule=3), dict(schedule=-1), dict(schedule=2),
+                                 dict(schedule=2, precision=1, p=2), dict(schedule=2, precision=1, m2l_mfma=2),
+                                 dict(schedule=2, precision=1, learned=1),
+                                 dict(schedule=2, precision=1, r_cut=0.24)])
 def test_bad_params_rejected_without_gpu(bad):
     kw = dict(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
     kw.update(bad)
@@ -64,3 +68,49 @@ def test_autotune_and_hybrid_tree_reject_bad_arguments_without_gpu():
     assert L.fmm_short_range_forces_graph(None, C.byref(prm), fake, fake) == hf.FMM_ERR_ARG
     prm.theta = 0.0
     assert L.fmm_short_range_forces_graph(fake, C.byref(prm), fake, fake) == hf.FMM_ERR_ARG
+
+
+def test_reserved_field_must_be_zero():
+    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
+    prm.reserved = 1
+    h = C.c_void_p()
+    assert hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h)) == hf.FMM_ERR_ARG
+
+
+def test_persistent_schedule_accepted_where_it_applies():
+    """Schedule 2 passes validation for the FP32 plain forms it serves: the parameter sets
+    are checked before the particle arguments, so n = 0 fails on the arguments alone."""
+    L = hf.lib()
+    best = C.c_int()
+    for kw in (dict(p=3), dict(p=5), dict(p=8), dict(p=6, split=1, r_cut=0.2), dict(p=4, m2l_mfma=1)):
+        prm = hf.params(box=1.0, r_s=0.04, theta=0.5, n_crit=32, precision=1, schedule=2, **kw)
+        arr = (hf.Params * 1)(prm)
+        assert L.fmm_autotune_params(arr, 1, 1, None, 0, None, None, None, 1, None, C.byref(best), None) == \
+            hf.FMM_ERR_ARG
+        assert L.fmm_last_error() == b"bad arguments", kw
+
+
+def test_autotune_params_rejects_bad_arguments_without_gpu():
+    L = hf.lib()
+    good = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
+    bad = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32, schedule=2)  # FP64: no persistent form
+    arr = (hf.Params * 2)(good, bad)
+    best = C.c_int()
+    fake = C.c_void_p(16)  # never dereferenced: the arguments are refused first
+    assert L.fmm_autotune_params(arr, 2, 1, None, 10, fake, fake, fake, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    assert b"schedule" in L.fmm_last_error()
+    assert L.fmm_autotune_params(arr, 0, 1, None, 10, fake, fake, fake, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+    assert L.fmm_autotune_params(arr, 1, 1, None, 0, fake, fake, fake, 1, None, C.byref(best), None) == \
+        hf.FMM_ERR_ARG
+
+
+def test_kernel_candidates_cover_the_served_combinations():
+    fp32 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=1)
+    c = hf.kernel_candidates(fp32, n_crits=(32, 48))
+    combos = {(q.n_crit, q.schedule, q.m2l_mfma) for q in c}
+    assert combos == {(nc, s, m) for nc in (32, 48) for s, m in ((1, 1), (1, 2), (2, 1))}
+    assert all(q.p == 5 and q.theta == 0.4 and q.precision == 1 for q in c)
+    fp64 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=0)
+    assert {(q.schedule, q.m2l_mfma) for q in hf.kernel_candidates(fp64)} == {(1, 0)}

@@ -70,6 +70,15 @@ def test_p2p_roofline_counts_listed_pairs(bench):
     assert r["traffic"] is None  # no counters recorded for this workload
 
 
+def test_fused_roofline_adds_the_m2l_work(bench):
+    wl = {"learned": False, "precision": 1, "theta": 0.4, "n_crit": 48}
+    st = {"p2p_pairs": 10 ** 9, "p2p_evaluated": 6 * 10 ** 8, "n_m2l": 10 ** 6}
+    r = bench.p2p_roofline(st, 2.0, wl, "none", {"p": 5}, 100, 0, fused=True)
+    assert r["m2l_flop_in_launch"] == 2 * 462 * 10 ** 6  # C(11, 6) = 462
+    assert r["flop_per_launch"] == 38 * 10 ** 9 + 2 * 462 * 10 ** 6
+    assert "persistent" in r["kernel"]
+
+
 def test_cube_sample_takes_whole_seeded_cubes(bench):
     import numpy as np
     rng = np.random.default_rng(0)

@@ -216,9 +216,9 @@ def test_hybrid_polynomial_split_approaches_ewald():
 
 def test_batched_config_full_forest_sampled():
     """The 64-box batched workload at full size, in the launch configuration the benchmark
-    times (its opening angle, FP32, the leaf limit the library's autotuner picks): the
-    smallest, median and largest box against the FP64 oracle on sampled particles and
-    against their brute-force sums."""
+    times (its opening angle, FP32, the leaf limit, schedule and M2L kernel the library's
+    autotuner picks): the smallest, median and largest box against the FP64 oracle on
+    sampled particles and against their brute-force sums."""
     import bench
     wl = bench.WORKLOADS["batched"]
     pr = inputs.split_params("batched")
@@ -227,8 +227,9 @@ def test_batched_config_full_forest_sampled():
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     pos, m = dev(np.concatenate([b[0] for b in boxes])), dev(np.concatenate([b[1] for b in boxes]))
     prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=32, precision=1)
-    best, ms = hf.autotune(pos, m, prm, offsets=off)
-    prm.n_crit = best
+    prm, table = bench.tune_kernels(hf, pos, m, prm, off)
+    best = prm.n_crit
+    print("autotuned:", table)
     t = hf.Tree().build_batched(pos, m, [prm] * len(boxes), off)
     got = t.short_range(prm).cpu().numpy()
     assert t.stats()["n"] == off[-1]
