@@ -52,7 +52,8 @@ WORKLOADS = {
                     cpu_cubes_1t=0.01),
 }
 M2L_KERNELS = {0: "library's choice (vector ALUs)", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}
-SCHEDULES = {0: "library's choice (two streams)", 1: "two streams", 2: "one persistent P2P + M2L kernel"}
+SCHEDULES = {0: "library's choice", 1: "two streams, P2P after the traversal", 2: "one persistent P2P + M2L kernel",
+             3: "two streams, P2P per leaf level during the traversal"}
 CUBE_LEVEL = 6
 CONFIG_SAMPLE_SEED = 777
 _T0 = time.perf_counter()
@@ -107,8 +108,9 @@ def main():
     ap.add_argument("--autotune", type=int, default=None, choices=(0, 1),
                     help="1: choose n_crit, schedule and M2L kernel with the library's autotuner before timing "
                          "(default: batched only)")
-    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2),
-                    help="P2P and M2L: 0 library's choice, 1 two kernels on two streams, 2 one persistent kernel")
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="P2P and M2L: 0 library's choice, 1 two kernels on two streams, 2 one persistent kernel, "
+                         "3 as 1 with P2P per leaf level during the traversal")
     ap.add_argument("--split", type=int, default=0, choices=(0, 1),
                     help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),

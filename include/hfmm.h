@@ -77,12 +77,15 @@ extern "C" {
  *             the matrix cores (FP32 MFMA; pairs sharing an offset share the transfer
  *             matrix), the other pairs on the vector ALUs; 0 the library's choice.
  *   schedule  how P2P and M2L share the GPU (the task pool of Sec. 4): 1 two kernels on
- *             two streams, P2P beside M2L; 2 one persistent kernel whose workgroups pull
- *             sink leaves (P2P) and then blocks of 64 M2L pairs from one device queue
- *             until both stages are done; 0 the library's choice (1).  Schedule 2 requires
- *             precision 1, learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, the
- *             degree-10 force law (r_cut / r_s up to about 5.6); FMM_ERR_ARG otherwise.
- *             The results do not depend on the schedule beyond FP32 summation order.
+ *             two streams, P2P after the traversal, beside M2L; 2 one persistent kernel
+ *             whose workgroups pull sink leaves (P2P) and then blocks of 64 M2L pairs from
+ *             one device queue until both stages are done; 3 as 1, but the P2P of each
+ *             leaf level is launched as soon as the traversal has listed that level, so
+ *             it runs beside the traversal of the finer levels; 0 the library's choice (3
+ *             for trees of 2^20 leaves or more, else 1).  Schedule 2 requires precision 1,
+ *             learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, the degree-10 force
+ *             law (r_cut / r_s up to about 5.6); FMM_ERR_ARG otherwise.  The results do
+ *             not depend on the schedule beyond FP32 summation order.
  *   reserved  must be 0. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;

@@ -106,7 +106,8 @@ def params(box=1.0, r_s=0.0390625, r_cut=None, theta=0.5, G=1.0, p=4, n_crit=32,
            learned=0, split=0, pm_assign=0, m2l_mfma=0, schedule=0) -> Params:
     """pm_assign: PM mass assignment, 0/2 CIC, 3 TSC, 4 PCS.  m2l_mfma: FP32 M2L kernel,
     0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs.  schedule:
-    0 library's choice, 1 P2P and M2L on two streams, 2 one persistent P2P + M2L kernel."""
+    0 library's choice, 1 P2P and M2L on two streams after the traversal, 2 one persistent
+    P2P + M2L kernel, 3 as 1 with P2P launched per leaf level during the traversal."""
     if r_cut is None:
         r_cut = 4.5 * r_s
     return Params(float(box), float(r_s), float(r_cut), float(theta), float(G), int(p), int(n_crit), int(mac_mode),
@@ -288,10 +289,10 @@ def autotune_params(pos, mass, cands, reps=2, offsets=None, stream=None):
 
 def kernel_candidates(prm: Params, n_crits=(32, 48)):
     """The tile and kernel settings the autotuner may vary for prm: each leaf limit in
-    n_crits, crossed with the two schedules and (FP32 orders 4..8, plain MAC) the two M2L
+    n_crits, crossed with the schedules and (FP32 orders 4..8, plain MAC) the two M2L
     kernels; combinations the library does not serve are left out."""
     fp32_plain = prm.precision == 1 and not prm.learned
-    scheds = (1, 2) if fp32_plain and 3 <= prm.p <= 8 else (1,)
+    scheds = (1, 2, 3) if fp32_plain and 3 <= prm.p <= 8 else (1, 3)
     mfmas = (1, 2) if fp32_plain and 4 <= prm.p <= 8 else (prm.m2l_mfma,)
     out = []
     for nc in n_crits:

@@ -43,7 +43,7 @@ static int check_params(const fmm_params *P)
     if (P->pm_assign != 0 && (P->pm_assign < 2 || P->pm_assign > 4))
         return set_error(FMM_ERR_ARG, "pm_assign must be 0, 2 (CIC), 3 (TSC) or 4 (PCS)");
     if (P->m2l_mfma < 0 || P->m2l_mfma > 2) return set_error(FMM_ERR_ARG, "m2l_mfma must be 0, 1 or 2");
-    if (P->schedule < 0 || P->schedule > 2) return set_error(FMM_ERR_ARG, "schedule must be 0, 1 or 2");
+    if (P->schedule < 0 || P->schedule > 3) return set_error(FMM_ERR_ARG, "schedule must be 0, 1, 2 or 3");
     if (P->reserved != 0) return set_error(FMM_ERR_ARG, "reserved must be 0");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
@@ -74,6 +74,33 @@ static void mark(fmm_tree *t, int k, hipStream_t st)
     if (t->timing) (void)hipEventRecord(t->ev[k], st);  // a failure shows in the stage's error check
 }
 
+// P2P of the leaves of each level as soon as the traversal has listed them: the launch for
+// level l waits (on the second stream) for the traversal kernel of level l only, so the
+// P2P work of coarse leaves runs beside the traversal of the finer levels.
+struct LevelP2P {
+    fmm_tree *t;
+    const fmm_params *P;
+    hipStream_t ax;
+};
+
+static int p2p_level_hook(void *ctx, int l, hipStream_t st)
+{
+    const LevelP2P &c = *static_cast<const LevelP2P *>(ctx);
+    fmm_tree *t = c.t;
+    if (l + 1 >= (int)t->leaf_lvl.size()) return 0;
+    const int first = t->leaf_lvl[l], count = t->leaf_lvl[l + 1] - first;
+    if (count <= 0) return 0;
+    int rc;
+    if ((rc = hip_check(hipEventRecord(t->lev[l], st), "event")) ||
+        (rc = hip_check(hipStreamWaitEvent(c.ax, t->lev[l], 0), "event wait")))
+        return rc;
+    if (t->timing) (void)hipEventRecord(t->p2p_t0[l], c.ax);  // timing only
+    // the traversal's overflow flag (counter byte 96): void lists are not read
+    if ((rc = p2p_range(t, c.P, first, count, ptr<int>(t->counters) + 24, c.ax))) return rc;
+    if (t->timing) (void)hipEventRecord(t->p2p_t1[l], c.ax);
+    return 0;
+}
+
 // The stages of one short-range evaluation on a built tree (or forest of boxes).
 // accumulate: add the short-range accelerations to acc instead of overwriting it.
 static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t st, int accumulate = 0)
@@ -96,33 +123,51 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
                 return set_error(FMM_ERR_HIP, "hipEventCreateWithFlags");
     }
+    if (!t->lev_ready) {
+        for (auto &e : t->lev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return set_error(FMM_ERR_HIP, "hipEventCreateWithFlags");
+        for (int l = 0; l <= kMaxLevel; ++l)
+            if (hipEventCreate(&t->p2p_t0[l]) != hipSuccess || hipEventCreate(&t->p2p_t1[l]) != hipSuccess)
+                return set_error(FMM_ERR_HIP, "hipEventCreate");
+        t->lev_ready = true;
+    }
     hipStream_t ax = t->aux;
-    // Dependencies: upward -> M2L; traversal -> {M2L, P2P}; M2L -> L2L; {L2L, P2P} -> L2P.
+    // Dependencies: upward -> M2L; traversal of level l -> P2P of level l's leaves;
+    // traversal -> M2L; M2L -> L2L; {L2L, P2P} -> L2P.
     // The plain traversal does not read multipoles, so the upward pass runs beside it on
-    // the second stream; P2P runs there beside M2L and L2L.
-    // The FP32 P2P's leaf boxes depend on the tree only: they are computed on the second
-    // stream ahead of P2P.
+    // the second stream; P2P runs there, level by level beside the traversal, then beside
+    // M2L and L2L.  The FP32 P2P's leaf boxes depend on the tree only: they are computed
+    // on the second stream ahead of P2P.
     if ((rc = hip_check(hipEventRecord(t->dep[0], st), "event")) || (rc = hip_check(hipStreamWaitEvent(ax, t->dep[0], 0), "event wait")))
         return rc;
     mark(t, 0, st);
+    const bool fused = P->schedule == 2;
+    // P2P level by level beside the traversal: measured faster from about a million leaves
+    // (16.7M box 77.9 -> 75.3 ms, 134M box 3% faster), slower below (2M box 9.2 -> 11.4 ms,
+    // 64-box forest 12.4 -> 16.6 ms: most P2P work sits in the finest levels, listed last,
+    // and each level's launch ends in its own tail)
+    const bool per_level = P->schedule == 3 || (P->schedule == 0 && t->nleaf >= (1 << 20));
+    LevelP2P lp{t, P, ax};
+    const TravHook hook{p2p_level_hook, &lp, ax};
+    const TravHook *hk = per_level ? &hook : nullptr;
     if (P->learned) {  // the selector's features read the multipoles
         mark(t, 9, st);
         if ((rc = upward(t, &P8, st))) return rc;
         mark(t, 1, st);
         if ((rc = hip_check(hipEventRecord(t->dep[1], st), "event"))) return rc;
         if ((rc = p2p_bbox(t, P, ax))) return rc;
-        rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st);
+        rc = traverse_mode(t, P, 2, hm.theta_max, t->Mc.p, ncoef(8), P->precision, dm, st, hk);
     } else {
         mark(t, 9, ax);
         if ((rc = upward(t, &P8, ax))) return rc;
         mark(t, 1, ax);
         if ((rc = hip_check(hipEventRecord(t->dep[1], ax), "event"))) return rc;
         if ((rc = p2p_bbox(t, P, ax))) return rc;
-        rc = traverse(t, P, st);
+        rc = traverse(t, P, st, hk);
     }
     if (rc) return rc;
     mark(t, 2, st);
-    const bool fused = P->schedule == 2;
     if (fused) {  // P2P and M2L in one persistent launch on st, after the second stream's work
         if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[3], 0), "event wait")))
             return rc;
@@ -132,13 +177,15 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
         mark(t, 6, st);
         mark(t, 3, st);
     }
-    if (!fused && ((rc = hip_check(hipEventRecord(t->dep[2], st), "event")) ||
-                   (rc = hip_check(hipStreamWaitEvent(ax, t->dep[2], 0), "event wait"))))
-        return rc;
-    if (!fused) mark(t, 5, ax);
-    if (!fused) {
+    if (!fused && !per_level) {  // P2P after the whole traversal
+        if ((rc = hip_check(hipEventRecord(t->dep[2], st), "event")) ||
+            (rc = hip_check(hipStreamWaitEvent(ax, t->dep[2], 0), "event wait")))
+            return rc;
+        mark(t, 5, ax);
         if ((rc = p2p(t, P, ax))) return rc;
         mark(t, 6, ax);
+    }
+    if (!fused) {  // (per level: P2P was launched during the traversal)
         if ((rc = hip_check(hipEventRecord(t->dep[3], ax), "event")) || (rc = hip_check(hipStreamWaitEvent(st, t->dep[1], 0), "event wait")))
             return rc;
         if ((rc = P->learned ? m2l_learned(t, P, st) : m2l(t, P, st))) return rc;
@@ -163,7 +210,17 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
         S.t_traverse_ms = P->learned ? ev_ms(t, 1, 2) : ev_ms(t, 0, 2);
         S.t_m2l_ms = fused ? ev_ms(t, 5, 6) : ev_ms(t, 2, 3);  // schedule 2: both stages are one launch
         S.t_downward_ms = ev_ms(t, 3, 4) + ev_ms(t, 10, 11);
-        S.t_p2p_ms = ev_ms(t, 5, 6);
+        if (!per_level) {
+            S.t_p2p_ms = ev_ms(t, 5, 6);
+        } else {  // the sum of the per-level P2P launches
+            S.t_p2p_ms = 0.0;
+            for (int l = 0; l + 1 < (int)t->leaf_lvl.size() && l <= kMaxLevel; ++l) {
+                if (t->leaf_lvl[l + 1] == t->leaf_lvl[l]) continue;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, t->p2p_t0[l], t->p2p_t1[l]);  // timing only
+                S.t_p2p_ms += ms;
+            }
+        }
         S.t_total_ms = ev_ms(t, 0, 11);
     }
     return hip_check(hipGetLastError(), "short range forces");
@@ -588,6 +645,11 @@ void fmm_free_tree(fmm_tree *t)
         for (auto &e : t->ev) (void)hipEventDestroy(e);
     if (t->bev_ready)
         for (auto &e : t->bev) (void)hipEventDestroy(e);
+    if (t->lev_ready) {
+        for (auto &e : t->lev) (void)hipEventDestroy(e);
+        for (auto &e : t->p2p_t0) (void)hipEventDestroy(e);
+        for (auto &e : t->p2p_t1) (void)hipEventDestroy(e);
+    }
     if (t->aux) {
         (void)hipStreamSynchronize(t->aux);
         for (auto &e : t->dep) (void)hipEventDestroy(e);

@@ -58,6 +58,8 @@ struct P2PArgs {
     unsigned long long *pairs;  // listed particle pairs (sum of n_A n_B over P2P leaf pairs)
     unsigned long long *evaluated;  // particle pairs actually evaluated (FP32 form: after the box test)
     const float4 *bbox;             // per cell: lo, hi of the particles relative to the cell centre
+    int first;                      // k_p2p: block b takes sink leaf leaves[first + b]
+    const int *err;                 // k_p2p: if non-NULL and non-zero, the lists are void: do nothing
 };
 
 // Bounding box of each leaf's particles in the FP32 cell-relative frame.
@@ -365,7 +367,8 @@ template <bool F64, bool POLY, int NPC>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
 {
     __shared__ P2PShared<F64> sh;
-    p2p_leaf<F64, POLY, NPC>(a, k, blockIdx.x, sh);
+    if (a.err && *a.err) return;  // the traversal overflowed: it reruns, and so does P2P
+    p2p_leaf<F64, POLY, NPC>(a, k, a.first + blockIdx.x, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -534,6 +537,8 @@ static void p2p_args(fmm_tree *t, P2PArgs &a)
     a.pairs = ptr<unsigned long long>(t->counters) + 1;
     a.evaluated = ptr<unsigned long long>(t->counters) + 24;
     a.bbox = ptr<float4>(t->bbox);
+    a.first = 0;
+    a.err = nullptr;
 }
 
 // Whether the fused persistent kernel serves these parameters: the FP32 plain form with
@@ -613,23 +618,28 @@ int p2p_m2l_fused_launch(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return set_error(FMM_ERR_ARG, "fused kernel compiled for orders 3..8");
 }
 
-int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st)
+int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int *err, hipStream_t st)
 {
-    if (t->nleaf == 0) return 0;
+    if (count <= 0) return 0;
+    if (first < 0 || count > t->nleaf - first) return set_error(FMM_ERR_STATE, "p2p: leaf range out of bounds");
     P2PConst k;
     if (int rc = p2p_setup(P, k)) return rc;
     P2PArgs a;
     p2p_args(t, a);
+    a.first = first;
+    a.err = err;
     if (P->precision) {
         if (t->bbox.bytes < (size_t)t->ncell * 32) return set_error(FMM_ERR_STATE, "p2p: leaf boxes not computed");
     } else {
         a.bbox = nullptr;
     }
-    if (P->precision && P->split == 1) k_p2p<false, true, 11><<<t->nleaf, 64, 0, st>>>(a, k);
-    else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<t->nleaf, 64, 0, st>>>(a, k);
-    else if (P->precision) k_p2p<false, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);
-    else k_p2p<true, false, 11><<<t->nleaf, 64, 0, st>>>(a, k);
+    if (P->precision && P->split == 1) k_p2p<false, true, 11><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision) k_p2p<false, false, 11><<<count, 64, 0, st>>>(a, k);
+    else k_p2p<true, false, 11><<<count, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");
 }
+
+int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st) { return p2p_range(t, P, 0, t->nleaf, nullptr, st); }
 
 }  // namespace hfmm

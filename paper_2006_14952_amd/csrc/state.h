@@ -24,6 +24,7 @@ struct fmm_tree {
     int nbox = 1;                          // roots: one per box of a batch
     std::vector<int> hboxoff;              // particle offsets of the boxes (host copy)
     std::vector<int> lvl_beg;              // cells of level l: lvl_beg[l] .. lvl_beg[l+1]-1
+    std::vector<int> leaf_lvl;             // leaves of level l: leaves[leaf_lvl[l] .. leaf_lvl[l+1]-1]
 
     // particles, Morton order
     hfmm::DevBuf keys[2], idx[2];
@@ -74,6 +75,9 @@ struct fmm_tree {
     hipEvent_t dep[4]{};
     hipEvent_t bev[hfmm::kMaxLevel + 1]{};  // tree build: one per level launch
     bool bev_ready = false;
+    // traversal: the lists of level l's sinks are complete (lev); P2P launch of level l (timing)
+    hipEvent_t lev[hfmm::kMaxLevel + 1]{}, p2p_t0[hfmm::kMaxLevel + 1]{}, p2p_t1[hfmm::kMaxLevel + 1]{};
+    bool lev_ready = false;
 
     // recorded evaluation (fmm_short_range_forces_graph): the executable graph, what it was
     // recorded with, and the build it belongs to
@@ -97,15 +101,26 @@ struct fmm_tree {
 namespace hfmm {
 int tree_build(fmm_tree *t, const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,
                const int64_t *offsets, hipStream_t st);
-int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st);
+// Called by the traversal after it has launched the kernel of sink level l on st: once that
+// launch ends, the lists of the level's sinks are complete.  `side` is the stream the hook
+// launches on; the traversal synchronises it before a rerun (whose lists replace these).
+struct TravHook {
+    int (*level)(void *ctx, int l, hipStream_t st);
+    void *ctx;
+    hipStream_t side;
+};
+int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st, const TravHook *hook = nullptr);
 struct MacModel;
 int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, const void *M, int mstride,
-                  int mprec, const MacModel *model, hipStream_t st);
+                  int mprec, const MacModel *model, hipStream_t st, const TravHook *hook = nullptr);
 int upward(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int downward_l2l(fmm_tree *t, const fmm_params *P, hipStream_t st);
 int p2p(fmm_tree *t, const fmm_params *P, hipStream_t st);
+// P2P of the sink leaves leaves[first .. first+count-1]; with err non-NULL the launch does
+// nothing while *err is non-zero (lists of a traversal that overflowed)
+int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int *err, hipStream_t st);
 int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st);  // before p2p (FP32 form): leaf boxes
 bool fused_applies(const fmm_params *P);                            // schedule 2 serves these parameters
 int p2p_m2l_fused_prepare(fmm_tree *t, const fmm_params *P, hipStream_t st);  // schedule 2: L, pairs, queue

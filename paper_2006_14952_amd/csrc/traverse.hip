@@ -477,7 +477,7 @@ static int ensure_pools(fmm_tree *t, const int *want)
 // candidates, M/mstride/mprec give the multipoles used by the features, model the
 // selector (learned only).
 int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, const void *M, int mstride,
-                  int mprec, const MacModel *model, hipStream_t st)
+                  int mprec, const MacModel *model, hipStream_t st, const TravHook *hook)
 {
     MacConst mc;
     mac_setup(P, mc);
@@ -566,6 +566,8 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             if (mode == kModePlain) k_traverse<kModePlain><<<g, 64, 0, st>>>(a, mc);
             else if (mode == kModeExport) k_traverse<kModeExport><<<g, 64, 0, st>>>(a, mc);
             else k_traverse<kModeLearned><<<g, 64, 0, st>>>(a, mc);
+            if (hook)
+                if ((rc = hook->level(hook->ctx, l, st))) return rc;
         }
         if ((rc = hip_check(hipGetLastError(), "traversal"))) return rc;
         // Being recorded: the tree and parameters are those of the evaluation just run, whose
@@ -591,6 +593,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
             t->trav_mode = mode;
             return 0;
         }
+        // what the hook launched read the counters the rerun clears: let it end first
+        if (hook && hook->side)
+            if ((rc = hip_check(hipStreamSynchronize(hook->side), "traversal side stream"))) return rc;
         if (err & 1) t->stk_cap *= 4;  // a wave's stack overflowed: larger stacks, rerun
         if (err & 2)
             if ((rc = ensure_pools(t, pools))) return rc;
@@ -598,9 +603,9 @@ int traverse_mode(fmm_tree *t, const fmm_params *P, int mode, double theta_max, 
     return set_error(FMM_ERR_NOMEM, "traversal did not fit after resizing");
 }
 
-int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st)
+int traverse(fmm_tree *t, const fmm_params *P, hipStream_t st, const TravHook *hook)
 {
-    return traverse_mode(t, P, kModePlain, 0.0, nullptr, 0, 0, nullptr, st);
+    return traverse_mode(t, P, kModePlain, 0.0, nullptr, 0, 0, nullptr, st, hook);
 }
 
 }  // namespace hfmm

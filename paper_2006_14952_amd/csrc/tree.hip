@@ -341,6 +341,21 @@ __global__ void k_leaf_flag(const Cell *__restrict__ cells, int ncell, int *__re
     if (c < ncell) flag[c] = cell_nchild(cells[c]) == 0;
 }
 
+// Leaves before the first cell of each level (the exclusive leaf-flag scan at the level
+// boundaries; the scan total past the last): the leaves of level l are
+// leaves[out[l] .. out[l+1]-1], since cells, and so leaves, are stored level by level.
+struct LevelBounds {
+    int b[kMaxLevel + 2];
+    int n;  // levels; b[0 .. n]
+};
+
+__global__ void k_leaf_levels(const int *__restrict__ off, int ncell, const int *__restrict__ total, LevelBounds lb,
+                              int *__restrict__ out)
+{
+    const int l = threadIdx.x;
+    if (l <= lb.n) out[l] = lb.b[l] < ncell ? off[lb.b[l]] : *total;
+}
+
 __global__ void k_leaf_compact(const Cell *__restrict__ cells, int ncell, const int *__restrict__ flag,
                                const int *__restrict__ off, int *__restrict__ leaves, int *__restrict__ leaf_of)
 {
@@ -467,12 +482,14 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
         t->n = 0;  // the tree is unusable: later calls see an empty tree, never aliased entries
         t->ncell = t->nleaf = t->nlevel = 0;
         t->lvl_beg.assign(1, 0);
+        t->leaf_lvl.assign(1, 0);
         t->stats.n = t->stats.n_cells = t->stats.n_leaves = t->stats.max_level = 0;
         return set_error(FMM_ERR_ARG, "octree of %d cells exceeds the %d cells an interaction-list entry can "
                                       "address (raise n_crit)", nc, kMaxCells - 1);
     }
     if (n == 0) {
         t->nleaf = 0;
+        t->leaf_lvl.assign(t->nlevel + 1, 0);
         return hip_check(hipStreamSynchronize(st), "tree");
     }
     // leaves
@@ -480,10 +497,19 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     int *flag = ptr<int>(t->nch), *off = flag + t->ncell;
     k_leaf_flag<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag);
     if ((rc = scan_exclusive(flag, off, t->ncell, bad + 1, st, t->scan_tmp))) return rc;
-    if ((rc = hip_check(hipMemcpyAsync(t->host, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st), "leaf count")))
+    if (t->nlevel > kMaxLevel + 1) return set_error(FMM_ERR_STATE, "octree deeper than %d levels", kMaxLevel + 1);
+    LevelBounds lb;
+    lb.n = t->nlevel;
+    for (int l = 0; l <= t->nlevel; ++l) lb.b[l] = t->lvl_beg[l];
+    int *hlev = bad + 32;  // flag area [32 ..]: leaves before each level
+    k_leaf_levels<<<1, 64, 0, st>>>(off, t->ncell, bad + 1, lb, hlev);
+    if ((rc = hip_check(hipMemcpyAsync(t->host, bad + 1, sizeof(int), hipMemcpyDeviceToHost, st), "leaf count")) ||
+        (rc = hip_check(hipMemcpyAsync(t->host + 32, hlev, (size_t)(t->nlevel + 1) * sizeof(int),
+                                       hipMemcpyDeviceToHost, st), "leaves per level")))
         return rc;
     if ((rc = hip_check(hipStreamSynchronize(st), "leaf count"))) return rc;
     t->nleaf = t->host[0];
+    t->leaf_lvl.assign(t->host + 32, t->host + 32 + t->nlevel + 1);
     if ((rc = grow(t->leaves, (size_t)t->nleaf * 4 + 4))) return rc;
     k_leaf_compact<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag, off, ptr<int>(t->leaves),
                                                           ptr<int>(t->leaf_of));

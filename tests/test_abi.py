@@ -27,7 +27,7 @@ def test_version_and_error_string():
 
 @pytest.mark.parametrize("bad", [dict(theta=0.0), dict(p=9), dict(p=-1), dict(n_crit=0), dict(r_cut=0.6),
                                  dict(r_s=-1.0), dict(precision=2), dict(mac_mode=8), dict(box=0.0),
-                                 dict(schedule=3), dict(schedule=-1), dict(schedule=2),
+                                 dict(schedule=4), dict(schedule=-1), dict(schedule=2),
                                  dict(schedule=2, precision=1, p=2), dict(schedule=2, precision=1, m2l_mfma=2),
                                  dict(schedule=2, precision=1, learned=1),
                                  dict(schedule=2, precision=1, r_cut=0.24)])
@@ -110,7 +110,7 @@ def test_kernel_candidates_cover_the_served_combinations():
     fp32 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=1)
     c = hf.kernel_candidates(fp32, n_crits=(32, 48))
     combos = {(q.n_crit, q.schedule, q.m2l_mfma) for q in c}
-    assert combos == {(nc, s, m) for nc in (32, 48) for s, m in ((1, 1), (1, 2), (2, 1))}
+    assert combos == {(nc, s, m) for nc in (32, 48) for s, m in ((1, 1), (1, 2), (2, 1), (3, 1), (3, 2))}
     assert all(q.p == 5 and q.theta == 0.4 and q.precision == 1 for q in c)
     fp64 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=0)
-    assert {(q.schedule, q.m2l_mfma) for q in hf.kernel_candidates(fp64)} == {(1, 0)}
+    assert {(q.schedule, q.m2l_mfma) for q in hf.kernel_candidates(fp64)} == {(1, 0), (3, 0)}

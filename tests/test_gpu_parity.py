@@ -282,6 +282,32 @@ def test_deep_chains_outgrow_the_first_cell_estimate():
     assert st["max_level"] >= 18
 
 
+@pytest.mark.parametrize("precision,schedule", [(0, 1), (0, 3), (1, 3)])
+def test_list_pool_overflow_reruns_the_traversal_and_p2p(precision, schedule):
+    """Leaves of one particle and r_cut = 0.4 box: about 2000 P2P entries per leaf, 24M in
+    all (over 340k chunks of 64), against a first pool room of 8 chunks per leaf plus 32
+    per resident traversal wave (about 230k chunks): the first traversal overflows and
+    reruns.  The
+    per-level P2P launches that ran beside the first attempt read only complete lists (those
+    of levels after the overflow skip themselves) and run again with the rerun: forces and
+    lists must match the oracle (schedule 3: P2P per leaf level; 1: after the traversal)."""
+    pos, m = inputs.uniform(12000, inputs.rng_for(150, precision))
+    prm = hf.params(r_s=0.4 / 4.5, r_cut=0.4, theta=0.5, p=4, n_crit=1, precision=precision, schedule=schedule)
+    print("case: pool overflow, precision %d, schedule %d" % (precision, schedule), flush=True)
+    if precision == 0:
+        _, _, e = check_fp64(pos, m, prm)
+        assert e.max() < 1e-9
+        return
+    got, t = gpu_run(pos, m, prm)
+    st = t.stats()
+    t.free()
+    ref = oracle.fmm(pos, m, opar(prm))
+    assert st["n_p2p"] == ref.stats["n_p2p"] and st["p2p_pairs"] == ref.stats["p2p_pairs"]
+    assert st["n_p2p"] > 12000 * 1800
+    e = rel_err(got, ref.acc)
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5
+
+
 @pytest.mark.parametrize("p", [2, 4, 6, 8])
 def test_polynomial_split_fp64_and_fp32(p):
     """The polynomial split (second truncation function): FP64 lists and forces against

@@ -1,5 +1,6 @@
 """Schedule 2: one persistent kernel whose workgroups pull sink leaves (P2P) and then blocks
 of 64 M2L pairs from a device queue (the task pool of Sec. 4 as a GPU work queue).
+Schedule 3: P2P launched per leaf level as soon as the traversal has listed that level.
 
 Against the FP64 oracle at the FP32 bar of the other parity tests (median <= 1e-6, p99
 <= 2e-5 relative), and against schedule 1 (two kernels on two streams) on the same tree:
@@ -159,7 +160,7 @@ def test_autotune_over_parameter_sets():
     pos, m = np.concatenate([b[0] for b in boxes]), np.concatenate([b[1] for b in boxes])
     prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.4, p=5, n_crit=32, precision=1)
     cands = hf.kernel_candidates(prm, n_crits=(16, 32))
-    assert len(cands) == 6
+    assert len(cands) == 10
     best, ms = hf.autotune_params(dev(pos), dev(m), cands, reps=1, offsets=off)
     print("sets (n_crit, schedule, m2l_mfma) -> ms:",
           [((c.n_crit, c.schedule, c.m2l_mfma), round(t, 3)) for c, t in zip(cands, ms)])
@@ -171,3 +172,43 @@ def test_autotune_over_parameter_sets():
     ref = oracle.fmm(boxes[b][0], boxes[b][1], opar(q)).acc
     e = rel_err(got[off[b]:off[b + 1]], ref)
     assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_per_level_p2p_matches_oracle_and_after_traversal(precision):
+    """Schedule 3 on a clustered box whose leaves span many levels, and on a forest: the
+    same counts as schedule 1 and forces equal up to summation order (FP32) or rounding
+    (FP64); against the oracle at the form's bar."""
+    pos, m = inputs.clustered(30000, 12, inputs.rng_for(507, precision))
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.45, p=5, n_crit=8, precision=precision, schedule=3)
+    t = hf.Tree().build(dev(pos), dev(m), prm)
+    print("case: schedule 3, precision %d" % precision, flush=True)
+    a3 = t.short_range(prm).cpu().numpy()
+    s3 = t.stats()
+    assert s3["max_level"] >= 6
+    a1 = t.short_range(hf.copy_params(prm, schedule=1)).cpu().numpy()
+    s1 = t.stats()
+    t.free()
+    for k in ("n_m2l", "n_p2p", "p2p_pairs", "p2p_evaluated"):
+        assert s1[k] == s3[k], k
+    assert rel_err(a3, a1).max() <= (1e-5 if precision else 1e-12)
+    ref = oracle.fmm(pos, m, opar(prm))
+    e = rel_err(a3, ref.acc)
+    if precision:
+        assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5
+    else:
+        assert e.max() <= 1e-9
+    # a forest: every box's leaves of a level in one launch
+    rng = inputs.rng_for(508, precision)
+    sizes = [0, 1] + list(rng.integers(500, 6000, 6))
+    boxes = [inputs.clustered(int(n), 2, rng) if n > 1 else (rng.random((int(n), 3)), np.full(int(n), 0.5))
+             for n in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    fp, fm = np.concatenate([b[0] for b in boxes]), np.concatenate([b[1] for b in boxes])
+    q = hf.params(r_s=0.02, r_cut=0.09, theta=0.4, p=4, n_crit=8, precision=precision, schedule=3)
+    got = hf.short_range_batched(dev(fp), dev(fm), [q] * len(boxes), off).cpu().numpy()
+    for b, (bp, bm) in enumerate(boxes):
+        if len(bp) == 0:
+            continue
+        e = rel_err(got[off[b]:off[b + 1]], oracle.fmm(bp, bm, opar(q)).acc)
+        assert (np.percentile(e, 99) <= 2e-5) if precision else (e.max() <= 1e-9), b
