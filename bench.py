@@ -242,7 +242,7 @@ def main():
         "timing": {"statistic": "median of per-step HIP-event times", "ms_steps": ms,
                    "ms_per_step_mean_wall": wall * 1e3, "input_generation_s": t_gen},
         "roofline": p2p_roofline(st, stage["t_p2p_ms"], wl, args.workload, pr, n, args.split,
-                                 fused=prm.schedule == 2),
+                                 fused=prm.schedule == 2, per_level=per_level(prm.schedule, st)),
         "stages_ms": stage,
         "roofline_step": stage_rooflines(st, stage, stage["t_build_ms"], med, n, pr["p"], bool(wl["learned"]),
                                          wl["precision"], args.split),
@@ -282,7 +282,7 @@ def main():
         out["plain"] = {"form": "plain MAC, fixed p=%d, theta=%.2f" % (pr["p"], wl["theta"]),
                         "value": n / (pmed * 1e-3), "ms_per_step": pmed, "ms_steps": pms_, "stages_ms": pstage,
                         "roofline": p2p_roofline(ps, pstage["t_p2p_ms"], wl, args.workload, pr, n, args.split,
-                                                 learned=False),
+                                                 learned=False, per_level=per_level(pp.schedule, ps)),
                         "counts": {k: ps[k] for k in ("n_m2l", "n_p2p", "p2p_pairs", "p2p_evaluated", "n_visit")},
                         "learned_speedup": pmed / med}
 
@@ -353,12 +353,20 @@ def tune_kernels(hf, pos, mass, prm, offsets=None, n_crits=(32, 48), reps=2):
     return cands[best], table
 
 
-def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=False):
+def per_level(schedule, st):
+    """Whether the library launched P2P per leaf level beside the traversal (schedule 3, or
+    the library's choice for trees of 2^22 leaves or more)."""
+    return schedule == 3 or (schedule == 0 and st["n_leaves"] >= (1 << 22))
+
+
+def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=False, per_level=False):
     """Roofline of the P2P kernel (the dominant one on the clustered boxes): algorithmic
     work = 38 flop per listed pair (30 with the polynomial split) over the launch's
     HIP-event duration on its own stream, against the FP32 (or FP64) vector peak.  Under
     the persistent schedule the kernel is the one P2P + M2L launch and its work adds the
-    M2L arithmetic, 2 C(p+6, 6) flop per accepted pair.
+    M2L arithmetic, 2 C(p+6, 6) flop per accepted pair.  With P2P launched per leaf level
+    beside the traversal, the duration is the sum of those launches, which share the device
+    with the traversal.
     traffic: scaled FETCH_SIZE + WRITE_SIZE per launch from profiles/, when those counters
     were taken on this workload with these parameters and the current P2P sources."""
     learned = wl["learned"] if learned is None else learned
@@ -382,7 +390,9 @@ def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=Fal
                             + (" + 2 C(p+6,6) flop per M2L pair" if fused else ""),
             "m2l_flop_in_launch": m2l_flop,
             "listed_pairs": st["p2p_pairs"], "evaluated_pairs": st["p2p_evaluated"],
-            "p2p_ms_per_launch": p2p_ms}
+            "p2p_ms_per_launch": p2p_ms,
+            "launches": ("one per leaf level, beside the traversal: duration = their sum per step" if per_level
+                         else "one per step")}
 
 
 def _binom(n, k):

@@ -82,7 +82,7 @@ extern "C" {
  *             one device queue until both stages are done; 3 as 1, but the P2P of each
  *             leaf level is launched as soon as the traversal has listed that level, so
  *             it runs beside the traversal of the finer levels; 0 the library's choice (3
- *             for trees of 2^20 leaves or more, else 1).  Schedule 2 requires precision 1,
+ *             for trees of 2^22 leaves or more, else 1).  Schedule 2 requires precision 1,
  *             learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, the degree-10 force
  *             law (r_cut / r_s up to about 5.6); FMM_ERR_ARG otherwise.  The results do
  *             not depend on the schedule beyond FP32 summation order.

@@ -143,11 +143,11 @@ static int run_forces(fmm_tree *t, const fmm_params *P, double *acc, hipStream_t
         return rc;
     mark(t, 0, st);
     const bool fused = P->schedule == 2;
-    // P2P level by level beside the traversal: measured faster from about a million leaves
-    // (16.7M box 77.9 -> 75.3 ms, 134M box 3% faster), slower below (2M box 9.2 -> 11.4 ms,
-    // 64-box forest 12.4 -> 16.6 ms: most P2P work sits in the finest levels, listed last,
-    // and each level's launch ends in its own tail)
-    const bool per_level = P->schedule == 3 || (P->schedule == 0 && t->nleaf >= (1 << 20));
+    // P2P level by level beside the traversal, measured on one box each: 134M box 718 ->
+    // 697 ms (19M leaves), 16.7M box 75.5 -> 75.0 ms (2.3M leaves), slower on small trees
+    // (2M box 9.2 -> 11.4 ms, 64-box forest 12.4 -> 16.6 ms): most P2P work sits in the
+    // finest levels, listed last, and each level's launch ends in its own tail
+    const bool per_level = P->schedule == 3 || (P->schedule == 0 && t->nleaf >= (1 << 22));
     LevelP2P lp{t, P, ax};
     const TravHook hook{p2p_level_hook, &lp, ax};
     const TravHook *hk = per_level ? &hook : nullptr;

@@ -92,3 +92,12 @@ def test_cube_sample_takes_whole_seeded_cubes(bench):
     assert 0.005 < len(tg) / len(pos) < 0.015
     assert np.array_equal(tg, bench.cube_sample(pos, 0.01, 5))  # seeded
     assert len(bench.cube_sample(pos, 1.0, 5)) == len(pos)
+
+
+def test_per_level_launches_follow_the_library_choice(bench):
+    assert bench.per_level(3, {"n_leaves": 10})
+    assert not bench.per_level(1, {"n_leaves": 1 << 23})
+    assert bench.per_level(0, {"n_leaves": 1 << 22}) and not bench.per_level(0, {"n_leaves": (1 << 22) - 1})
+    wl = {"learned": False, "precision": 1, "theta": 0.5, "n_crit": 32}
+    r = bench.p2p_roofline({"p2p_pairs": 10, "p2p_evaluated": 8}, 1.0, wl, "none", {"p": 8}, 10, 0, per_level=True)
+    assert "per leaf level" in r["launches"]
