@@ -59,8 +59,8 @@ extern "C" {
  *             r_cut, no forced opening across it; forces stay correct, at higher cost)
  *   precision 0: FP64 everywhere; 1: P2P and M2L in FP32 on cell-relative coordinates with
  *             compensated per-particle sums, FP64 positions, cell offsets and final sum;
- *             with split 0 the FP32 pair force uses a fitted polynomial whose degree (10 or
- *             14) is chosen for r_cut / r_s, and r_cut > 6 r_s is rejected (FMM_ERR_ARG):
+ *             with split 0 the FP32 pair force uses a fitted polynomial whose degree (9, 10
+ *             or 14) is chosen for r_cut / r_s, and r_cut > 6 r_s is rejected (FMM_ERR_ARG):
  *             beyond it FP32 cancellation near the cutoff exceeds the form's error bar
  *   learned   0: plain MAC at fixed p; 1: learned accept/order selector (see
  *             fmm_load_mac_model), the plain MAC's hard rules still apply
@@ -83,8 +83,8 @@ extern "C" {
  *             leaf level is launched as soon as the traversal has listed that level, so
  *             it runs beside the traversal of the finer levels; 0 the library's choice (3
  *             for trees of 2^22 leaves or more, else 1).  Schedule 2 requires precision 1,
- *             learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, the degree-10 force
- *             law (r_cut / r_s up to about 5.6); FMM_ERR_ARG otherwise.  The results do
+ *             learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, a force law of
+ *             degree 9 or 10 (r_cut / r_s up to about 5.1); FMM_ERR_ARG otherwise.  The results do
  *             not depend on the schedule beyond FP32 summation order.
  *   reserved  must be 0. */
 typedef struct fmm_params {

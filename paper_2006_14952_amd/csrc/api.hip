@@ -51,7 +51,7 @@ static int check_params(const fmm_params *P)
     }
     if (P->schedule == 2 && !fused_applies(P))
         return set_error(FMM_ERR_ARG, "schedule 2 (one persistent P2P + M2L kernel) requires precision 1, learned 0, "
-                                      "3 <= p <= 8, m2l_mfma != 2 and the degree-10 force law");
+                                      "3 <= p <= 8, m2l_mfma != 2 and a force law of degree 9 or 10");
     return 0;
 }
 

@@ -54,9 +54,12 @@ constexpr int kChunk = 64;
 constexpr int kMaxCells = 1 << 27;
 
 // Per-call constants of the P2P force law in FP32: f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),
-// t = 2 r^2 / r_cut^2 - 1, S a polynomial fitted on the host: of degree 10 or 14, the
-// lower whose error in r^3 f_(1) stays below kP2PFitTol over [0, r_cut] (checked on the
-// host at every fit; degree 10 serves r_cut up to about 5 r_s, 14 beyond).  The two terms
+// t = 2 r^2 / r_cut^2 - 1, S a polynomial fitted on the host: of degree 9, 10 or 14, the
+// lowest whose error in r^3 f_(1) stays below kP2PFitTol over [0, r_cut] (checked on the
+// host at every fit, with the coefficients rounded to FP32; degree 9 serves r_cut up to
+// about 4.6 r_s, 10 up to about 5.1 r_s, 14 up to 6 r_s: degree 12 also meets the
+// tolerance there, but at 6 r_s its larger error, 5e-7 against 2e-7, put the force's p99
+// against the FP64 oracle at 2.1e-5 and its maximum at 1.4e-3).  The two terms
 // cancel as r^3 f_(1) = -(erfc(u) + 2u/sqrt(pi) e^(-u^2)), u = r/2r_s, falls towards r_cut:
 // their FP32 rounding (about 1e-7 of 1/r^3) is 2e-5 of a pair's own force at a cutoff of
 // 4.5 r_s, 2e-4 at 6 r_s and 5e-2 at 7 r_s, where particles whose force comes from pairs

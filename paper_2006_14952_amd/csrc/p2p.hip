@@ -13,7 +13,7 @@
 // centre offset c_B + s box - c_A added when staging, and
 //   f_(1)(r) = -1/r^3 + S(t)/(8 r_s^3),  t = 2 r^2/r_cut^2 - 1,
 // with S(t) = (4/sqrt(pi)) int_0^1 q^2 exp(-v q^2) dq (v = r^2/4r_s^2) replaced by a
-// polynomial of degree 10 or 14 fitted on the host, the lower that meets the FP32
+// polynomial of degree 9, 10 or 14 fitted on the host, the lowest that meets the FP32
 // tolerance at this r_cut / r_s <= 6 (its coefficients carry the factor 1/(8 r_s^3));
 // the sum of each staged block is added to a Kahan-compensated per-particle accumulator.
 // A listed source leaf whose particles' bounding box lies farther than r_cut from the sink
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5)
 // queue is empty: first the sink leaves (P2P), then the 64-pair blocks of the flattened
 // M2L array.  One launch covers both stages of every box of a forest, so no stage waits
 // for the tail of another and no launch boundary falls between them.
-template <bool POLY, int P>
+template <bool POLY, int NPC, int P>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 2 : (P >= 5 ? 3 : 4)))) void k_p2p_m2l_persist(
     P2PArgs a, P2PConst k, const int2 *__restrict__ pairs, int64_t npair, const float *__restrict__ M,
     float *__restrict__ L, Split sp, int stride, int *__restrict__ queue)
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 2 :
         if (threadIdx.x == 0) item = atomicAdd(queue, 1);
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
         if (item >= total) break;
-        if (item < nleaf) p2p_leaf<false, POLY, 11>(a, k, item, sh.p);
+        if (item < nleaf) p2p_leaf<false, POLY, NPC>(a, k, item, sh.p);
         else m2l_pairs_block<P, float>(a.cells, pairs, npair, M, L, a.box, sp, stride, item - nleaf, sh.m);
         __syncthreads();  // the block's shared memory is reused by the next item
     }
@@ -458,7 +458,7 @@ static double fit_error(double vcut, int m, const double *coef)
     return worst;
 }
 
-// Force-law constants.  FP32 form, Gaussian split: the lower polynomial length of 11 and 15 whose
+// Force-law constants.  FP32 form, Gaussian split: the lowest polynomial length of 10, 11, 15 whose
 // checked error is at most kP2PFitTol; returns FMM_ERR_ARG for r_cut > kP2PMaxCut r_s (FP32
 // cancellation near the cutoff) or if no fit meets the tolerance.  The last fit is cached
 // (same vcut, same result).
@@ -479,7 +479,7 @@ int p2p_setup(const fmm_params *P, P2PConst &k)
         std::lock_guard<std::mutex> lk(mu);
         if (vcut != cached_vcut) {
             cached_m = 0;
-            for (int mm : {11, 15}) {
+            for (int mm : {10, 11, 15}) {
                 fit_S(vcut, mm, cached);
                 if (fit_error(vcut, mm, cached) <= kP2PFitTol) {
                     cached_m = mm;
@@ -542,16 +542,16 @@ static void p2p_args(fmm_tree *t, P2PArgs &a)
 }
 
 // Whether the fused persistent kernel serves these parameters: the FP32 plain form with
-// the pair M2L kernel (orders 3..8) and the degree-10 force law or the polynomial split.
+// the pair M2L kernel (orders 3..8) and a force law of degree 9 or 10, or the polynomial split.
 bool fused_applies(const fmm_params *P)
 {
     if (P->precision != 1 || P->learned || P->p < 3 || P->m2l_mfma == 2) return false;
     if (P->split == 1) return true;
     P2PConst k;
-    return p2p_setup(P, k) == 0 && k.ncoef == 11;
+    return p2p_setup(P, k) == 0 && (k.ncoef == 10 || k.ncoef == 11);
 }
 
-template <bool POLY, int P> static int launch_persist(fmm_tree *t, const P2PArgs &a, const P2PConst &k, Split sp,
+template <bool POLY, int NPC, int P> static int launch_persist(fmm_tree *t, const P2PArgs &a, const P2PConst &k, Split sp,
                                                       int64_t np, int *queue, hipStream_t st)
 {
     static int per_cu = 0, ncu = 0;
@@ -559,14 +559,14 @@ template <bool POLY, int P> static int launch_persist(fmm_tree *t, const P2PArgs
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_p2p_m2l_persist<POLY, P>, 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_p2p_m2l_persist<POLY, NPC, P>, 64, 0) != hipSuccess ||
             per_cu <= 0)
             return set_error(FMM_ERR_HIP, "occupancy of the fused kernel");
     }
     const int64_t items = (int64_t)t->nleaf + (np + 63) / 64;
     const int64_t g = std::min<int64_t>(items, (int64_t)per_cu * ncu);
     if (g <= 0) return 0;
-    k_p2p_m2l_persist<POLY, P><<<(unsigned)g, 64, 0, st>>>(a, k, ptr<int2>(t->m2l_pairs), np, ptr<float>(t->Mc),
+    k_p2p_m2l_persist<POLY, NPC, P><<<(unsigned)g, 64, 0, st>>>(a, k, ptr<int2>(t->m2l_pairs), np, ptr<float>(t->Mc),
                                                           ptr<float>(t->Lc), sp, ncoef(P), queue);
     return hip_check(hipGetLastError(), "fused p2p + m2l");
 }
@@ -598,24 +598,33 @@ int p2p_m2l_fused_launch(fmm_tree *t, const fmm_params *P, hipStream_t st)
     const Split sp{P->split ? P->r_cut : P->r_s, P->split};
     if (P->split == 1) {
         switch (P->p) {
-        case 3: return launch_persist<true, 3>(t, a, k, sp, np, queue, st);
-        case 4: return launch_persist<true, 4>(t, a, k, sp, np, queue, st);
-        case 5: return launch_persist<true, 5>(t, a, k, sp, np, queue, st);
-        case 6: return launch_persist<true, 6>(t, a, k, sp, np, queue, st);
-        case 7: return launch_persist<true, 7>(t, a, k, sp, np, queue, st);
-        case 8: return launch_persist<true, 8>(t, a, k, sp, np, queue, st);
+        case 3: return launch_persist<true, 11, 3>(t, a, k, sp, np, queue, st);
+        case 4: return launch_persist<true, 11, 4>(t, a, k, sp, np, queue, st);
+        case 5: return launch_persist<true, 11, 5>(t, a, k, sp, np, queue, st);
+        case 6: return launch_persist<true, 11, 6>(t, a, k, sp, np, queue, st);
+        case 7: return launch_persist<true, 11, 7>(t, a, k, sp, np, queue, st);
+        case 8: return launch_persist<true, 11, 8>(t, a, k, sp, np, queue, st);
         }
-    } else {
+    } else if (k.ncoef == 10) {
         switch (P->p) {
-        case 3: return launch_persist<false, 3>(t, a, k, sp, np, queue, st);
-        case 4: return launch_persist<false, 4>(t, a, k, sp, np, queue, st);
-        case 5: return launch_persist<false, 5>(t, a, k, sp, np, queue, st);
-        case 6: return launch_persist<false, 6>(t, a, k, sp, np, queue, st);
-        case 7: return launch_persist<false, 7>(t, a, k, sp, np, queue, st);
-        case 8: return launch_persist<false, 8>(t, a, k, sp, np, queue, st);
+        case 3: return launch_persist<false, 10, 3>(t, a, k, sp, np, queue, st);
+        case 4: return launch_persist<false, 10, 4>(t, a, k, sp, np, queue, st);
+        case 5: return launch_persist<false, 10, 5>(t, a, k, sp, np, queue, st);
+        case 6: return launch_persist<false, 10, 6>(t, a, k, sp, np, queue, st);
+        case 7: return launch_persist<false, 10, 7>(t, a, k, sp, np, queue, st);
+        case 8: return launch_persist<false, 10, 8>(t, a, k, sp, np, queue, st);
+        }
+    } else if (k.ncoef == 11) {
+        switch (P->p) {
+        case 3: return launch_persist<false, 11, 3>(t, a, k, sp, np, queue, st);
+        case 4: return launch_persist<false, 11, 4>(t, a, k, sp, np, queue, st);
+        case 5: return launch_persist<false, 11, 5>(t, a, k, sp, np, queue, st);
+        case 6: return launch_persist<false, 11, 6>(t, a, k, sp, np, queue, st);
+        case 7: return launch_persist<false, 11, 7>(t, a, k, sp, np, queue, st);
+        case 8: return launch_persist<false, 11, 8>(t, a, k, sp, np, queue, st);
         }
     }
-    return set_error(FMM_ERR_ARG, "fused kernel compiled for orders 3..8");
+    return set_error(FMM_ERR_ARG, "fused kernel compiled for orders 3..8 and force laws of degree 9 or 10");
 }
 
 int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int *err, hipStream_t st)
@@ -634,8 +643,10 @@ int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int 
         a.bbox = nullptr;
     }
     if (P->precision && P->split == 1) k_p2p<false, true, 11><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 10) k_p2p<false, false, 10><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 11) k_p2p<false, false, 11><<<count, 64, 0, st>>>(a, k);
     else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<count, 64, 0, st>>>(a, k);
-    else if (P->precision) k_p2p<false, false, 11><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision) return set_error(FMM_ERR_STATE, "p2p: no kernel for a force law of %d coefficients", k.ncoef);
     else k_p2p<true, false, 11><<<count, 64, 0, st>>>(a, k);
     return hip_check(hipGetLastError(), "p2p");
 }

@@ -115,7 +115,8 @@ def test_clustered_midsize_fp64_and_fp32():
 @pytest.mark.parametrize("ratio", [5.0, 5.5, 6.0])
 def test_fp32_force_law_at_larger_cutoffs(ratio):
     """The FP32 pair force is a polynomial fit whose degree the library raises with
-    r_cut / r_s (10 up to about 5 r_s, 14 up to 6 r_s, the largest it accepts): at cutoffs
+    r_cut / r_s (9 up to about 4.6 r_s, 10 up to about 5.1 r_s, 14 up to 6 r_s, the largest
+    it accepts): at cutoffs
     beyond the workloads' 4.5 r_s the FP32 form must still meet the FP32 bar against the
     FP64 oracle."""
     rng = inputs.rng_for(108, int(ratio * 10))
