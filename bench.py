@@ -367,8 +367,9 @@ def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=Fal
     M2L arithmetic, 2 C(p+6, 6) flop per accepted pair.  With P2P launched per leaf level
     beside the traversal, the duration is the sum of those launches, which share the device
     with the traversal.
-    traffic: scaled FETCH_SIZE + WRITE_SIZE per launch from profiles/, when those counters
-    were taken on this workload with these parameters and the current P2P sources."""
+    traffic: scaled FETCH_SIZE + WRITE_SIZE of the step's P2P launches from profiles/, when
+    those counters were taken on this workload with these parameters, the same launch
+    pattern and the current P2P sources."""
     learned = wl["learned"] if learned is None else learned
     flop = P2P_FLOP_PER_PAIR[split] * st["p2p_pairs"]
     m2l_flop = 2 * _binom(pr["p"] + 6, 6) * st["n_m2l"] if fused else 0
@@ -381,7 +382,8 @@ def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=Fal
         rec = json.load(open(tf))
         same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
                                                 ("n_crit", wl["n_crit"]), ("learned", bool(learned)),
-                                                ("split", split), ("p2p_source_sha", p2p_source_sha())))
+                                                ("split", split), ("p2p_source_sha", p2p_source_sha()),
+                                                ("per_level", bool(per_level))))
         if same and not fused:
             traffic = rec.get("bytes_per_launch")
     return {"kernel": "p2p + m2l (one persistent launch)" if fused else "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
