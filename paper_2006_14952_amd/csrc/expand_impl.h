@@ -811,7 +811,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     T *__restrict__ L, double box, Split sp, int stride)
 {
     __shared__ M2LPairShared<P, T> sh;
-    m2l_pairs_block<P, T>(cells, pairs, npair, M, L, box, sp, stride, blockIdx.x, sh);
+    m2l_pairs_block<P, T>(cells, pairs, npair, M, L, box, sp, stride, xcd_order(blockIdx.x, gridDim.x), sh);
 }
 
 int flatten_pairs(fmm_tree *t, int kind, int64_t npair, hipStream_t st);

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5)
 {
     __shared__ P2PShared<F64> sh;
     if (a.err && *a.err) return;  // the traversal overflowed: it reruns, and so does P2P
-    p2p_leaf<F64, POLY, NPC>(a, k, a.first + blockIdx.x, sh);
+    p2p_leaf<F64, POLY, NPC>(a, k, a.first + xcd_order(blockIdx.x, gridDim.x), sh);
 }
 
 // ---------------------------------------------------------------------------

@@ -203,7 +203,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == kMod
         bnext[k] = __builtin_amdgcn_readfirstlane(ws[k]);
         bend[k] = __builtin_amdgcn_readfirstlane(ws[kKinds + k]);
     }
-    for (int t = blockIdx.x; t < a.ln; t += gridDim.x) {
+    for (int t = xcd_order(blockIdx.x, gridDim.x); t < a.ln; t += gridDim.x) {
         const int A = a.lbeg + t;
         const int4 ga = cellc[A];
         const int parentA = a.cells[A].parent;
