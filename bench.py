@@ -43,12 +43,19 @@ P2P_FLOP_PER_PAIR = {0: 38.0, 1: 30.0}
 # cpu_cubes: the oracle's sample for cpu_baseline, a seeded fraction of the level-6 cubes
 # of the box (all particles in them; 1.0 = the whole input); cpu_cubes_1t the same for the
 # one-thread figure.
+# n_crit: the leaf limit used without autotuning; tune: the leaf limits the library's
+# autotuner chooses from before timing (the default); kernels: the batched line also tunes
+# the schedule and the M2L kernel.
 WORKLOADS = {
-    "full": dict(theta=0.5, precision=1, n_crit=32, learned=True, cpu_cubes=0.0025, cpu_cubes_1t=0.0001),
-    "large": dict(theta=0.5, precision=1, n_crit=32, learned=False, cpu_cubes=0.01, cpu_cubes_1t=0.0005),
-    "clustered": dict(theta=0.42, precision=1, n_crit=32, learned=False, cpu_cubes=0.05, cpu_cubes_1t=0.005),
-    "uniform": dict(theta=0.5, precision=0, n_crit=32, learned=False, cpu_cubes=1.0, cpu_cubes_1t=0.05),
-    "batched": dict(theta=0.4, precision=1, n_crit=32, learned=False, autotune=True, cpu_cubes=0.1,
+    "full": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96, 128), learned=True, cpu_cubes=0.0025,
+                 cpu_cubes_1t=0.0001),
+    "large": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96), learned=False, cpu_cubes=0.01,
+                  cpu_cubes_1t=0.0005),
+    "clustered": dict(theta=0.42, precision=1, n_crit=48, tune=(32, 48, 64), learned=False, cpu_cubes=0.05,
+                      cpu_cubes_1t=0.005),
+    "uniform": dict(theta=0.5, precision=0, n_crit=32, tune=(16, 32, 64), learned=False, cpu_cubes=1.0,
+                    cpu_cubes_1t=0.05),
+    "batched": dict(theta=0.4, precision=1, n_crit=48, tune=(32, 48, 64), kernels=True, learned=False, cpu_cubes=0.1,
                     cpu_cubes_1t=0.01),
 }
 M2L_KERNELS = {0: "library's choice (vector ALUs)", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}
@@ -105,9 +112,9 @@ def main():
     ap.add_argument("--precision", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--n-crit", type=int, default=None)
-    ap.add_argument("--autotune", type=int, default=None, choices=(0, 1),
-                    help="1: choose n_crit, schedule and M2L kernel with the library's autotuner before timing "
-                         "(default: batched only)")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1),
+                    help="1 (default): choose n_crit (batched: also schedule and M2L kernel) with the library's "
+                         "autotuner before timing; 0: the workload's fixed n_crit (or --n-crit)")
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 3),
                     help="P2P and M2L: 0 library's choice, 1 two kernels on two streams, 2 one persistent kernel, "
                          "3 as 1 with P2P per leaf level during the traversal")
@@ -174,9 +181,8 @@ def main():
     pos = torch.tensor(pos_np, device=dev)
     mass = torch.tensor(m_np, device=dev)
     tuned = None
-    if args.autotune if args.autotune is not None else wl.get("autotune", False):
-        log("autotuning n_crit, schedule and M2L kernel")
-        prm, tuned = tune_kernels(hf, pos, mass, prm, offsets if batched else None)
+    if args.autotune and args.n_crit is None:
+        prm, tuned = tune(hf, wl, pos, mass, prm, offsets if batched else None)
         wl["n_crit"] = prm.n_crit
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -341,6 +347,18 @@ def cpu_baseline(oracle, pos, m, op, frac, nthreads, what):
     if res.stats.get("p2p_pairs"):
         rec["p2p_incut_fraction"] = res.stats["p2p_incut"] / res.stats["p2p_pairs"]
     return rec, (tg, res.acc)
+
+
+def tune(hf, wl, pos, mass, prm, offsets=None):
+    """The workload's launch configuration from the library's autotuner: the leaf limit
+    from wl["tune"] (and, with wl["kernels"], the schedule and the M2L kernel); returns the
+    parameter set and every candidate's ms per step."""
+    if wl.get("kernels"):
+        log("autotuning n_crit, schedule and M2L kernel")
+        return tune_kernels(hf, pos, mass, prm, offsets, n_crits=wl["tune"])
+    log("autotuning n_crit over %s" % (wl["tune"],))
+    best, ms = hf.autotune(pos, mass, prm, candidates=wl["tune"], offsets=offsets)
+    return hf.copy_params(prm, n_crit=best), {"n_crit %d" % k: round(v, 3) for k, v in ms.items()}
 
 
 def tune_kernels(hf, pos, mass, prm, offsets=None, n_crits=(32, 48), reps=2):

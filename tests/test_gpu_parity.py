@@ -144,24 +144,31 @@ def test_fp32_rejects_cutoffs_beyond_the_fit():
     assert rel_err(got, oracle.fmm(pos, m, opar(prm)).acc).max() < 1e-9
 
 
-def test_clustered_config_full_size_sampled():
-    """N = 128^3 clustered, p = 6, at the opening angle and leaf limit the benchmark times
-    for this box, FP32 and FP64 forms at full size; the oracle evaluates 1500 sampled
-    particles exactly (only their sink cells are traversed)."""
+def _bench_leaf_limits(workload):
+    import bench
+    return bench.WORKLOADS[workload]["tune"]
+
+
+@pytest.mark.parametrize("ncrit", _bench_leaf_limits("clustered"))
+def test_clustered_config_full_size_sampled(ncrit):
+    """N = 128^3 clustered, p = 6, at the opening angle the benchmark times for this box and
+    each leaf limit its autotuner chooses from, FP32 and FP64 forms at full size; the oracle
+    evaluates 1500 sampled particles exactly (only their sink cells are traversed)."""
     import bench
     wl = bench.WORKLOADS["clustered"]
     pos, m = inputs.make("clustered")
     pr = inputs.split_params("clustered")
     tg = inputs.rng_for(1, 7).choice(len(pos), 1500, replace=False)
-    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"], precision=0)
+    prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=ncrit, precision=0)
+    print("case: clustered full size, n_crit %d" % ncrit, flush=True)
     got64, ref, e64 = check_fp64(pos, m, prm, lists=False, targets=tg)
     bf = oracle.bruteforce(pos, m, opar(prm), targets=tg)
     assert np.percentile(rel_err(got64[tg], bf), 99) <= 1e-3
     prm.precision = 1
     got32, _ = gpu_run(pos, m, prm)
     e32 = rel_err(got32[tg], ref.acc[tg])
-    print("fp32 full size vs oracle: median %.2e p99 %.2e max %.2e" % (np.median(e32), np.percentile(e32, 99),
-                                                                      e32.max()))
+    print("fp32 full size, n_crit %d, vs oracle: median %.2e p99 %.2e max %.2e" % (
+        ncrit, np.median(e32), np.percentile(e32, 99), e32.max()))
     assert np.percentile(e32, 99) <= 1e-4
     assert np.percentile(rel_err(got32[tg], bf), 99) <= 1e-3
 

@@ -227,7 +227,7 @@ def test_batched_config_full_forest_sampled():
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     pos, m = dev(np.concatenate([b[0] for b in boxes])), dev(np.concatenate([b[1] for b in boxes]))
     prm = hf.params(r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=32, precision=1)
-    prm, table = bench.tune_kernels(hf, pos, m, prm, off)
+    prm, table = bench.tune(hf, wl, pos, m, prm, off)
     best = prm.n_crit
     print("autotuned:", table)
     t = hf.Tree().build_batched(pos, m, [prm] * len(boxes), off)
