@@ -76,6 +76,25 @@ def test_fp32_every_order_clustered(p):
     t.free()
 
 
+@pytest.mark.parametrize("ncrit", [33, 96, 300])
+def test_fp32_leaves_larger_than_a_sink_chunk(ncrit):
+    """Leaves of more sink particles than one P2P pass takes: each chunk is tested against
+    the box of its own particles, and the forces must still meet the FP32 bar against the
+    oracle (lists and counts identical)."""
+    pos, m = inputs.clustered(30000, 10, inputs.rng_for(106, ncrit))
+    prm = hf.params(r_s=0.012, r_cut=0.054, theta=0.5, p=5, n_crit=ncrit, precision=1)
+    got, t = gpu_run(pos, m, prm)
+    st = t.stats()
+    t.free()
+    ref = oracle.fmm(pos, m, opar(prm))
+    assert st["n_m2l"] == ref.stats["n_m2l"] and st["n_p2p"] == ref.stats["n_p2p"]
+    assert ref.stats["p2p_incut"] <= st["p2p_evaluated"] <= st["p2p_pairs"] == ref.stats["p2p_pairs"]
+    e = rel_err(got, ref.acc)
+    print("n_crit %d fp32 vs oracle: median %.2e p99 %.2e max %.2e; evaluated / listed %.3f" % (
+        ncrit, np.median(e), np.percentile(e, 99), e.max(), st["p2p_evaluated"] / st["p2p_pairs"]))
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5 and e.max() <= 1e-3
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_mac_modes_lists_identical(mode):
     """Every MAC reading, and the conventional MAC (bit 2), on the GPU and the oracle."""
