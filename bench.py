@@ -396,14 +396,15 @@ def p2p_roofline(st, p2p_ms, wl, workload, pr, n, split, learned=None, fused=Fal
     achieved = flop / (p2p_ms * 1e-3) if p2p_ms > 0 else 0.0
     traffic = None
     tf = os.path.join(ROOT, "profiles", "p2p_traffic_%s_fp%d.json" % (workload, 32 if wl["precision"] else 64))
-    if os.path.exists(tf):
-        rec = json.load(open(tf))
-        same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
-                                                ("n_crit", wl["n_crit"]), ("learned", bool(learned)),
-                                                ("split", split), ("p2p_source_sha", p2p_source_sha()),
-                                                ("per_level", bool(per_level))))
-        if same and not fused:
-            traffic = rec.get("bytes_per_launch")
+    if os.path.exists(tf) and not fused:
+        recs = json.load(open(tf))
+        for rec in recs if isinstance(recs, list) else [recs]:
+            same = all(rec.get(k) == v for k, v in (("n", n), ("p", pr["p"]), ("theta", wl["theta"]),
+                                                    ("n_crit", wl["n_crit"]), ("learned", bool(learned)),
+                                                    ("split", split), ("p2p_source_sha", p2p_source_sha()),
+                                                    ("per_level", bool(per_level))))
+            if same:
+                traffic = rec.get("bytes_per_launch")
     return {"kernel": "p2p + m2l (one persistent launch)" if fused else "p2p", "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic, "flop_per_launch": flop,
             "unit_of_work": "%.0f flop per listed particle pair" % P2P_FLOP_PER_PAIR[split]
