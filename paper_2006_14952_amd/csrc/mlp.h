@@ -14,14 +14,18 @@ constexpr int kOffW1 = 0, kOffB1 = 1024, kOffW2 = 1088, kOffB2 = 5184, kOffW3 = 
 constexpr int kNParam = 5768;
 
 typedef short short4v __attribute__((ext_vector_type(4)));
+typedef short short8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
-// The network as the inference reads it: BF16 MFMA B-operand fragments of the weights
-// (see build_model), FP32 biases and feature normalisation.
+// The network as the inference reads it: BF16 MFMA A-operand fragments of the weights
+// (see build_model), FP32 biases and feature normalisation.  Layer 1 (16 inputs) runs on
+// the 16x16x16 BF16 MFMA, layers 2 and 3 (64 inputs) on the 16x16x32 one, two K steps
+// each instead of four.
 struct MlpWeights {
     short4v w1[4][64];      // [col tile][lane]
-    short4v w2[4][4][64];   // [k chunk][col tile][lane]
-    short4v w3[4][64];      // [k chunk][lane]
+    short8v w2[2][4][64];   // [k chunk of 32][col tile][lane]
+    short8v w3[2][64];      // [k chunk of 32][lane]
     float b1[64], b2[64], b3[16];
     float mu[kFeat], isd[kFeat];
 };
@@ -135,11 +139,17 @@ __device__ __forceinline__ short4v relu_pack(const float4v c, const float4 bias)
 
 // Logits of the 64 pairs of a wave (one per lane; lanes without a pair take part with
 // zero features).  `act` is 64 x 64 BF16 of LDS, `out` receives 8 logits per lane.
-// v_mfma_f32_16x16x16_bf16 operand layout (per lane l): A[i = l%16][k = 4(l/16)+r],
-// B[k = 4(l/16)+r][j = l%16], D[i = 4(l/16)+r][j = l%16], r = 0..3.  Each layer computes
-// the transposed product D = W^T act^T: the weight fragment is the A operand and the
-// activations the B operand, so a lane ends with 4 consecutive outputs of one pair.
-// Row tile t holds pairs 16t .. 16t+15.
+// MFMA operand layout (per lane l, lane group g = l/16): v_mfma_f32_16x16x16_bf16 takes
+// A[i = l%16][k = 4g+r] and B[k = 4g+r][j = l%16], r = 0..3; v_mfma_f32_16x16x32_bf16 takes
+// 8 values per lane, K slots (g, r), r = 0..7, paired between A and B the same way; both
+// give D[i = 4g+r][j = l%16], r = 0..3.  Each layer computes the transposed product
+// D = W^T act^T: the weight fragment is the A operand and the activations the B operand,
+// so a lane ends with 4 consecutive outputs of one pair.  Row tile t holds pairs 16t .. 16t+15.
+__device__ __forceinline__ bf8v cat_bf8(const short4v lo, const short4v hi)
+{
+    return __builtin_bit_cast(bf8v, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float *fin, short *act, float *out)
 {
     const int lane = threadIdx.x & 63;
@@ -155,7 +165,8 @@ __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float
     }
     __syncthreads();
     // The output fragment of a layer (4 consecutive outputs of one pair per lane) is laid
-    // out as the next layer's B operand (4 consecutive inputs of one pair), so the hidden
+    // out as the next layer's B operand: two fragments side by side are the 8 K slots of a
+    // 16x16x32 step (build_model orders the next layer's weights to match), so the hidden
     // activations stay in registers; only the input (one pair per lane) and the logits
     // (back to one pair per lane) pass through LDS.
     short4v h1[4][4];  // [pair tile t][output chunk u]
@@ -178,10 +189,12 @@ __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float
     for (int u = 0; u < 4; ++u) {
         float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-            const short4v w = W.w2[kc][u][lane];
+        for (int kc = 0; kc < 2; ++kc) {
+            const bf8v w = __builtin_bit_cast(bf8v, W.w2[kc][u][lane]);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h1[t][kc], c[t], 0, 0, 0);
+            for (int t = 0; t < 4; ++t)
+                c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, cat_bf8(h1[t][2 * kc], h1[t][2 * kc + 1]), c[t], 0, 0,
+                                                               0);
         }
         const float4 bias = *reinterpret_cast<const float4 *>(W.b2 + 16 * u + 4 * lk);
 #pragma unroll
@@ -190,10 +203,11 @@ __device__ __forceinline__ void mlp_logits_wave(const MlpWeights &W, const float
     // layer 3: 64 -> 8 (padded to 16 outputs)
     float4v c[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-        const short4v w = W.w3[kc][lane];
+    for (int kc = 0; kc < 2; ++kc) {
+        const bf8v w = __builtin_bit_cast(bf8v, W.w3[kc][lane]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) c[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w, h2[t][kc], c[t], 0, 0, 0);
+        for (int t = 0; t < 4; ++t)
+            c[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, cat_bf8(h2[t][2 * kc], h2[t][2 * kc + 1]), c[t], 0, 0, 0);
     }
     __syncthreads();  // every lane has read its input rows before the logits overwrite them
     float *fout = reinterpret_cast<float *>(act);

@@ -57,17 +57,19 @@ static void build_model(const float *w, const float *mu, const float *isd, doubl
                 int k = 4 * (l / 16) + r, j = 16 * u + l % 16;
                 M.w.w1[u][l][r] = host_bf16(w[kOffW1 + k * kHid + j]);
             }
-    for (int kc = 0; kc < 4; ++kc)
+    // 16x16x32 steps: K slot r of lane l in step kc multiplies the hidden unit that the
+    // previous layer's output fragments leave there, 16 (2 kc + r / 4) + 4 (l / 16) + r % 4
+    for (int kc = 0; kc < 2; ++kc)
         for (int u = 0; u < 4; ++u)
             for (int l = 0; l < 64; ++l)
-                for (int r = 0; r < 4; ++r) {
-                    int k = 16 * kc + 4 * (l / 16) + r, j = 16 * u + l % 16;
+                for (int r = 0; r < 8; ++r) {
+                    int k = 16 * (2 * kc + r / 4) + 4 * (l / 16) + r % 4, j = 16 * u + l % 16;
                     M.w.w2[kc][u][l][r] = host_bf16(w[kOffW2 + k * kHid + j]);
                 }
-    for (int kc = 0; kc < 4; ++kc)
+    for (int kc = 0; kc < 2; ++kc)
         for (int l = 0; l < 64; ++l)
-            for (int r = 0; r < 4; ++r) {
-                int k = 16 * kc + 4 * (l / 16) + r, j = l % 16;
+            for (int r = 0; r < 8; ++r) {
+                int k = 16 * (2 * kc + r / 4) + 4 * (l / 16) + r % 4, j = l % 16;
                 M.w.w3[kc][l][r] = j < kCls ? host_bf16(w[kOffW3 + k * kCls + j]) : 0;
             }
     for (int j = 0; j < kHid; ++j) {
