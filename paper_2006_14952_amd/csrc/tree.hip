@@ -159,17 +159,18 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
     }
 }
 
-// 8 passes over the Morton key, then (batches) 1 or 2 passes over the box index, so the
-// order is by box, then by key; stable throughout.  Sets t->sorted to the result buffer.
-static int radix_sort(fmm_tree *t, int n, int nbox, hipStream_t st)
+// Passes over the Morton key's digits first_digit .. 7, then (batches) 1 or 2 passes over
+// the box index, so the order is by box, then by key; stable throughout.  Sorts the
+// buffer pair t->sorted holds (t->sorted = 0 after k_keys) and sets t->sorted to the result.
+static int radix_sort(fmm_tree *t, int n, int nbox, int first_digit, hipStream_t st)
 {
     int nb = (n + kRsTile - 1) / kRsTile;
     if (int rc = grow(t->nch, (size_t)256 * nb * 2 * sizeof(int))) return rc;
     int *hist = ptr<int>(t->nch), *offs = hist + 256 * nb;
     const int *boxoff = ptr<int>(t->boxoff);
     int npass = 8 + (nbox > 1) + (nbox > 256);
-    int cur = 0;
-    for (int pass = 0; pass < npass; ++pass) {
+    int cur = t->sorted;
+    for (int pass = first_digit; pass < npass; ++pass) {
         bool bpass = pass >= 8;
         int shift = bpass ? 8 * (pass - 8) : 8 * pass;
         const int *bo = bpass ? boxoff : nullptr;
@@ -411,12 +412,24 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     }
     int *bad = ptr<int>(t->flag);
     if ((rc = hip_check(hipMemsetAsync(bad, 0, sizeof(int), st), "tree flags"))) return rc;
+    // The sort starts at the key's third digit: bits 16 .. 62 order the particles exactly to
+    // level 15 (a level-l octant is decided by key bits 3 (21 - l) .. 3 (21 - l) + 2).  Only
+    // a tree that splits a level-15 cell needs the two lowest digits; the level loop then
+    // stops at level 16, and the arrays are sorted again over every digit (a full LSD sort
+    // of the partly sorted arrays) before the cells are built anew.
+    constexpr int kPartialDigit = 2, kPartialLevels = 16;
+    auto sort_gather = [&](int first_digit) -> int {
+        if (int r = radix_sort(t, n, nbox, first_digit, st)) return r;
+        k_gather<<<blocks(n, 256), 256, 0, st>>>(pos, mass, ptr<uint32_t>(t->idx[t->sorted]), n, P->box,
+                                                 ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
+                                                 ptr<double>(t->ms), ptr<int>(t->perm));
+        return hip_check(hipGetLastError(), "tree sort");
+    };
+    bool partial = n > 0;
     if (n > 0) {
+        t->sorted = 0;
         k_keys<<<blocks(n, 256), 256, 0, st>>>(pos, n, P->box, ptr<uint64_t>(t->keys[0]), ptr<uint32_t>(t->idx[0]), bad);
-        if ((rc = radix_sort(t, n, nbox, st))) return rc;
-        k_gather<<<blocks(n, 256), 256, 0, st>>>(pos, mass, ptr<uint32_t>(t->idx[t->sorted]), n, P->box, ptr<double>(t->xs),
-                                                 ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms),
-                                                 ptr<int>(t->perm));
+        if ((rc = sort_gather(kPartialDigit))) return rc;
     }
     if ((rc = hip_check(hipGetLastError(), "tree keys"))) return rc;
 
@@ -432,11 +445,13 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     }
     int *lv = bad + 8, *ovf = bad + 2;  // flag area: [0] non-finite, [1] scan total, [2] overflow, [8..] lv
     int *hl = t->host + kHostLevels;    // pinned mirror of lv
-    const uint64_t *keys = ptr<uint64_t>(t->keys[t->sorted]);
     const int nc_ = P->n_crit > 0 ? P->n_crit : 1;
+    int launched = 0;
+    for (;;) {  // once, or twice after a partial sort that does not reach deep enough
+    const uint64_t *keys = ptr<uint64_t>(t->keys[t->sorted]);
     int64_t cap64 = (nc_ >= 2 ? 8 * (int64_t)n / nc_ : 4 * (int64_t)n) + 64 * (int64_t)nbox + 1024;
     if (t->ncell > 0) cap64 = cap64 > (int64_t)t->ncell * 5 / 4 + 1024 ? cap64 : (int64_t)t->ncell * 5 / 4 + 1024;
-    int launched = 0;
+    const int lmax = partial ? kPartialLevels : kMaxLevel;
     for (int attempt = 0;; ++attempt) {
         if (cap64 > 0x7fffffff || attempt > 3) return set_error(FMM_ERR_NOMEM, "octree does not fit");
         const int cap = (int)cap64;
@@ -449,7 +464,7 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
         hl[1] = nbox;
         int64_t bound = nbox;  // the cells of level l are at most 8^l nbox (and cap)
         launched = 0;
-        for (int l = 0; l < kMaxLevel && n > 0; ++l) {
+        for (int l = 0; l < lmax && n > 0; ++l) {
             const int b = (int)bound, g = blocks(b, 256) < 4096 ? blocks(b, 256) : 4096;
             k_count_children_dev<<<g, 256, 0, st>>>(ptr<Cell>(t->cells), lv, l, P->n_crit, keys, nch, ovf);
             if ((rc = scan_exclusive_dn(nch, off, lv + l, lv + l + 1, b, bad + 1, st, t->scan_tmp))) return rc;
@@ -472,6 +487,13 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
         if (t->host[0]) return set_error(FMM_ERR_NAN, "non-finite particle position");
         if (!t->host[2]) break;
         cap64 *= 4;  // a level did not fit: rebuild with more room
+    }
+    if (partial && launched == kPartialLevels && hl[kPartialLevels + 1] > hl[kPartialLevels]) {
+        partial = false;  // a level-15 cell splits: sort over every digit and build again
+        if ((rc = sort_gather(0))) return rc;
+        continue;
+    }
+    break;
     }
     t->lvl_beg.assign(1, 0);
     for (int l = 0; l <= launched && hl[l + 1] > hl[l]; ++l) t->lvl_beg.push_back(hl[l + 1]);

@@ -309,6 +309,30 @@ def test_deep_chains_outgrow_the_first_cell_estimate():
     assert st["max_level"] >= 18
 
 
+@pytest.mark.parametrize("level", [14, 15, 16, 17])
+def test_tree_depth_around_the_partial_sort(level):
+    """The build sorts the Morton keys from their third 8-bit digit (key bits 16 and up,
+    which decide the octants of levels 1..15) and sorts again over every digit only when a
+    level-15 cell splits.  Twenty pairs of particles that share every cell down to level
+    `level` - 1 and part there, over 3000 uniform particles, put the deepest cells at
+    `level` with leaves of one particle: the tree and lists must match the oracle's on
+    both sides of that bound."""
+    rng = inputs.rng_for(131, level)
+    bg = rng.uniform(0.0, 1.0, (3000, 3))
+    h = 2.0 ** -(level - 1)
+    cell = rng.integers(0, 2 ** (level - 1), (20, 3)).astype(np.float64)
+    a = (cell + np.array([0.25, 0.5, 0.5])) * h
+    b = (cell + np.array([0.75, 0.5, 0.5])) * h
+    pos = np.concatenate([bg, a, b])
+    m = np.full(len(pos), 1.0 / len(pos))
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.5, p=2, n_crit=1)
+    check_fp64(pos, m, prm)
+    t = hf.Tree().build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+    st = t.stats()
+    t.free()
+    assert st["max_level"] == level
+
+
 @pytest.mark.parametrize("precision,schedule", [(0, 1), (0, 3), (1, 3)])
 def test_list_pool_overflow_reruns_the_traversal_and_p2p(precision, schedule):
     """Leaves of one particle and r_cut = 0.4 box: about 2000 P2P entries per leaf, 24M in
