@@ -208,11 +208,15 @@ template <class T> __device__ __forceinline__ void pair_sep(const Cell &ca, cons
 
 __device__ __forceinline__ double cell_h(const Cell &c, double box) { return ldexp(box, -cell_level(c)); }
 
+// One thread per leaf.  The FP32 form reads each particle's leaf-relative FP32 record
+// (x - c, m), one 16-byte load, instead of four FP64 arrays: the same values (the FP64
+// difference rounded to FP32, then scaled by the power of two 1/h for a box of power-of-two
+// size), a quarter of the loads and half the bytes.
 template <int P, class T>
 __global__ __launch_bounds__(64) void k_p2m(const Cell *__restrict__ cells, const int *__restrict__ leaves, int nleaf,
                                             const double *__restrict__ xs, const double *__restrict__ ys,
-                                            const double *__restrict__ zs, const double *__restrict__ ms, double box,
-                                            T *__restrict__ M)
+                                            const double *__restrict__ zs, const double *__restrict__ ms,
+                                            const float4 *__restrict__ rel, double box, T *__restrict__ M)
 {
     constexpr int NC = Tab<P>::NC;
     constexpr Tab<P> tb{};
@@ -227,7 +231,13 @@ __global__ __launch_bounds__(64) void k_p2m(const Cell *__restrict__ cells, cons
     for (int k = 0; k < NC; ++k) acc[k] = 0;
     for (int i = cc.beg; i < cc.end; ++i) {
         T mono[NC];
-        monomials<P, T>((T)((xs[i] - cx) * ih), (T)((ys[i] - cy) * ih), (T)((zs[i] - cz) * ih), (T)ms[i], mono);
+        if constexpr (sizeof(T) == 4) {
+            const float4 r = rel[i];
+            const T s = (T)ih;
+            monomials<P, T>(r.x * s, r.y * s, r.z * s, r.w, mono);
+        } else {
+            monomials<P, T>((T)((xs[i] - cx) * ih), (T)((ys[i] - cy) * ih), (T)((zs[i] - cz) * ih), (T)ms[i], mono);
+        }
 #pragma unroll
         for (int k = 0; k < NC; ++k) acc[k] += mono[k];
     }
@@ -845,7 +855,7 @@ template <int P, class T> struct Upward {
             return rc;
         k_p2m<P, T><<<nblk(t->nleaf, 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaves), t->nleaf,
                                                        ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
-                                                       ptr<double>(t->ms), t->box, ptr<T>(t->Mc));
+                                                       ptr<double>(t->ms), ptr<float4>(t->rel32), t->box, ptr<T>(t->Mc));
         for (int l = t->nlevel - 2; l >= 0; --l) {
             int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
             if constexpr (P >= 7)
