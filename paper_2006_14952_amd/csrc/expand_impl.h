@@ -247,14 +247,15 @@ __global__ __launch_bounds__(64) void k_p2m(const Cell *__restrict__ cells, cons
 }
 
 template <int P, class T>
-__global__ __launch_bounds__(64) void k_m2m(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ M)
+__global__ __launch_bounds__(64) void k_m2m(const Cell *__restrict__ cells, const int *__restrict__ inner, int lbeg,
+                                            int ln, T *__restrict__ M)
 {
     constexpr int NC = Tab<P>::NC;
     constexpr Tab<P> tb{};
     constexpr SubTab<P> st{};
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ln) return;
-    int c = lbeg + t;
+    int c = inner[lbeg + t];
     Cell cc = cells[c];
     int nch = cell_nchild(cc);
     if (nch == 0) return;
@@ -474,13 +475,14 @@ template <int P, class T> __device__ __forceinline__ void shift_weights(T h, boo
 // M2M for the parents of one level, a thread per parent: each child's multipole is
 // shifted in registers (x-hat = +-1/2 in child units) and added to the parent.
 template <int P, class T>
-__global__ __launch_bounds__(64) void k_m2m_axis(const Cell *__restrict__ cells, int lbeg, int ln, T *__restrict__ M)
+__global__ __launch_bounds__(64) void k_m2m_axis(const Cell *__restrict__ cells, const int *__restrict__ inner, int lbeg,
+                                                 int ln, T *__restrict__ M)
 {
     constexpr int NC = ncoef(P);
     constexpr Tab<P> tb{};
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ln) return;
-    const int c = lbeg + t;
+    const int c = inner[lbeg + t];
     const Cell cc = cells[c];
     const int nch = cell_nchild(cc);
     if (nch == 0) return;
@@ -856,12 +858,18 @@ template <int P, class T> struct Upward {
         k_p2m<P, T><<<nblk(t->nleaf, 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaves), t->nleaf,
                                                        ptr<double>(t->xs), ptr<double>(t->ys), ptr<double>(t->zs),
                                                        ptr<double>(t->ms), ptr<float4>(t->rel32), t->box, ptr<T>(t->Mc));
+        // M2M over the cells with children only, level by level (inner[] holds them in cell
+        // order; those of level l follow the lvl_beg[l] - leaf_lvl[l] before it): at 134M
+        // seven cells in eight are leaves, whose threads would idle
         for (int l = t->nlevel - 2; l >= 0; --l) {
-            int lb = t->lvl_beg[l], ln = t->lvl_beg[l + 1] - lb;
+            const int lb = t->lvl_beg[l] - t->leaf_lvl[l], ln = t->lvl_beg[l + 1] - t->leaf_lvl[l + 1] - lb;
+            if (ln <= 0) continue;
             if constexpr (P >= 7)
-                k_m2m_axis<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+                k_m2m_axis<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->inner), lb, ln,
+                                                               ptr<T>(t->Mc));
             else
-                k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), lb, ln, ptr<T>(t->Mc));
+                k_m2m<P, T><<<nblk(ln, 64), 64, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->inner), lb, ln,
+                                                          ptr<T>(t->Mc));
         }
         return hip_check(hipGetLastError(), "upward pass");
     }

@@ -39,6 +39,7 @@ struct fmm_tree {
     // cells
     hfmm::DevBuf cells;           // Cell[ncell]
     hfmm::DevBuf leaves;          // int[nleaf]
+    hfmm::DevBuf inner;           // int[ncell - nleaf]: the cells with children, level by level
     hfmm::DevBuf Mc, Lc;          // expansion coefficients, ncell x ncoef(p) (float or double)
 
     // interaction lists: per cell and list kind (hfmm::kKinds), a chain of 64-entry chunks;

@@ -357,11 +357,18 @@ __global__ void k_leaf_levels(const int *__restrict__ off, int ncell, const int 
     if (l <= lb.n) out[l] = lb.b[l] < ncell ? off[lb.b[l]] : *total;
 }
 
+// Leaves and the cells with children, each in cell order (so level by level): a cell with
+// children is number c - off[c] among them.
 __global__ void k_leaf_compact(const Cell *__restrict__ cells, int ncell, const int *__restrict__ flag,
-                               const int *__restrict__ off, int *__restrict__ leaves, int *__restrict__ leaf_of)
+                               const int *__restrict__ off, int *__restrict__ leaves, int *__restrict__ inner,
+                               int *__restrict__ leaf_of)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell || !flag[c]) return;
+    if (c >= ncell) return;
+    if (!flag[c]) {
+        inner[c - off[c]] = c;
+        return;
+    }
     leaves[off[c]] = c;
     Cell cc = cells[c];
     for (int i = cc.beg; i < cc.end; ++i) leaf_of[i] = c;
@@ -532,9 +539,9 @@ int tree_build(fmm_tree *t, const fmm_params *P, int64_t n64, const double *pos,
     if ((rc = hip_check(hipStreamSynchronize(st), "leaf count"))) return rc;
     t->nleaf = t->host[0];
     t->leaf_lvl.assign(t->host + 32, t->host + 32 + t->nlevel + 1);
-    if ((rc = grow(t->leaves, (size_t)t->nleaf * 4 + 4))) return rc;
+    if ((rc = grow(t->leaves, (size_t)t->nleaf * 4 + 4) | grow(t->inner, (size_t)(t->ncell - t->nleaf) * 4 + 4))) return rc;
     k_leaf_compact<<<blocks(t->ncell, 256), 256, 0, st>>>(ptr<Cell>(t->cells), t->ncell, flag, off, ptr<int>(t->leaves),
-                                                          ptr<int>(t->leaf_of));
+                                                          ptr<int>(t->inner), ptr<int>(t->leaf_of));
     k_rel32<<<blocks(n, 256), 256, 0, st>>>(ptr<Cell>(t->cells), ptr<int>(t->leaf_of), ptr<double>(t->xs),
                                             ptr<double>(t->ys), ptr<double>(t->zs), ptr<double>(t->ms), n, P->box,
                                             ptr<float4>(t->rel32));
