@@ -103,6 +103,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t *__restri
     hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Scatter of one tile: the keys are ranked by digit in registers (ballots, as before),
+// placed in LDS in the tile's digit order, and written from there by consecutive threads, so
+// each digit's run of the tile goes out as consecutive addresses (whole cache lines) rather
+// than as one scattered 8-byte store per key.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__restrict__ kin,
                                                            const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
                                                            uint32_t *__restrict__ vout, int n, int shift,
@@ -111,6 +115,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
 {
     __shared__ int cnt[4][256];
     __shared__ int boff[256];
+    __shared__ int dstart[256];  // first slot of each digit in the tile ordered by digit
+    __shared__ int wsum[4];
+    __shared__ uint64_t skey[kRsTile];
+    __shared__ uint32_t sval[kRsTile];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int k = threadIdx.x; k < 4 * 256; k += kRsThreads) (&cnt[0][0])[k] = 0;
     boff[threadIdx.x] = offs[threadIdx.x * nblocks + blockIdx.x];
@@ -139,23 +147,40 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t *__res
         pos[r] = ok ? old + rank : -1;
     }
     __syncthreads();
-    {  // per-digit prefix over the four waves
-        int d = threadIdx.x, run = 0;
+    {  // per-digit prefix over the four waves, then over the digits (a block-wide scan)
+        const int d = threadIdx.x;
+        int run = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int c = cnt[q][d];
             cnt[q][d] = run;
             run += c;
         }
+        const int incl = wave_incl_sum(run);
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        int add = 0;
+        for (int q = 0; q < w; ++q) add += wsum[q];
+        dstart[d] = add + incl - run;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kRsRounds; ++r) {
         if (pos[r] < 0) continue;
-        int d = rs_digit(key[r], val[r], shift, boxoff, nbox);
-        int o = boff[d] + cnt[w][d] + pos[r];
-        kout[o] = key[r];
-        vout[o] = val[r];
+        const int d = rs_digit(key[r], val[r], shift, boxoff, nbox);
+        const int l = dstart[d] + cnt[w][d] + pos[r];
+        skey[l] = key[r];
+        sval[l] = val[r];
+    }
+    __syncthreads();
+    const int ntile = min(kRsTile, n - blockIdx.x * kRsTile);
+    for (int j = threadIdx.x; j < ntile; j += kRsThreads) {
+        const uint64_t k = skey[j];
+        const uint32_t v = sval[j];
+        const int d = rs_digit(k, v, shift, boxoff, nbox);
+        const int o = boff[d] + j - dstart[d];
+        kout[o] = k;
+        vout[o] = v;
     }
 }
 
