@@ -47,16 +47,16 @@ P2P_FLOP_PER_PAIR = {0: 38.0, 1: 30.0}
 # autotuner chooses from before timing (the default); kernels: the batched line also tunes
 # the schedule and the M2L kernel.
 WORKLOADS = {
-    "full": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96, 128), learned=True, cpu_cubes=0.0025,
+    "full": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96, 128), learned=True, cpu_cubes=0.0075,
                  cpu_cubes_1t=0.0001),
-    "large": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96), learned=False, cpu_cubes=0.01,
-                  cpu_cubes_1t=0.0005),
-    "clustered": dict(theta=0.42, precision=1, n_crit=48, tune=(32, 48, 64), learned=False, cpu_cubes=0.05,
-                      cpu_cubes_1t=0.005),
+    "large": dict(theta=0.5, precision=1, n_crit=64, tune=(48, 64, 96), learned=False, cpu_cubes=0.05,
+                  cpu_cubes_1t=0.003),
+    "clustered": dict(theta=0.42, precision=1, n_crit=48, tune=(32, 48, 64), learned=False, cpu_cubes=0.4,
+                      cpu_cubes_1t=0.04),
     "uniform": dict(theta=0.5, precision=0, n_crit=32, tune=(16, 32, 64), learned=False, cpu_cubes=1.0,
-                    cpu_cubes_1t=0.05),
-    "batched": dict(theta=0.4, precision=1, n_crit=48, tune=(32, 48, 64), kernels=True, learned=False, cpu_cubes=0.1,
-                    cpu_cubes_1t=0.01),
+                    cpu_cubes_1t=1.0),
+    "batched": dict(theta=0.4, precision=1, n_crit=48, tune=(32, 48, 64), kernels=True, learned=False, cpu_cubes=1.0,
+                    cpu_cubes_1t=0.15),
 }
 M2L_KERNELS = {0: "library's choice (vector ALUs)", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}
 SCHEDULES = {0: "library's choice", 1: "two streams, P2P after the traversal", 2: "one persistent P2P + M2L kernel",
