@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 3),
                     help="P2P and M2L: 0 library's choice, 1 two kernels on two streams, 2 one persistent kernel, "
                          "3 as 1 with P2P per leaf level during the traversal")
+    ap.add_argument("--deterministic", type=int, default=0, choices=(0, 1),
+                    help="1: every sum in a fixed order (bit-identical repeated runs; slower M2L)")
     ap.add_argument("--split", type=int, default=0, choices=(0, 1),
                     help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
@@ -169,7 +171,7 @@ def main():
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
                     precision=wl["precision"], learned=int(wl["learned"]), split=args.split, m2l_mfma=args.m2l_mfma,
-                    schedule=args.schedule)
+                    schedule=args.schedule, deterministic=args.deterministic)
     sel = None
     if wl["learned"]:
         from paper_2006_14952_amd import learned
@@ -244,7 +246,8 @@ def main():
             + "; step = octree build + short-range forces (PM timed separately)",
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
             "split": args.split, "selector": sel or "fixed p and theta", "autotuned_ms": tuned,
-            "m2l_kernel": M2L_KERNELS[prm.m2l_mfma], "schedule": SCHEDULES[prm.schedule]},
+            "m2l_kernel": M2L_KERNELS[prm.m2l_mfma], "schedule": SCHEDULES[prm.schedule],
+            "sums": "fixed order (deterministic)" if prm.deterministic else "atomics (fastest)"},
         "timing": {"statistic": "median of per-step HIP-event times", "ms_steps": ms,
                    "ms_per_step_mean_wall": wall * 1e3, "input_generation_s": t_gen},
         "roofline": p2p_roofline(st, stage["t_p2p_ms"], wl, args.workload, pr, n, args.split,
@@ -278,7 +281,7 @@ def main():
     if wl["learned"] and args.plain_steps > 0:
         pp = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
                        precision=wl["precision"], learned=0, split=args.split, m2l_mfma=args.m2l_mfma,
-                       schedule=args.schedule)
+                       schedule=args.schedule, deterministic=args.deterministic)
         log("plain fixed-order form, %d steps" % args.plain_steps)
         pms_, pwall, pstats = timed(pp, 1, args.plain_steps)
         plain_got = acc.cpu().numpy()

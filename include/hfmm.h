@@ -86,7 +86,15 @@ extern "C" {
  *             learned 0, 3 <= p <= 8, m2l_mfma != 2 and, with split 0, a force law of
  *             degree 9 or 10 (r_cut / r_s up to about 5.1); FMM_ERR_ARG otherwise.  The results do
  *             not depend on the schedule beyond FP32 summation order.
- *   reserved  must be 0. */
+ *   deterministic  0: the fastest kernels, whose floating-point sums over the M2L pairs of
+ *             a sink (and the PM mass deposit) are combined by atomics, so two runs agree
+ *             only to rounding (about 1e-11 relative in FP64, 1e-5 in FP32); 1: every sum
+ *             in a fixed order, so repeated runs on the same input give bit-identical
+ *             accelerations: M2L by one thread per sink over its list in list order, the
+ *             PM deposit in 64-bit fixed point (scaled by the total |mass|, exact integer
+ *             sums, rounding below 1e-15 of the total mass per particle).  Slower (the M2L
+ *             stage several times); schedule 2 and m2l_mfma 2 are refused with it
+ *             (FMM_ERR_ARG).  0 or 1. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
@@ -97,7 +105,7 @@ typedef struct fmm_params {
     int pm_assign;
     int m2l_mfma;
     int schedule;
-    int reserved;
+    int deterministic;
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts

@@ -44,7 +44,11 @@ static int check_params(const fmm_params *P)
         return set_error(FMM_ERR_ARG, "pm_assign must be 0, 2 (CIC), 3 (TSC) or 4 (PCS)");
     if (P->m2l_mfma < 0 || P->m2l_mfma > 2) return set_error(FMM_ERR_ARG, "m2l_mfma must be 0, 1 or 2");
     if (P->schedule < 0 || P->schedule > 3) return set_error(FMM_ERR_ARG, "schedule must be 0, 1, 2 or 3");
-    if (P->reserved != 0) return set_error(FMM_ERR_ARG, "reserved must be 0");
+    if (P->deterministic != 0 && P->deterministic != 1) return set_error(FMM_ERR_ARG, "deterministic must be 0 or 1");
+    if (P->deterministic && P->schedule == 2)
+        return set_error(FMM_ERR_ARG, "deterministic mode has no persistent P2P + M2L kernel (schedule 2)");
+    if (P->deterministic && P->m2l_mfma == 2)
+        return set_error(FMM_ERR_ARG, "deterministic mode has no matrix-core M2L (m2l_mfma 2)");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;
@@ -232,7 +236,8 @@ static bool same_params(const fmm_params &a, const fmm_params &b)
 {
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
            a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
-           a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma && a.schedule == b.schedule;
+           a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma && a.schedule == b.schedule &&
+           a.deterministic == b.deterministic;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,

@@ -5,7 +5,7 @@
 namespace hfmm {
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st);
 template <class T>
-int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st);
+int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, int det, hipStream_t st);
 
 static Split split_of(const fmm_params *P) { return Split{P->split ? P->r_cut : P->r_s, P->split}; }
 static int flatten_learned(fmm_tree *t, hipStream_t st);
@@ -21,10 +21,12 @@ int upward(fmm_tree *t, const fmm_params *P, hipStream_t st)
 // ALUs, 0 = the library's choice (the vector ALUs).
 static int use_mfma(const fmm_params *P) { return P->m2l_mfma == 2; }
 
+// deterministic mode: the thread-per-sink kernel, which sums each sink's pairs in list
+// order in registers (no atomics)
 int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
-    return P->precision ? m2l_t<float>(t, P->p, split_of(P), 0, P->p, 0, use_mfma(P), st)
-                        : m2l_t<double>(t, P->p, split_of(P), 0, P->p, 0, 0, st);
+    return P->precision ? m2l_t<float>(t, P->p, split_of(P), 0, P->p, 0, use_mfma(P), P->deterministic, st)
+                        : m2l_t<double>(t, P->p, split_of(P), 0, P->p, 0, 0, P->deterministic, st);
 }
 
 // Learned selector: coefficients stored at order 8; the pairs accepted at order o are
@@ -32,10 +34,11 @@ int m2l(fmm_tree *t, const fmm_params *P, hipStream_t st)
 int m2l_learned(fmm_tree *t, const fmm_params *P, hipStream_t st)
 {
     if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(8) * (P->precision ? 4 : 8), st)) return rc;
-    if (int rc = flatten_learned(t, st)) return rc;
+    if (!P->deterministic)
+        if (int rc = flatten_learned(t, st)) return rc;
     for (int o = 2; o <= 8; ++o) {
-        int rc = P->precision ? m2l_t<float>(t, o, split_of(P), 1, 8, 1, 0, st)
-                              : m2l_t<double>(t, o, split_of(P), 1, 8, 1, 0, st);
+        int rc = P->precision ? m2l_t<float>(t, o, split_of(P), 1, 8, 1, 0, P->deterministic, st)
+                              : m2l_t<double>(t, o, split_of(P), 1, 8, 1, 0, P->deterministic, st);
         if (rc) return rc;
     }
     return 0;

@@ -3,7 +3,7 @@
 
 namespace hfmm {
 template int upward_t<float>(fmm_tree *, int, hipStream_t);
-template int m2l_t<float>(fmm_tree *, int, Split, int, int, int, int, hipStream_t);
+template int m2l_t<float>(fmm_tree *, int, Split, int, int, int, int, int, hipStream_t);
 template int l2l_t<float>(fmm_tree *, int, hipStream_t);
 template int l2p_t<float>(fmm_tree *, int, double, double *, int, hipStream_t);
 }  // namespace hfmm

@@ -881,10 +881,11 @@ template <int P, class T> struct M2L {
     // flatten_learned has already laid out by order (the pair kernel adds to L).
     // mfma != 0 (FP32, orders 4..8, plain list): pairs of cells on one level on the matrix
     // cores (m2l_mfma.hip), the others by the lane-per-pair kernel below.
-    static int run(fmm_tree *t, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st)
+    // det != 0: the thread-per-sink kernel below for every order (a fixed summation order).
+    static int run(fmm_tree *t, Split sp, int learned, int pstore, int accumulate, int mfma, int det, hipStream_t st)
     {
         const int kind = learned ? kKindOrd : 0;
-        if constexpr (pair_m2l<P, T>()) {
+        if constexpr (pair_m2l<P, T>()) if (!det) {
             const int64_t np = learned ? t->stats.n_m2l_by_order[P - 2] : t->n_m2l;
             if (!accumulate)
                 if (int rc = zero_async(t->Lc.p, (size_t)t->ncell * ncoef(pstore) * sizeof(T), st)) return rc;
@@ -943,9 +944,9 @@ template <int P, class T> struct L2P {
 
 template <class T> int upward_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<Upward, T>(p, t, st); }
 template <class T>
-int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, hipStream_t st)
+int m2l_t(fmm_tree *t, int p, Split sp, int learned, int pstore, int accumulate, int mfma, int det, hipStream_t st)
 {
-    return dispatch_p<M2L, T>(p, t, sp, learned, pstore, accumulate, mfma, st);
+    return dispatch_p<M2L, T>(p, t, sp, learned, pstore, accumulate, mfma, det, st);
 }
 template <class T> int l2l_t(fmm_tree *t, int p, hipStream_t st) { return dispatch_p<L2L, T>(p, t, st); }
 template <class T> int l2p_t(fmm_tree *t, int p, double G, double *acc, int accumulate, hipStream_t st)

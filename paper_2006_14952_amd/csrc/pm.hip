@@ -125,6 +125,67 @@ __global__ void k_deposit(S src, int n, double box, int M, double inv_vol, doubl
             }
 }
 
+// Deterministic deposit (fmm_params.deterministic): every contribution m w / d^3 is rounded
+// to an integer multiple of 2^-e and summed in 64-bit integers, whose sums do not depend on
+// the order of the atomics.  e is the largest exponent with n max|m| / d^3 2^e < 2^62, so no
+// partial sum overflows; a contribution's rounding is at most 2^-(e+1), below 1e-15 of the
+// total |mass| / d^3 for any n up to 2^30.
+template <class S> __global__ __launch_bounds__(256) void k_mass_absmax(S src, int n, unsigned long long *mx)
+{
+    __shared__ unsigned long long w[256];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // |m| >= 0: the order of the bit patterns is the order of the values
+    w[threadIdx.x] = p < n ? (unsigned long long)__double_as_longlong(fabs(src.m(p))) : 0ull;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) w[threadIdx.x] = max(w[threadIdx.x], w[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && w[0]) atomicMax(mx, w[0]);
+}
+
+__device__ __forceinline__ int fixed_exponent(const unsigned long long *mx, int n, double inv_vol)
+{
+    const double bound = (double)n * __longlong_as_double((long long)*mx) * inv_vol;
+    return bound > 0.0 ? 61 - ilogb(bound) : 0;
+}
+
+template <class S, int ORDER>
+__global__ void k_deposit_fixed(S src, int n, double box, int M, double inv_vol, const unsigned long long *__restrict__ mx,
+                                unsigned long long *__restrict__ rho)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int e = fixed_exponent(mx, n, inv_vol);
+    double inv_d = M / box;
+    int i[3];
+    double w[3][ORDER];
+    for (int a = 0; a < 3; ++a) {
+        double x = src.x(p, a);
+        x -= box * floor(x / box);
+        assign_weights<ORDER>(x, inv_d, M, i[a], w[a]);
+    }
+    double m = src.m(p) * inv_vol;
+    for (int dx = 0; dx < ORDER; ++dx)
+        for (int dy = 0; dy < ORDER; ++dy)
+            for (int dz = 0; dz < ORDER; ++dz) {
+                size_t idx = ((size_t)((i[0] + dx) % M) * M + (i[1] + dy) % M) * M + (i[2] + dz) % M;
+                const long long q = llrint(ldexp(m * w[0][dx] * w[1][dy] * w[2][dz], e));
+                atomicAdd(&rho[idx], (unsigned long long)q);
+            }
+}
+
+// The integer mesh back to FP64, in place.
+__global__ void k_fixed_to_double(unsigned long long *__restrict__ rho, size_t nr, const unsigned long long *__restrict__ mx,
+                                  int n, double inv_vol)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    const int e = fixed_exponent(mx, n, inv_vol);
+    const double v = ldexp((double)(long long)rho[i], -e);
+    reinterpret_cast<double *>(rho)[i] = v;
+}
+
 __device__ __forceinline__ double sinc(double x) { return fabs(x) < 1e-8 ? 1.0 : sin(x) / x; }
 
 // long-range filter at |k|^2 = k2: Gaussian split exp(-k^2 r_s^2); polynomial split the
@@ -227,9 +288,23 @@ static int pm_run(const fmm_params *P, int mesh, int n, S src, const double *pos
     double d = P->box / mesh;
     const int order = P->pm_assign == 0 ? 2 : P->pm_assign;
     const unsigned nb = (unsigned)((n + 255) / 256);
-    if (order == 3) k_deposit<S, 3><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
-    else if (order == 4) k_deposit<S, 4><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
-    else k_deposit<S, 2><<<nb, 256, 0, st>>>(src, n, P->box, mesh, 1.0 / (d * d * d), ptr<double>(pl->rho));
+    const double inv_vol = 1.0 / (d * d * d);
+    if (P->deterministic) {
+        unsigned long long *mx = ptr<unsigned long long>(pl->amesh);  // the output mesh is not yet in use
+        unsigned long long *irho = ptr<unsigned long long>(pl->rho);
+        if (int rc = hip_check(hipMemsetAsync(mx, 0, 8, st), "pm mass bound")) return rc;
+        k_mass_absmax<S><<<nb, 256, 0, st>>>(src, n, mx);
+        if (order == 3) k_deposit_fixed<S, 3><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, mx, irho);
+        else if (order == 4) k_deposit_fixed<S, 4><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, mx, irho);
+        else k_deposit_fixed<S, 2><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, mx, irho);
+        k_fixed_to_double<<<(unsigned)((nr + 255) / 256), 256, 0, st>>>(irho, nr, mx, n, inv_vol);
+    } else if (order == 3) {
+        k_deposit<S, 3><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, ptr<double>(pl->rho));
+    } else if (order == 4) {
+        k_deposit<S, 4><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, ptr<double>(pl->rho));
+    } else {
+        k_deposit<S, 2><<<nb, 256, 0, st>>>(src, n, P->box, mesh, inv_vol, ptr<double>(pl->rho));
+    }
     if (hipfftSetStream(pl->r2c, st) != HIPFFT_SUCCESS || hipfftSetStream(pl->c2r, st) != HIPFFT_SUCCESS)
         return set_error(FMM_ERR_HIP, "hipfftSetStream");
     if (hipfftExecD2Z(pl->r2c, ptr<double>(pl->rho), ptr<hipfftDoubleComplex>(pl->rhok)) != HIPFFT_SUCCESS)

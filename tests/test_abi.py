@@ -70,11 +70,28 @@ def test_autotune_and_hybrid_tree_reject_bad_arguments_without_gpu():
     assert L.fmm_short_range_forces_graph(fake, C.byref(prm), fake, fake) == hf.FMM_ERR_ARG
 
 
-def test_reserved_field_must_be_zero():
-    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32)
-    prm.reserved = 1
+def test_deterministic_field_validated():
+    """deterministic is 0 or 1, and refuses the kernels that combine sums with atomics in
+    an order of their own (the persistent P2P + M2L kernel, the matrix-core M2L)."""
+    L = hf.lib()
     h = C.c_void_p()
-    assert hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h)) == hf.FMM_ERR_ARG
+    for kw in (dict(deterministic=2), dict(deterministic=-1), dict(deterministic=1, precision=1, p=5, schedule=2),
+               dict(deterministic=1, precision=1, p=6, m2l_mfma=2)):
+        prm = hf.params(box=1.0, r_s=0.04, theta=0.5, n_crit=32, **{"p": 4, **kw})
+        assert L.fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h)) == hf.FMM_ERR_ARG, kw
+        assert b"deterministic" in L.fmm_last_error(), kw
+    # accepted sets pass validation (checked before the particle arguments: n = 0 then fails
+    # on the arguments alone, with no GPU call)
+    best = C.c_int()
+    for kw in (dict(), dict(precision=1, p=6, schedule=3), dict(precision=1, p=8, m2l_mfma=1)):
+        prm = hf.params(box=1.0, r_s=0.04, theta=0.5, n_crit=32, deterministic=1, **{"p": 4, **kw})
+        arr = (hf.Params * 1)(prm)
+        assert L.fmm_autotune_params(arr, 1, 1, None, 0, None, None, None, 1, None, C.byref(best), None) == \
+            hf.FMM_ERR_ARG
+        assert L.fmm_last_error() == b"bad arguments", kw
+    # the autotuner's candidate sets keep to the deterministic kernels
+    cands = hf.kernel_candidates(hf.params(p=6, precision=1, deterministic=1), n_crits=(32,))
+    assert {(c.schedule, c.m2l_mfma) for c in cands} == {(1, 0), (3, 0)}
 
 
 def test_persistent_schedule_accepted_where_it_applies():
