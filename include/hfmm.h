@@ -139,8 +139,8 @@ typedef struct fmm_tree fmm_tree; /* opaque; owned by the library */
  * is reused (its device memory only grows).  Uses params->box and params->n_crit.
  * Synchronises the stream (level sizes are read back).  n = 0 is allowed, n <= 2^30.
  * A tree of 2^27 cells or more is rejected with FMM_ERR_ARG (interaction-list entries
- * address cells with 27 bits; a larger n_crit gives fewer cells); the tree passed in
- * *out is then left empty. */
+ * address cells with 27 bits; a larger n_crit gives fewer cells).  On any failure a
+ * tree passed in *out is left empty (0 particles) and must be rebuilt before use. */
 int fmm_build_tree(const fmm_params *params, int64_t n, const double *pos, const double *mass, void *stream,
                    fmm_tree **out);
 
@@ -324,6 +324,18 @@ int fmm_mlp_grad_noalloc(const float *params, const float *mu, const float *isd,
  * the moment updates (as torch.optim.Adam's weight_decay), not a decoupled (AdamW) decay. */
 int fmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, float beta1,
                  float beta2, float eps, float weight_decay, void *stream);
+
+/* Bound on the device memory the library's own buffers may hold, process-wide: trees and
+ * their lists, forests, PM meshes, training scratch (not the caller's arrays, the FFT plans'
+ * work areas or the selector model).  0, the default, is no bound.  The buffers are kept
+ * for reuse and freed only with their tree (PM meshes at exit), so the bound applies to
+ * what they hold together.  A call that would grow a buffer past it fails with
+ * FMM_ERR_NOMEM before allocating, as a failed device allocation does; a tree whose build
+ * fails that way is left empty (rebuild it or free it).  Always returns 0. */
+int fmm_set_memory_limit(uint64_t bytes);
+
+/* Bytes the library's device buffers hold now (*bytes); FMM_ERR_ARG if bytes is NULL. */
+int fmm_get_memory_use(uint64_t *bytes);
 
 void fmm_free_tree(fmm_tree *tree);
 

@@ -89,6 +89,8 @@ def lib():
         L.fmm_mlp_grad.argtypes = [fp, fp, fp, fp, fp, fp, C.c_int, fp, fp, vp]
         L.fmm_mlp_grad_noalloc.argtypes = [fp, fp, fp, fp, fp, fp, C.c_int, fp, fp, vp]
         L.fmm_mlp_adam.argtypes = [fp, fp, fp, fp, i64, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+        L.fmm_set_memory_limit.argtypes = [C.c_uint64]
+        L.fmm_get_memory_use.argtypes = [C.POINTER(C.c_uint64)]
         L.fmm_free_tree.argtypes = [vp]
         L.fmm_free_tree.restype = None
         L.fmm_last_error.restype = C.c_char_p
@@ -338,6 +340,17 @@ def short_range_batched(pos, mass, per_box, offsets, out=None, stream=None):
     _check(lib().fmm_short_range_forces_batched(arr, nb, off, _dev64(pos, (3,)), _dev64(mass), _dev64(out, (3,)),
                                                 _stream(stream)))
     return out
+
+
+def set_memory_limit(nbytes):
+    """Bound on the device memory the library's buffers hold (0: none); see fmm_set_memory_limit."""
+    _check(lib().fmm_set_memory_limit(int(nbytes)))
+
+
+def memory_in_use():
+    v = C.c_uint64()
+    _check(lib().fmm_get_memory_use(C.byref(v)))
+    return int(v.value)
 
 
 def load_mac_model(path):

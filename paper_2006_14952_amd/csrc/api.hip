@@ -59,12 +59,7 @@ static int check_params(const fmm_params *P)
     return 0;
 }
 
-static void free_buf(DevBuf &b)
-{
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-}
+static void free_buf(DevBuf &b) { release(b); }
 
 static float ev_ms(fmm_tree *t, int a, int b)
 {
@@ -255,7 +250,15 @@ static int build_common(const fmm_params *P, int64_t n, const double *pos, const
     ++t->build_serial;  // buffers may move: a recorded evaluation of the old tree is void
     int rc = tree_build(t, P, n, pos, mass, nbox, offsets, st);
     if (rc) {
-        if (fresh) fmm_free_tree(t);
+        if (fresh) {
+            fmm_free_tree(t);
+        } else {  // a reused tree that failed part way (e.g. out of memory) is left empty
+            t->n = 0;
+            t->ncell = t->nleaf = t->nlevel = 0;
+            t->lvl_beg.assign(1, 0);
+            t->leaf_lvl.assign(1, 0);
+            t->stats.n = t->stats.n_cells = t->stats.n_leaves = t->stats.max_level = 0;
+        }
         return rc;
     }
     if (t->timing) {
@@ -571,8 +574,8 @@ int fmm_mac_training_data(fmm_tree *t, const fmm_params *P, double theta_max, co
         rc = hip_check(hipMemcpyAsync(&n, ctr.p, 4, hipMemcpyDeviceToHost, st), "training data");
         if (!rc) rc = hip_check(hipStreamSynchronize(st), "training data");
     }
-    if (aref.p) (void)hipFree(aref.p);
-    if (ctr.p) (void)hipFree(ctr.p);
+    release(aref);
+    release(ctr);
     *count = n < cap ? n : cap;
     return rc;
 }
@@ -630,11 +633,24 @@ int fmm_short_range_forces_batched(const fmm_params *per_box, int nbox, const in
     return run_forces(forest, &per_box[0], acc, (hipStream_t)stream);
 }
 
+int fmm_set_memory_limit(uint64_t bytes)
+{
+    set_memory_limit(bytes);
+    return 0;
+}
+
+int fmm_get_memory_use(uint64_t *bytes)
+{
+    if (!bytes) return set_error(FMM_ERR_ARG, "bytes is NULL");
+    *bytes = memory_in_use();
+    return 0;
+}
+
 void fmm_free_tree(fmm_tree *t)
 {
     if (!t) return;
     DevBuf *bufs[] = {&t->keys[0], &t->keys[1], &t->idx[0], &t->idx[1], &t->xs, &t->ys, &t->zs, &t->ms, &t->perm,
-                      &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->Mc, &t->Lc, &t->lhead,
+                      &t->leaf_of, &t->rel32, &t->nearf, &t->cells, &t->leaves, &t->inner, &t->Mc, &t->Lc, &t->lhead,
                       &t->lcnt, &t->tstack, &t->counters, &t->scan_tmp, &t->nch, &t->flag, &t->boxoff,
                       &t->m2l_ctr, &t->m2l_pairs, &t->bbox, &t->wstate, &t->cfeat, &t->cellc, &t->mf_ne,
                       &t->mf_no, &t->mf_offe, &t->mf_offn, &t->mf_spos, &t->mf_sinks, &t->mf_csr, &t->mf_tot};

@@ -92,7 +92,10 @@ struct DevBuf {
 };
 
 int grow(DevBuf &b, size_t bytes);                    // 0 or FMM_ERR_NOMEM; content is lost
+void release(DevBuf &b);                              // frees b (if held) and empties it
 uint64_t buffer_moves();  // reallocations by grow() so far (process-wide): recorded graphs check it
+void set_memory_limit(uint64_t bytes);  // bound on the bytes all DevBufs hold (0: none); grow() refuses beyond it
+uint64_t memory_in_use();               // bytes all DevBufs hold now
 int grow_keep(DevBuf &b, size_t bytes, size_t used);  // keeps the first `used` bytes
 template <class T> inline T *ptr(DevBuf &b) { return static_cast<T *>(b.p); }
 

@@ -31,20 +31,40 @@ int hip_check(hipError_t e, const char *what)
 static std::atomic<uint64_t> g_moves{0};
 uint64_t buffer_moves() { return g_moves.load(std::memory_order_relaxed); }
 
+// Bytes the library's device buffers hold (process-wide) and the caller's bound on them.
+static std::atomic<uint64_t> g_used{0}, g_limit{0};
+void set_memory_limit(uint64_t bytes) { g_limit.store(bytes, std::memory_order_relaxed); }
+uint64_t memory_in_use() { return g_used.load(std::memory_order_relaxed); }
+
 int grow(DevBuf &b, size_t bytes)
 {
     if (bytes <= b.bytes) return 0;
-    g_moves.fetch_add(1, std::memory_order_relaxed);  // a recorded graph may hold the old address
     size_t want = bytes + bytes / 4 + 256;
+    const uint64_t lim = g_limit.load(std::memory_order_relaxed);
+    if (lim && memory_in_use() - b.bytes + want > lim)
+        return set_error(FMM_ERR_NOMEM, "device buffers would hold %llu bytes, over the limit of %llu",
+                         (unsigned long long)(memory_in_use() - b.bytes + want), (unsigned long long)lim);
+    g_moves.fetch_add(1, std::memory_order_relaxed);  // a recorded graph may hold the old address
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
         (void)hipGetLastError();
         return set_error(FMM_ERR_NOMEM, "hipMalloc of %zu bytes failed", want);
     }
-    if (b.p) (void)hipFree(b.p);
+    release(b);
+    g_used.fetch_add(want, std::memory_order_relaxed);
     b.p = p;
     b.bytes = want;
     return 0;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        g_used.fetch_sub(b.bytes, std::memory_order_relaxed);
+    }
+    b.p = nullptr;
+    b.bytes = 0;
 }
 
 // Grow keeping the first `used` bytes.  The caller's stream must be idle.
@@ -55,11 +75,11 @@ int grow_keep(DevBuf &b, size_t bytes, size_t used)
     if (int rc = grow(nb, bytes)) return rc;
     if (b.p && used) {
         if (hipMemcpy(nb.p, b.p, used, hipMemcpyDeviceToDevice) != hipSuccess) {
-            (void)hipFree(nb.p);
+            release(nb);
             return set_error(FMM_ERR_HIP, "device copy while growing a buffer");
         }
     }
-    if (b.p) (void)hipFree(b.p);
+    release(b);
     b = nb;
     return 0;
 }

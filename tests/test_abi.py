@@ -131,3 +131,12 @@ def test_kernel_candidates_cover_the_served_combinations():
     assert all(q.p == 5 and q.theta == 0.4 and q.precision == 1 for q in c)
     fp64 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=0)
     assert {(q.schedule, q.m2l_mfma) for q in hf.kernel_candidates(fp64)} == {(1, 0), (3, 0)}
+
+
+def test_memory_limit_entry_points_on_the_host():
+    """Setting the bound and reading the use are host-side (no GPU call); a NULL output is
+    an argument error."""
+    L = hf.lib()
+    assert L.fmm_get_memory_use(None) == hf.FMM_ERR_ARG
+    assert L.fmm_set_memory_limit(0) == 0
+    assert hf.memory_in_use() >= 0

@@ -249,6 +249,36 @@ def test_errors_reported():
     assert ei.value.code == hf.FMM_ERR_STATE
 
 
+def test_memory_limit_is_reported_as_nomem():
+    """fmm_set_memory_limit: a build that would grow the library's buffers past the bound
+    fails with FMM_ERR_NOMEM before allocating; a reused tree that fails so is left empty;
+    with the bound lifted the same calls succeed and give the same forces."""
+    rng = inputs.rng_for(132)
+    pos, m = inputs.clustered(20000, 4, rng)
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.5, p=4, n_crit=16)
+    ref, t = gpu_run(pos, m, prm)
+    held = hf.memory_in_use()
+    t.free()
+    assert hf.memory_in_use() < held
+    small = inputs.clustered(500, 2, rng)
+    t2 = hf.Tree().build(torch.tensor(small[0], device="cuda"), torch.tensor(small[1], device="cuda"), prm)
+    try:
+        hf.set_memory_limit(hf.memory_in_use() + (1 << 20))  # 1 MiB of headroom: far below a 20k build
+        with pytest.raises(hf.FMMError) as ei:
+            hf.Tree().build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+        assert ei.value.code == hf.FMM_ERR_NOMEM
+        with pytest.raises(hf.FMMError) as ei:  # the reused small tree, rebuilt larger
+            t2.build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+        assert ei.value.code == hf.FMM_ERR_NOMEM
+        assert t2.stats()["n"] == 0
+    finally:
+        hf.set_memory_limit(0)
+    t2.build(torch.tensor(pos, device="cuda"), torch.tensor(m, device="cuda"), prm)
+    got = t2.short_range(prm).cpu().numpy()
+    t2.free()
+    assert rel_err(got, ref).max() <= 1e-9
+
+
 def test_cell_count_limit_is_an_error_not_an_alias():
     """List entries address cells with 27 bits.  A uniform box with leaves of one particle
     has about 1.49 cells per particle: 96 Mi particles need about 150M cells (>= 2^27) and
