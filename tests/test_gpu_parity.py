@@ -215,6 +215,25 @@ def test_two_body_and_wrapping():
     np.testing.assert_allclose(got2, ref, rtol=1e-9)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lattice_zero_force_and_momentum(precision):
+    """Invariants on the GPU: on a perfect lattice every particle's short-range force
+    cancels (FP64 to rounding, FP32 to its force-law error); on a clustered box the total
+    momentum change sum m_i a_i stays at the FMM's error level."""
+    pos, m = inputs.lattice(16)
+    prm = hf.params(r_s=1.25 / 16, r_cut=4.5 * 1.25 / 16, theta=0.5, p=4, n_crit=8, precision=precision)
+    got, t = gpu_run(pos, m, prm)
+    t.free()
+    scale = m[0] / (1.0 / 16) ** 2  # a neighbour's Newtonian force at the lattice spacing
+    assert np.abs(got).max() < (1e-6 if precision else 1e-10) * scale, np.abs(got).max() / scale
+    pos, m = inputs.clustered(8000, 6, np.random.default_rng(8))
+    prm = hf.params(r_s=0.015, r_cut=0.0675, theta=0.4, p=6, n_crit=16, precision=precision)
+    acc, t = gpu_run(pos, m, prm)
+    t.free()
+    tot = np.abs(m[:, None] * acc).sum()
+    assert np.abs((m[:, None] * acc).sum(0)).max() < 1e-4 * tot
+
+
 def test_single_leaf_and_ragged_sizes():
     rng = inputs.rng_for(104)
     for n in (5, 63, 64, 65, 4095, 4097, 9001):
