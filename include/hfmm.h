@@ -327,7 +327,7 @@ int fmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t s
 
 /* Bound on the device memory the library's own buffers may hold, process-wide: trees and
  * their lists, forests, PM meshes, training scratch (not the caller's arrays, the FFT plans'
- * work areas or the selector model).  0, the default, is no bound.  The buffers are kept
+ * work areas, the selector model or the fixed scratch array of fmm_mlp_grad_noalloc).  0, the default, is no bound.  The buffers are kept
  * for reuse and freed only with their tree (PM meshes at exit), so the bound applies to
  * what they hold together.  A call that would grow a buffer past it fails with
  * FMM_ERR_NOMEM before allocating, as a failed device allocation does; a tree whose build
