@@ -59,6 +59,7 @@ WORKLOADS = {
                     cpu_cubes_1t=0.15),
 }
 M2L_KERNELS = {0: "library's choice (vector ALUs)", 1: "vector ALUs", 2: "matrix cores (same-level pairs)"}
+TILES = (16, 32, 64)  # P2P sink tiles (particles) the autotuner chooses from
 SCHEDULES = {0: "library's choice", 1: "two streams, P2P after the traversal", 2: "one persistent P2P + M2L kernel",
              3: "two streams, P2P per leaf level during the traversal"}
 CUBE_LEVEL = 6
@@ -120,6 +121,8 @@ def main():
                          "3 as 1 with P2P per leaf level during the traversal")
     ap.add_argument("--deterministic", type=int, default=0, choices=(0, 1),
                     help="1: every sum in a fixed order (bit-identical repeated runs; slower M2L)")
+    ap.add_argument("--p2p-chunk", type=int, default=0, choices=(0, 16, 32, 64),
+                    help="P2P sink tile in particles (0: autotuned with the leaf limit, else fixed)")
     ap.add_argument("--split", type=int, default=0, choices=(0, 1),
                     help="truncation function: 0 Gaussian (erfc) split, 1 polynomial split")
     ap.add_argument("--learned", type=int, default=None, choices=(0, 1),
@@ -171,7 +174,7 @@ def main():
     n = len(pos_np)
     prm = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
                     precision=wl["precision"], learned=int(wl["learned"]), split=args.split, m2l_mfma=args.m2l_mfma,
-                    schedule=args.schedule, deterministic=args.deterministic)
+                    schedule=args.schedule, deterministic=args.deterministic, p2p_chunk=args.p2p_chunk)
     sel = None
     if wl["learned"]:
         from paper_2006_14952_amd import learned
@@ -184,7 +187,8 @@ def main():
     mass = torch.tensor(m_np, device=dev)
     tuned = None
     if args.autotune and args.n_crit is None:
-        prm, tuned = tune(hf, wl, pos, mass, prm, offsets if batched else None)
+        prm, tuned = tune(hf, wl, pos, mass, prm, offsets if batched else None,
+                          chunks=TILES if args.p2p_chunk == 0 else (args.p2p_chunk,))
         wl["n_crit"] = prm.n_crit
     acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -247,6 +251,7 @@ def main():
             "n": n, "p": pr["p"], "theta": wl["theta"], "n_crit": wl["n_crit"], "precision": wl["precision"],
             "split": args.split, "selector": sel or "fixed p and theta", "autotuned_ms": tuned,
             "m2l_kernel": M2L_KERNELS[prm.m2l_mfma], "schedule": SCHEDULES[prm.schedule],
+            "p2p_sink_tile": prm.p2p_chunk or 32,
             "sums": "fixed order (deterministic)" if prm.deterministic else "atomics (fastest)"},
         "timing": {"statistic": "median of per-step HIP-event times", "ms_steps": ms,
                    "ms_per_step_mean_wall": wall * 1e3, "input_generation_s": t_gen},
@@ -281,7 +286,7 @@ def main():
     if wl["learned"] and args.plain_steps > 0:
         pp = hf.params(box=1.0, r_s=pr["rs"], r_cut=pr["rcut"], theta=wl["theta"], p=pr["p"], n_crit=wl["n_crit"],
                        precision=wl["precision"], learned=0, split=args.split, m2l_mfma=args.m2l_mfma,
-                       schedule=args.schedule, deterministic=args.deterministic)
+                       schedule=args.schedule, deterministic=args.deterministic, p2p_chunk=args.p2p_chunk)
         log("plain fixed-order form, %d steps" % args.plain_steps)
         pms_, pwall, pstats = timed(pp, 1, args.plain_steps)
         plain_got = acc.cpu().numpy()
@@ -352,24 +357,28 @@ def cpu_baseline(oracle, pos, m, op, frac, nthreads, what):
     return rec, (tg, res.acc)
 
 
-def tune(hf, wl, pos, mass, prm, offsets=None):
+def tune(hf, wl, pos, mass, prm, offsets=None, chunks=None):
     """The workload's launch configuration from the library's autotuner: the leaf limit
-    from wl["tune"] (and, with wl["kernels"], the schedule and the M2L kernel); returns the
-    parameter set and every candidate's ms per step."""
+    from wl["tune"] crossed with the P2P sink tiles in chunks (and, with wl["kernels"], the
+    schedule and the M2L kernel); returns the parameter set and every candidate's ms per step."""
     if wl.get("kernels"):
-        log("autotuning n_crit, schedule and M2L kernel")
-        return tune_kernels(hf, pos, mass, prm, offsets, n_crits=wl["tune"])
-    log("autotuning n_crit over %s" % (wl["tune"],))
-    best, ms = hf.autotune(pos, mass, prm, candidates=wl["tune"], offsets=offsets)
-    return hf.copy_params(prm, n_crit=best), {"n_crit %d" % k: round(v, 3) for k, v in ms.items()}
+        log("autotuning n_crit, P2P sink tile, schedule and M2L kernel")
+        return tune_kernels(hf, pos, mass, prm, offsets, n_crits=wl["tune"], chunks=chunks)
+    log("autotuning n_crit over %s and the P2P sink tile over %s" % (wl["tune"], chunks))
+    sets = [hf.copy_params(prm, n_crit=nc, p2p_chunk=ch) for nc in wl["tune"]
+            for ch in hf.sink_tiles(nc, chunks or (prm.p2p_chunk,))]
+    best, ms = hf.autotune_params(pos, mass, sets, offsets=offsets)
+    return sets[best], {"n_crit %d, tile %d" % (c.n_crit, c.p2p_chunk or 32): round(t, 3) for c, t in zip(sets, ms)}
 
 
-def tune_kernels(hf, pos, mass, prm, offsets=None, n_crits=(32, 48), reps=2):
-    """The library's autotuner over the leaf limits n_crits crossed with the schedules and
-    M2L kernels that serve prm; returns the fastest parameter set and every set's ms."""
-    cands = hf.kernel_candidates(prm, n_crits=n_crits)
+def tune_kernels(hf, pos, mass, prm, offsets=None, n_crits=(32, 48), reps=2, chunks=None):
+    """The library's autotuner over the leaf limits n_crits crossed with the P2P sink
+    tiles, schedules and M2L kernels that serve prm; returns the fastest parameter set and
+    every set's ms."""
+    cands = hf.kernel_candidates(prm, n_crits=n_crits, chunks=chunks)
     best, ms = hf.autotune_params(pos, mass, cands, reps=reps, offsets=offsets)
-    table = {"n_crit %d, %s, M2L on %s" % (c.n_crit, SCHEDULES[c.schedule], M2L_KERNELS[c.m2l_mfma]): round(t, 3)
+    table = {"n_crit %d, tile %d, %s, M2L on %s" % (c.n_crit, c.p2p_chunk or 32, SCHEDULES[c.schedule],
+                                                   M2L_KERNELS[c.m2l_mfma]): round(t, 3)
              for c, t in zip(cands, ms)}
     return cands[best], table
 

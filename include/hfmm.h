@@ -94,7 +94,12 @@ extern "C" {
  *             PM deposit in 64-bit fixed point (scaled by the total |mass|, exact integer
  *             sums, rounding below 1e-15 of the total mass per particle).  Slower (the M2L
  *             stage several times); schedule 2 and m2l_mfma 2 are refused with it
- *             (FMM_ERR_ARG).  0 or 1. */
+ *             (FMM_ERR_ARG).  0 or 1.
+ *   p2p_chunk sink tile of P2P: a sink leaf is processed in Morton-ordered chunks of this
+ *             many particles, each culled against the box of its own particles and
+ *             replicated 64 / size times across the 64 lanes of a wave; 16, 32 or 64, 0 the
+ *             library's choice (32).  A tile size for fmm_autotune_params; the results
+ *             do not depend on it beyond FP32 summation order. */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;
@@ -106,6 +111,7 @@ typedef struct fmm_params {
     int m2l_mfma;
     int schedule;
     int deterministic;
+    int p2p_chunk;
 } fmm_params;
 
 /* Counters and stage times of the last fmm_short_range_forces on a tree. Counts

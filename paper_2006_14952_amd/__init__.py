@@ -32,7 +32,7 @@ class Params(C.Structure):
     _fields_ = [("box", C.c_double), ("r_s", C.c_double), ("r_cut", C.c_double), ("theta", C.c_double),
                 ("G", C.c_double), ("p", C.c_int), ("n_crit", C.c_int), ("mac_mode", C.c_int),
                 ("precision", C.c_int), ("learned", C.c_int), ("split", C.c_int), ("pm_assign", C.c_int),
-                ("m2l_mfma", C.c_int), ("schedule", C.c_int), ("deterministic", C.c_int)]
+                ("m2l_mfma", C.c_int), ("schedule", C.c_int), ("deterministic", C.c_int), ("p2p_chunk", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -105,17 +105,18 @@ def _check(rc):
 
 
 def params(box=1.0, r_s=0.0390625, r_cut=None, theta=0.5, G=1.0, p=4, n_crit=32, mac_mode=0, precision=0,
-           learned=0, split=0, pm_assign=0, m2l_mfma=0, schedule=0, deterministic=0) -> Params:
+           learned=0, split=0, pm_assign=0, m2l_mfma=0, schedule=0, deterministic=0, p2p_chunk=0) -> Params:
     """pm_assign: PM mass assignment, 0/2 CIC, 3 TSC, 4 PCS.  m2l_mfma: FP32 M2L kernel,
     0 library's choice, 1 vector ALUs, 2 matrix cores for same-level pairs.  schedule:
     0 library's choice, 1 P2P and M2L on two streams after the traversal, 2 one persistent
     P2P + M2L kernel, 3 as 1 with P2P launched per leaf level during the traversal.
-    deterministic: 1 sums every result in a fixed order (bit-identical repeated runs)."""
+    deterministic: 1 sums every result in a fixed order (bit-identical repeated runs).
+    p2p_chunk: P2P sink tile, 16, 32 or 64 particles (0: the library's choice, 32)."""
     if r_cut is None:
         r_cut = 4.5 * r_s
     return Params(float(box), float(r_s), float(r_cut), float(theta), float(G), int(p), int(n_crit), int(mac_mode),
                   int(precision), int(learned), int(split), int(pm_assign), int(m2l_mfma), int(schedule),
-                  int(deterministic))
+                  int(deterministic), int(p2p_chunk))
 
 
 def copy_params(prm: Params, **changes) -> Params:
@@ -291,21 +292,31 @@ def autotune_params(pos, mass, cands, reps=2, offsets=None, stream=None):
     return best.value, [float(m) for m in ms]
 
 
-def kernel_candidates(prm: Params, n_crits=(32, 48)):
+def sink_tiles(n_crit, chunks):
+    """The P2P sink tiles of ``chunks`` that can differ from the default 32 at leaf limit
+    n_crit (a tile acts as 32 when no leaf exceeds min(tile, 32) particles); 0 and 32 stay."""
+    return tuple(int(c) for c in chunks if c in (0, 32) or n_crit > min(c, 32))
+
+
+def kernel_candidates(prm: Params, n_crits=(32, 48), chunks=None):
     """The tile and kernel settings the autotuner may vary for prm: each leaf limit in
     n_crits, crossed with the schedules and (FP32 orders 4..8, plain MAC) the two M2L
-    kernels; combinations the library does not serve are left out."""
+    kernels, and with the P2P sink tiles in ``chunks`` (None: prm's own); combinations
+    the library does not serve are left out, and so are sink tiles that cannot differ
+    from the default 32 at that leaf limit (no leaf exceeds min(tile, 32) particles)."""
     fp32_plain = prm.precision == 1 and not prm.learned
     det = bool(prm.deterministic)
     scheds = (1, 2, 3) if fp32_plain and 3 <= prm.p <= 8 and not det else (1, 3)
     mfmas = (1, 2) if fp32_plain and 4 <= prm.p <= 8 and not det else (prm.m2l_mfma,)
     out = []
     for nc in n_crits:
+        tiles = (prm.p2p_chunk,) if chunks is None else sink_tiles(nc, chunks)
         for sc in scheds:
             for mf in mfmas:
                 if sc == 2 and mf == 2:
                     continue
-                out.append(copy_params(prm, n_crit=int(nc), schedule=sc, m2l_mfma=mf))
+                for ch in tiles:
+                    out.append(copy_params(prm, n_crit=int(nc), schedule=sc, m2l_mfma=mf, p2p_chunk=int(ch)))
     return out
 
 

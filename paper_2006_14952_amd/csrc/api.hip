@@ -49,6 +49,8 @@ static int check_params(const fmm_params *P)
         return set_error(FMM_ERR_ARG, "deterministic mode has no persistent P2P + M2L kernel (schedule 2)");
     if (P->deterministic && P->m2l_mfma == 2)
         return set_error(FMM_ERR_ARG, "deterministic mode has no matrix-core M2L (m2l_mfma 2)");
+    if (P->p2p_chunk != 0 && P->p2p_chunk != 16 && P->p2p_chunk != 32 && P->p2p_chunk != 64)
+        return set_error(FMM_ERR_ARG, "p2p_chunk must be 0, 16, 32 or 64 (got %d)", P->p2p_chunk);
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;
@@ -232,7 +234,7 @@ static bool same_params(const fmm_params &a, const fmm_params &b)
     return a.box == b.box && a.r_s == b.r_s && a.r_cut == b.r_cut && a.theta == b.theta && a.G == b.G && a.p == b.p &&
            a.n_crit == b.n_crit && a.mac_mode == b.mac_mode && a.precision == b.precision && a.learned == b.learned &&
            a.split == b.split && a.pm_assign == b.pm_assign && a.m2l_mfma == b.m2l_mfma && a.schedule == b.schedule &&
-           a.deterministic == b.deterministic;
+           a.deterministic == b.deterministic && a.p2p_chunk == b.p2p_chunk;
 }
 
 static int build_common(const fmm_params *P, int64_t n, const double *pos, const double *mass, int nbox,

@@ -4,12 +4,13 @@
 //
 // One 64-lane wave per sink leaf.  The sources of up to 64 list entries form one stream
 // of slots (a wave prefix sum over the entry sizes), staged 256 slots at a time in LDS.
-// A sink of n_A <= 32 particles is held floor(64 / n_A) times in the wave; copy g walks
-// slots g, g + G, ... of the staged stream, and the copies are summed through LDS at
-// the end.  Larger leaves are processed in Morton-ordered chunks of 32 sink particles
-// (two copies each), each culled against the box of its own particles: measured against
-// chunks of 64 culled by the leaf's box, 2M box 8.49 -> 7.83 ms at n_crit 48, 16.7M box
-// 56.7 -> 51.6 ms and 134M box 480 -> 430 ms at n_crit 96 (chunks of 16: 1% slower).
+// A sink of n_A <= C particles (the sink tile, C = 16, 32 or 64, default 32) is held
+// floor(64 / n_A) times in the wave; copy g walks slots g, g + G, ... of the staged stream,
+// and the copies are summed through LDS at the end.  Larger leaves are processed in
+// Morton-ordered chunks of C sink particles, each culled against the box of its own
+// particles: chunks of 32 against chunks of 64 culled by the leaf's box, 2M box 8.49 ->
+// 7.83 ms at n_crit 48, 16.7M box 56.7 -> 51.6 ms and 134M box 480 -> 430 ms at n_crit 96
+// (chunks of 16: 1% slower).
 //
 // FP64 form: absolute FP64 positions, erfc/exp from the device math library.
 // FP32 form: FP32 coordinates relative to each particle's leaf centre, the exact
@@ -97,8 +98,9 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 }
 
 constexpr int kStage = 256;
-// Sink particles per pass over a leaf's list: a leaf of more is processed in Morton-ordered
-// chunks of this many, each tested against the box of its own particles.
+// Sink particles per pass over a leaf's list unless fmm_params.p2p_chunk names 16 or 64: a
+// leaf of more is processed in Morton-ordered chunks of this many, each tested against the
+// box of its own particles.
 constexpr int kSinkChunk = 32;
 
 __device__ __forceinline__ float wave_minf(float v)
@@ -152,11 +154,12 @@ __device__ __forceinline__ void p2p_leaf(const P2PArgs &a, const P2PConst &k, in
         ahi = a.bbox[2 * (size_t)A + 1];
     }
 
-    for (int ib = 0; ib < nA; ib += kSinkChunk) {
-        const int ns = min(kSinkChunk, nA - ib);
+    const int chunk = k.chunk;
+    for (int ib = 0; ib < nA; ib += chunk) {
+        const int ns = min(chunk, nA - ib);
         const int G = 64 / ns, g = lane / ns, si = lane - g * ns;
         if constexpr (!F64) {
-            if (nA > kSinkChunk) {  // one chunk of the leaf: the box of its own particles
+            if (nA > chunk) {  // one chunk of the leaf: the box of its own particles
                 const float4 me = a.rel[ca.beg + ib + (lane < ns ? lane : 0)];
                 alo = make_float4(wave_minf(me.x), wave_minf(me.y), wave_minf(me.z), 0.0f);
                 ahi = make_float4(wave_maxf(me.x), wave_maxf(me.y), wave_maxf(me.z), 0.0f);
@@ -531,6 +534,7 @@ int p2p_setup(const fmm_params *P, P2PConst &k)
     k.rc2 = (float)(P->r_cut * P->r_cut);
     k.rs = P->r_s;
     k.rc2d = P->r_cut * P->r_cut;
+    k.chunk = P->p2p_chunk ? P->p2p_chunk : kSinkChunk;
     return 0;
 }
 

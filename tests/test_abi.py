@@ -16,7 +16,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_param_struct_layout_matches_header():
-    assert C.sizeof(hf.Params) == 5 * 8 + 10 * 4
+    assert C.sizeof(hf.Params) == 5 * 8 + 12 * 4  # eleven ints, padded to 8 bytes
     assert C.sizeof(hf.Stats) == 16 * 8 + 16 * 8
 
 
@@ -131,6 +131,24 @@ def test_kernel_candidates_cover_the_served_combinations():
     assert all(q.p == 5 and q.theta == 0.4 and q.precision == 1 for q in c)
     fp64 = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=0)
     assert {(q.schedule, q.m2l_mfma) for q in hf.kernel_candidates(fp64)} == {(1, 0), (3, 0)}
+    assert {q.p2p_chunk for q in c} == {0}
+
+
+def test_sink_tile_candidates_skip_tiles_equal_to_the_default():
+    """A P2P sink tile is a candidate only where the leaf limit lets it differ from 32:
+    16 once leaves may exceed 16 particles, 64 once they may exceed 32."""
+    prm = hf.params(r_s=0.005, r_cut=0.025, theta=0.4, p=5, precision=1, schedule=1, m2l_mfma=1)
+    got = {(q.n_crit, q.p2p_chunk) for q in hf.kernel_candidates(prm, n_crits=(16, 32, 48, 96), chunks=(16, 32, 64))
+           if q.schedule == 1 and q.m2l_mfma == 1}
+    assert got == {(16, 32), (32, 16), (32, 32), (48, 16), (48, 32), (48, 64), (96, 16), (96, 32), (96, 64)}
+
+
+@pytest.mark.parametrize("chunk", [8, 24, 128, -32])
+def test_bad_sink_tile_rejected_without_gpu(chunk):
+    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32, precision=1, p2p_chunk=chunk)
+    h = C.c_void_p()
+    assert hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h)) == hf.FMM_ERR_ARG
+    assert b"p2p_chunk" in hf.lib().fmm_last_error()
 
 
 def test_memory_limit_entry_points_on_the_host():

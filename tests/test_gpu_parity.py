@@ -95,6 +95,38 @@ def test_fp32_leaves_larger_than_a_sink_chunk(ncrit):
     assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5 and e.max() <= 1e-3
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("chunk", [16, 64])
+def test_p2p_sink_tiles_match_the_oracle(chunk, precision):
+    """The P2P sink tile (fmm_params.p2p_chunk, 16 or 64 particles instead of 32) only
+    regroups a leaf's particles for the pair loop: lists and listed pairs as the oracle's,
+    forces on the form's bar, and nested chunk boxes cull monotonically (a tile of 16
+    evaluates no more pairs than one of 32, a tile of 64 no fewer)."""
+    pos, m = inputs.clustered(30000, 10, inputs.rng_for(107, chunk, precision))
+    base = hf.params(r_s=0.012, r_cut=0.054, theta=0.5, p=5, n_crit=96, precision=precision)
+    print("case: p2p_chunk", chunk, "precision", precision, flush=True)
+    if precision == 0:
+        check_fp64(pos, m, hf.copy_params(base, p2p_chunk=chunk))
+        return
+    got, t = gpu_run(pos, m, hf.copy_params(base, p2p_chunk=chunk))
+    st = t.stats()
+    t.free()
+    _, t32 = gpu_run(pos, m, base)
+    st32 = t32.stats()
+    t32.free()
+    ref = oracle.fmm(pos, m, opar(base))
+    assert st["n_m2l"] == ref.stats["n_m2l"] and st["n_p2p"] == ref.stats["n_p2p"]
+    assert ref.stats["p2p_incut"] <= st["p2p_evaluated"] <= st["p2p_pairs"] == ref.stats["p2p_pairs"]
+    if chunk < 32:
+        assert st["p2p_evaluated"] <= st32["p2p_evaluated"]
+    else:
+        assert st["p2p_evaluated"] >= st32["p2p_evaluated"]
+    e = rel_err(got, ref.acc)
+    print("p2p_chunk %d: median %.2e p99 %.2e max %.2e; evaluated %d (tile 32: %d)" % (
+        chunk, np.median(e), np.percentile(e, 99), e.max(), st["p2p_evaluated"], st32["p2p_evaluated"]))
+    assert np.median(e) <= 1e-6 and np.percentile(e, 99) <= 2e-5 and e.max() <= 1e-3
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_mac_modes_lists_identical(mode):
     """Every MAC reading, and the conventional MAC (bit 2), on the GPU and the oracle."""
