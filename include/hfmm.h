@@ -99,7 +99,8 @@ extern "C" {
  *             many particles, each culled against the box of its own particles and
  *             replicated 64 / size times across the 64 lanes of a wave; 16, 32 or 64, 0 the
  *             library's choice (32).  A tile size for fmm_autotune_params; the results
- *             do not depend on it beyond FP32 summation order. */
+ *             do not depend on it beyond FP32 summation order.  Schedule 2 has tile 32
+ *             only (FMM_ERR_ARG for 16 or 64). */
 typedef struct fmm_params {
     double box, r_s, r_cut, theta, G;
     int p, n_crit;

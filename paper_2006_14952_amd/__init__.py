@@ -316,6 +316,8 @@ def kernel_candidates(prm: Params, n_crits=(32, 48), chunks=None):
                 if sc == 2 and mf == 2:
                     continue
                 for ch in tiles:
+                    if sc == 2 and ch not in (0, 32):  # the persistent kernel has tile 32 only
+                        continue
                     out.append(copy_params(prm, n_crit=int(nc), schedule=sc, m2l_mfma=mf, p2p_chunk=int(ch)))
     return out
 

@@ -51,6 +51,8 @@ static int check_params(const fmm_params *P)
         return set_error(FMM_ERR_ARG, "deterministic mode has no matrix-core M2L (m2l_mfma 2)");
     if (P->p2p_chunk != 0 && P->p2p_chunk != 16 && P->p2p_chunk != 32 && P->p2p_chunk != 64)
         return set_error(FMM_ERR_ARG, "p2p_chunk must be 0, 16, 32 or 64 (got %d)", P->p2p_chunk);
+    if (P->schedule == 2 && P->p2p_chunk != 0 && P->p2p_chunk != 32)
+        return set_error(FMM_ERR_ARG, "the persistent P2P + M2L kernel (schedule 2) has the sink tile 32 only");
     if (P->precision == 1) {  // the FP32 force law must meet its tolerance at this r_cut / r_s
         P2PConst k;
         if (int rc = p2p_setup(P, k)) return rc;

@@ -82,7 +82,6 @@ struct P2PConst {
     float two_over_rc2;
     float rc2;
     double rs, rc2d;
-    int chunk;             // sink particles per pass over a leaf's list: 16, 32 or 64
 };
 
 // ---------------------------------------------------------------------------

@@ -131,7 +131,10 @@ template <bool F64> struct P2PShared {
 };
 
 // P2P of sink leaf `leaves[li]`.
-template <bool F64, bool POLY, int NPC>
+// CHUNK: the sink tile (16, 32 or 64 particles), a compile-time constant: a tile read at
+// run time (from P2PConst, or as an extra kernel argument) changed the register allocation
+// of the pair loop and cost 0.8-1.1% of the 134M box's P2P time.
+template <bool F64, bool POLY, int NPC, int CHUNK>
 __device__ __forceinline__ void p2p_leaf(const P2PArgs &a, const P2PConst &k, int li, P2PShared<F64> &sh)
 {
     using R = typename std::conditional<F64, double, float>::type;
@@ -154,12 +157,11 @@ __device__ __forceinline__ void p2p_leaf(const P2PArgs &a, const P2PConst &k, in
         ahi = a.bbox[2 * (size_t)A + 1];
     }
 
-    const int chunk = k.chunk;
-    for (int ib = 0; ib < nA; ib += chunk) {
-        const int ns = min(chunk, nA - ib);
+    for (int ib = 0; ib < nA; ib += CHUNK) {
+        const int ns = min(CHUNK, nA - ib);
         const int G = 64 / ns, g = lane / ns, si = lane - g * ns;
         if constexpr (!F64) {
-            if (nA > chunk) {  // one chunk of the leaf: the box of its own particles
+            if (nA > CHUNK) {  // one chunk of the leaf: the box of its own particles
                 const float4 me = a.rel[ca.beg + ib + (lane < ns ? lane : 0)];
                 alo = make_float4(wave_minf(me.x), wave_minf(me.y), wave_minf(me.z), 0.0f);
                 ahi = make_float4(wave_maxf(me.x), wave_maxf(me.y), wave_maxf(me.z), 0.0f);
@@ -393,12 +395,12 @@ __device__ __forceinline__ void p2p_leaf(const P2PArgs &a, const P2PConst &k, in
     }
 }
 
-template <bool F64, bool POLY, int NPC>
+template <bool F64, bool POLY, int NPC, int CHUNK>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(F64 ? 2 : 5))) void k_p2p(P2PArgs a, P2PConst k)
 {
     __shared__ P2PShared<F64> sh;
     if (a.err && *a.err) return;  // the traversal overflowed: it reruns, and so does P2P
-    p2p_leaf<F64, POLY, NPC>(a, k, a.first + xcd_order(blockIdx.x, gridDim.x), sh);
+    p2p_leaf<F64, POLY, NPC, CHUNK>(a, k, a.first + xcd_order(blockIdx.x, gridDim.x), sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 2 :
         if (threadIdx.x == 0) item = atomicAdd(queue, 1);
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
         if (item >= total) break;
-        if (item < nleaf) p2p_leaf<false, POLY, NPC>(a, k, item, sh.p);
+        if (item < nleaf) p2p_leaf<false, POLY, NPC, kSinkChunk>(a, k, item, sh.p);
         else m2l_pairs_block<P, float>(a.cells, pairs, npair, M, L, a.box, sp, stride, item - nleaf, sh.m);
         __syncthreads();  // the block's shared memory is reused by the next item
     }
@@ -534,9 +536,10 @@ int p2p_setup(const fmm_params *P, P2PConst &k)
     k.rc2 = (float)(P->r_cut * P->r_cut);
     k.rs = P->r_s;
     k.rc2d = P->r_cut * P->r_cut;
-    k.chunk = P->p2p_chunk ? P->p2p_chunk : kSinkChunk;
     return 0;
 }
+
+
 
 // The FP32 form's leaf bounding boxes (they depend on the tree only).
 int p2p_bbox(fmm_tree *t, const fmm_params *P, hipStream_t st)
@@ -658,6 +661,16 @@ int p2p_m2l_fused_launch(fmm_tree *t, const fmm_params *P, hipStream_t st)
     return set_error(FMM_ERR_ARG, "fused kernel compiled for orders 3..8 and force laws of degree 9 or 10");
 }
 
+template <int CHUNK>
+static void launch_p2p(const fmm_params *P, const P2PConst &k, const P2PArgs &a, int count, hipStream_t st)
+{
+    if (P->precision && P->split == 1) k_p2p<false, true, 11, CHUNK><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 10) k_p2p<false, false, 10, CHUNK><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision && k.ncoef == 11) k_p2p<false, false, 11, CHUNK><<<count, 64, 0, st>>>(a, k);
+    else if (P->precision) k_p2p<false, false, 15, CHUNK><<<count, 64, 0, st>>>(a, k);
+    else k_p2p<true, false, 11, CHUNK><<<count, 64, 0, st>>>(a, k);
+}
+
 int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int *err, hipStream_t st)
 {
     if (count <= 0) return 0;
@@ -673,12 +686,11 @@ int p2p_range(fmm_tree *t, const fmm_params *P, int first, int count, const int 
     } else {
         a.bbox = nullptr;
     }
-    if (P->precision && P->split == 1) k_p2p<false, true, 11><<<count, 64, 0, st>>>(a, k);
-    else if (P->precision && k.ncoef == 10) k_p2p<false, false, 10><<<count, 64, 0, st>>>(a, k);
-    else if (P->precision && k.ncoef == 11) k_p2p<false, false, 11><<<count, 64, 0, st>>>(a, k);
-    else if (P->precision && k.ncoef == 15) k_p2p<false, false, 15><<<count, 64, 0, st>>>(a, k);
-    else if (P->precision) return set_error(FMM_ERR_STATE, "p2p: no kernel for a force law of %d coefficients", k.ncoef);
-    else k_p2p<true, false, 11><<<count, 64, 0, st>>>(a, k);
+    if (P->precision && k.split != 1 && k.ncoef != 10 && k.ncoef != 11 && k.ncoef != 15)
+        return set_error(FMM_ERR_STATE, "p2p: no kernel for a force law of %d coefficients", k.ncoef);
+    if (P->p2p_chunk == 16) launch_p2p<16>(P, k, a, count, st);
+    else if (P->p2p_chunk == 64) launch_p2p<64>(P, k, a, count, st);
+    else launch_p2p<kSinkChunk>(P, k, a, count, st);
     return hip_check(hipGetLastError(), "p2p");
 }
 

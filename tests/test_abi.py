@@ -143,12 +143,16 @@ def test_sink_tile_candidates_skip_tiles_equal_to_the_default():
     assert got == {(16, 32), (32, 16), (32, 32), (48, 16), (48, 32), (48, 64), (96, 16), (96, 32), (96, 64)}
 
 
-@pytest.mark.parametrize("chunk", [8, 24, 128, -32])
-def test_bad_sink_tile_rejected_without_gpu(chunk):
-    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32, precision=1, p2p_chunk=chunk)
+@pytest.mark.parametrize("chunk,schedule", [(8, 0), (24, 0), (128, 0), (-32, 0), (16, 2), (64, 2)])
+def test_bad_sink_tile_rejected_without_gpu(chunk, schedule):
+    prm = hf.params(box=1.0, r_s=0.04, theta=0.5, p=4, n_crit=32, precision=1, p2p_chunk=chunk, schedule=schedule)
     h = C.c_void_p()
     assert hf.lib().fmm_build_tree(C.byref(prm), 0, None, None, None, C.byref(h)) == hf.FMM_ERR_ARG
-    assert b"p2p_chunk" in hf.lib().fmm_last_error()
+    assert b"p2p_chunk" in hf.lib().fmm_last_error() or b"sink tile" in hf.lib().fmm_last_error()
+    if schedule == 2:
+        cands = hf.kernel_candidates(hf.params(r_s=0.005, r_cut=0.025, p=5, precision=1), n_crits=(96,),
+                                     chunks=(16, 32, 64))
+        assert all(q.p2p_chunk in (0, 32) for q in cands if q.schedule == 2)
 
 
 def test_memory_limit_entry_points_on_the_host():
