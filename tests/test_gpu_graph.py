@@ -113,3 +113,41 @@ def test_learned_selector_replays():
     torch.cuda.synchronize()
     _close(out.cpu().numpy(), ref, 2e-5)
     t.free()
+
+
+def test_sink_tile_change_records_again_and_forest_tiles_agree():
+    """The P2P sink tile is part of the recorded parameters: after replays at tile 32, a call
+    with tile 16 records again and its replays equal the eager tile-16 evaluation bit for bit
+    (deterministic sums); a forest evaluated at tile 64 equals each box evaluated alone."""
+    pos, m = inputs.clustered(30000, 12, inputs.rng_for(403))
+    base = hf.params(r_s=0.012, r_cut=0.054, theta=0.45, p=5, n_crit=96, precision=1, deterministic=1, schedule=1)
+    t = hf.Tree().build(dev(pos), dev(m), base)
+    eager = {c: t.short_range(hf.copy_params(base, p2p_chunk=c)).clone() for c in (32, 16)}
+    torch.cuda.synchronize()
+    out = torch.empty((len(pos), 3), dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    for c in (32, 32, 16, 16, 16):
+        print("case: recorded evaluation, sink tile", c, flush=True)
+        out.fill_(np.nan)
+        torch.cuda.synchronize()
+        t.short_range_graph(hf.copy_params(base, p2p_chunk=c), out=out, stream=s)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager[c]), c
+    t.free()
+    e = np.abs((eager[16] - eager[32]).cpu().numpy()) / np.abs(eager[32].cpu().numpy()).max()
+    assert 0 < e.max() < 1e-5  # other FP32 summation groups, same forces
+    sizes = [4000, 900, 7000, 1]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    parts = [inputs.clustered(n_b, 4, inputs.rng_for(404, b)) if n_b > 1 else
+             (np.array([[0.25, 0.5, 0.75]]), np.array([1.0])) for b, n_b in enumerate(sizes)]
+    fpos = np.concatenate([q[0] for q in parts])
+    fm = np.concatenate([q[1] / len(q[1]) for q in parts])
+    prm = hf.params(r_s=0.02, r_cut=0.09, theta=0.45, p=5, n_crit=96, precision=1, deterministic=1, schedule=1,
+                    p2p_chunk=64)
+    print("case: forest, sink tile 64", flush=True)
+    forest = hf.short_range_batched(dev(fpos), dev(fm), [prm] * len(sizes), offs).cpu().numpy()
+    for b in range(len(sizes)):
+        alone = hf.short_range(dev(parts[b][0]), dev(parts[b][1] / len(parts[b][1])), prm)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(forest[offs[b]:offs[b + 1]], alone.cpu().numpy(), rtol=2e-5,
+                                   atol=1e-9 * np.abs(forest).max())
